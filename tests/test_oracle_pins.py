@@ -1,0 +1,239 @@
+"""Pins of the FP64 oracle against values fixed by the paper and by
+mathematics, not by the oracle itself: hand-worked examples (tests/golden),
+library special cases (scipy.ndimage, numpy.fft, numpy.median), closed forms.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from oracle import ref
+
+
+def test_worked_example_1_tile_mode(golden):
+    g = golden("worked_example_1.json")
+    X = np.array(g["frames"], float)
+    d, r = ref.pixel_terms(X, 0)
+    np.testing.assert_array_equal(d, g["delta"])
+    np.testing.assert_allclose(r, g["r"], rtol=0, atol=0)
+    q = ref.index_maps(X, mode=ref.TILES, tile=g["tile"])
+    assert q.shape == (1, 1, 1)
+    assert q[0, 0, 0] == pytest.approx(g["q"], rel=1e-15)
+    # Eq. (6) sum form: sum(D) max(D) sum(r) / (N_T^2)^2
+    assert g["sum_delta"] * g["max_delta"] * g["sum_r"] / 16.0 == pytest.approx(q[0, 0, 0], rel=1e-15)
+    M = ref.normaliser(X, g["C"])
+    assert M == g["M"]
+    assert 1 - q[0, 0, 0] / M**2 == pytest.approx(g["tlisi"], rel=1e-15)
+
+
+def test_worked_example_1_signed_reading(golden):
+    g = golden("worked_example_1.json")["signed_variant"]
+    X = np.array(g["frames"], float)
+    d, r_abs = ref.pixel_terms(X, 0, r_signed=False)
+    _, r_sig = ref.pixel_terms(X, 0, r_signed=True)
+    np.testing.assert_array_equal(d, g["delta"])
+    np.testing.assert_array_equal(r_abs, g["r_abs"])
+    np.testing.assert_array_equal(r_sig, g["r_signed"])
+    qa = ref.index_maps(X, mode=ref.TILES, tile=2)[0, 0, 0]
+    qs = ref.index_maps(X, mode=ref.TILES, tile=2, r_signed=True)[0, 0, 0]
+    assert qa == pytest.approx(g["q_abs"], rel=1e-15)
+    assert qs == pytest.approx(g["q_signed"], rel=1e-15)
+    M = ref.normaliser(X)
+    assert 1 - qs / M**2 == pytest.approx(g["tlisi_signed"], rel=1e-15)
+
+
+def test_worked_example_2_per_pixel_zscore(golden):
+    g = golden("worked_example_2.json")
+    X = np.array(g["frames"], float)
+    q = ref.index_maps(X, mode=ref.SLIDING, window=g["window"])
+    np.testing.assert_allclose(q[0], g["q"], rtol=1e-15)
+    np.testing.assert_allclose(1 - q[0] / 25.0, g["tlisi"], rtol=1e-15)
+    mu, sig = ref.spread(q[0])
+    assert mu == pytest.approx(g["mu"], rel=1e-15)
+    assert sig == pytest.approx(g["sigma"], rel=1e-14)
+    np.testing.assert_allclose((q[0] - mu) / sig, g["z"], atol=1e-7)
+    comps = ref.components(q[0], mu, sig, g["tau"])
+    assert [(c["peak_y"], c["peak_x"]) for c in comps] == [tuple(p) for p in g["selected"]]
+    out = ref.detect(X, tau=g["tau"], window=1, branches=ref.IMAGE)
+    assert len(out["cands"]) == 1 and out["cands"][0]["label"] == 1
+
+
+def test_worked_example_3_clipped_window(golden):
+    g = golden("worked_example_3.json")
+    X = np.array(g["frames"], float)
+    d, r = ref.pixel_terms(X, 0)
+    np.testing.assert_array_equal(d, g["delta"])
+    np.testing.assert_array_equal(r, g["r"])
+    q = ref.index_maps(X, mode=ref.SLIDING, window=g["window"])
+    np.testing.assert_allclose(q[0], g["q"], rtol=1e-15)
+    assert ref.normaliser(X) == g["M"]
+
+
+def test_zero_reference_uses_C(golden):
+    g = golden("zero_reference.json")
+    X = np.array(g["frames"], float)
+    d, r = ref.pixel_terms(X, 0, C=g["C"])
+    np.testing.assert_allclose(d, g["delta"], rtol=1e-12)
+    np.testing.assert_allclose(r, g["r"], rtol=1e-12)
+    q = ref.index_maps(X, window=1, C=g["C"])
+    np.testing.assert_allclose(q[0], g["q"], rtol=1e-12)
+
+
+def test_ccl_example(golden):
+    g = golden("ccl_example.json")
+    z = np.array(g["z"], float)
+    comps = ref.components(z, 0.0, 1.0, g["tau"])
+    assert len(comps) == len(g["components"])
+    for c, e in zip(comps, g["components"]):
+        for k, v in e.items():
+            assert c[k] == pytest.approx(v, rel=1e-14), (k, c, e)
+
+
+def test_spectrum_closed_form(golden):
+    g = golden("spectrum_example.json")
+    n = g["nprime"]
+    s = np.arange(n)
+    v = g["offset"] + sum(a * np.cos(2 * np.pi * k * s / n) for k, a in g["terms"])
+    cube = v.reshape(n, 1, 1)
+    assert ref.eta(cube, 0)[0, 0] == pytest.approx(g["eta_max"], rel=1e-12)
+    assert ref.eta(cube, 2)[0, 0] == pytest.approx(g["eta_hsum2"], rel=1e-12)
+    # constant series -> eta = 0
+    assert ref.eta(np.full((n, 1, 1), 7.0), 0)[0, 0] == pytest.approx(0.0, abs=1e-12)
+
+
+def test_spread_examples(golden):
+    g = golden("spread_example.json")
+    for key in ("odd", "even"):
+        med, sig = ref.spread(np.array(g[key]["values"], float), ref.MEDIAN_MAD)
+        assert med == g[key]["median"]
+        assert sig == pytest.approx(g["scale"] * g[key]["mad"], rel=1e-15)
+    # the scale is 1 / Phi^-1(3/4)
+    from scipy.stats import norm
+
+    assert g["scale"] == pytest.approx(1.0 / norm.ppf(0.75), rel=1e-12)
+
+
+# ---- library special cases ------------------------------------------------
+
+def _rand_stack(rng, n, H, W, zeros=False):
+    X = rng.normal(size=(n, H, W))
+    X[:, rng.integers(0, H, 3), rng.integers(0, W, 3)] += 20.0
+    if zeros:
+        X[rng.random((n, H, W)) < 0.05] = 0.0
+    return X
+
+
+@pytest.mark.parametrize("shape,w", [((5, 13, 17), 3), ((4, 9, 20), 7), ((3, 8, 5), 9), ((6, 31, 11), 5)])
+def test_sliding_windows_match_scipy(shape, w):
+    """Window sums / max over the clipped window equal scipy's zero-padded
+    box filters (Delta, r >= 0 so padding with 0 is neutral), and the count
+    equals the box filter of ones."""
+    rng = np.random.default_rng(sum(shape) + w)
+    X = _rand_stack(rng, *shape, zeros=True)
+    q = ref.index_maps(X, window=w)
+    for s in range(shape[0] - 2):
+        d, r = ref.pixel_terms(X, s)
+        ones = np.ones_like(d)
+        cnt = ndimage.correlate(ones, np.ones((w, w)), mode="constant", cval=0.0)
+        sd = ndimage.correlate(d, np.ones((w, w)), mode="constant", cval=0.0)
+        sr = ndimage.correlate(r, np.ones((w, w)), mode="constant", cval=0.0)
+        md = ndimage.maximum_filter(d, size=w, mode="constant", cval=0.0)
+        np.testing.assert_allclose(q[s], (sd / cnt) * md * (sr / cnt), rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("shape,t", [((4, 12, 10), 4), ((3, 9, 13), 4), ((5, 7, 7), 1), ((3, 33, 70), 32)])
+def test_tile_mode_matches_block_reduction(shape, t):
+    rng = np.random.default_rng(shape[1] * 7 + t)
+    X = _rand_stack(rng, *shape)
+    q = ref.index_maps(X, mode=ref.TILES, tile=t)
+    H, W = shape[1:]
+    Ty, Tx = -(-H // t), -(-W // t)
+    assert q.shape == (shape[0] - 2, Ty, Tx)
+    for s in range(shape[0] - 2):
+        d, r = ref.pixel_terms(X, s)
+        for ty in range(Ty):
+            for tx in range(Tx):
+                bd = d[ty * t:(ty + 1) * t, tx * t:(tx + 1) * t]
+                br = r[ty * t:(ty + 1) * t, tx * t:(tx + 1) * t]
+                assert q[s, ty, tx] == pytest.approx(bd.mean() * bd.max() * br.mean(), rel=1e-12)
+
+
+def test_eta_matches_numpy_rfft():
+    rng = np.random.default_rng(3)
+    for npr in (4, 5, 14, 30, 31, 62):
+        cube = rng.normal(size=(npr, 3, 4)) + 5.0
+        e = ref.eta(cube, 0)
+        v = cube - cube.mean(0, keepdims=True)
+        A = np.abs(np.fft.rfft(v, axis=0))[1:npr // 2 + 1]
+        np.testing.assert_allclose(e, A.max(0), rtol=1e-10)
+        # harmonic sum of 3 terms from the same magnitudes
+        K = npr // 2
+        hs = np.stack([sum(A[j * k - 1] for j in range(1, 4) if j * k <= K) for k in range(1, K + 1)])
+        np.testing.assert_allclose(ref.eta(cube, 3), hs.max(0), rtol=1e-10)
+
+
+def test_spread_matches_numpy():
+    rng = np.random.default_rng(4)
+    for n in (1, 2, 7, 100, 1001):
+        v = rng.gamma(2.0, size=n)
+        mu, sig = ref.spread(v, ref.MEAN_STD)
+        assert mu == pytest.approx(v.mean(), rel=1e-13)
+        assert sig == pytest.approx(v.std(ddof=0), rel=1e-12, abs=1e-15)
+        med, s2 = ref.spread(v, ref.MEDIAN_MAD)
+        assert med == np.median(v)
+        assert s2 == pytest.approx(1.482602218505602 * np.median(np.abs(v - np.median(v))), rel=1e-15)
+
+
+def test_components_match_scipy_label():
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        H, W = rng.integers(1, 40, 2)
+        z = rng.normal(size=(H, W)) * 2
+        tau = 1.0
+        comps, mask = ref.components(z, 0.0, 1.0, tau, with_mask=True)
+        np.testing.assert_array_equal(mask, z > tau)
+        lab, nl = ndimage.label(z > tau, structure=np.ones((3, 3)))
+        assert nl == len(comps)
+        seen = {}
+        for c in comps:
+            l = lab.flat[c["label"]]
+            assert l > 0 and l not in seen
+            seen[l] = c
+            ys, xs = np.nonzero(lab == l)
+            lin = ys * W + xs
+            assert c["label"] == lin.min()
+            assert c["n_pix"] == len(ys)
+            w = z[ys, xs]
+            best = np.lexsort((lin, -w))[0]
+            assert (c["peak_y"], c["peak_x"]) == (ys[best], xs[best])
+            assert c["cy"] == pytest.approx((w * ys).sum() / w.sum(), rel=1e-12)
+            assert c["cx"] == pytest.approx((w * xs).sum() / w.sum(), rel=1e-12, abs=1e-12)
+            assert (c["y0"], c["x0"], c["y1"], c["x1"]) == (ys.min(), xs.min(), ys.max(), xs.max())
+        # canonical order: increasing label
+        assert [c["label"] for c in comps] == sorted(c["label"] for c in comps)
+
+
+# ---- closed forms ------------------------------------------------------------
+
+@pytest.mark.parametrize("tau,q", [(3.0, 1.3498980316301e-3), (4.0, 3.1671241833120e-5)])
+def test_threshold_stage_gaussian_tail(tau, q):
+    """Fed an N(0,1) map, the N-sigma selection keeps a fraction within a
+    binomial interval of the Gaussian tail Q(tau)."""
+    rng = np.random.default_rng(int(tau * 10))
+    N = 2_000_000
+    v = rng.normal(size=(1000, N // 1000))
+    mu, sig = ref.spread(v)
+    _, mask = ref.components(v, mu, sig, tau, with_mask=True)
+    frac = mask.mean()
+    assert q == pytest.approx(0.5 * math.erfc(tau / math.sqrt(2)), rel=1e-9)
+    tol = 5 * math.sqrt(q * (1 - q) / N) + 2e-6 * q * 0
+    assert abs(frac - q) < tol, (frac, q, tol)
+
+
+def test_mad_sigma_consistent_on_gaussian():
+    rng = np.random.default_rng(11)
+    N = 400_000
+    v = rng.normal(size=N)
+    _, sig = ref.spread(v, ref.MEDIAN_MAD)
+    assert abs(sig - 1.0) < 5 * 1.17 / math.sqrt(N)
