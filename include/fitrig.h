@@ -1,0 +1,170 @@
+/*
+ * fitrig.h - C ABI of the MI355X (gfx950) FITrig trigger library.
+ *
+ * The library computes, for a stack of fast-imaging snapshots, the
+ * transient-oriented index tLISI of Li, Adamek & Armour ("FITrig",
+ * arXiv 2509.21754), per pixel (sliding window) or per tile, then the
+ * per-triple spread, the N-sigma selection, 8-connected candidate
+ * components and the image-frequency branch:
+ *
+ *   triple s (0-based) = snapshots s, s+1, s+2; reference = snapshot s+1;
+ *   D(s) = |x(s+1) - x(s)|, Delta = |D(s) - D(s+1)|          Sec. 2.2.4, Eq. (3)
+ *   x_hat = x(s+1), or C where x(s+1) == 0                  Eq. (5)
+ *   r = min(Delta / |x_hat|, 1)                             Eq. (4)
+ *   tLISI = 1 - mean(Delta) max(Delta) mean(r) / M^2,
+ *   M = max(max over the stack, C)                          Eq. (2), Eq. (6)
+ *   z = (mu - tLISI) / sigma per triple; select z > tau     Sec. 2.4.1, Eqs. (8)-(9)
+ *   eta = h(|F_s[q(s) - mean q]|) per tile, z on eta        Sec. 2.4.2, Eqs. (10)-(12)
+ *
+ * The index map holds q = mean(Delta) max(Delta) mean(r) (tLISI = 1 - q/M^2);
+ * the z-score of Eq. (8) is computed on q, which is the same number.
+ *
+ * All device pointers are HIP device memory of the device named in the
+ * config. Every call returns a fitrig_status (0 = OK, < 0 = error).
+ * Threading: a context is not thread-safe; use one per host thread.
+ * Determinism: results depend only on the inputs and the config, and are
+ * bitwise reproducible on the same GPU and build.
+ */
+#ifndef FITRIG_H
+#define FITRIG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FITRIG_ABI_VERSION 1
+
+typedef int32_t fitrig_status;
+#define FITRIG_OK 0
+#define FITRIG_E_INVAL (-1)   /* bad argument: see each call */
+#define FITRIG_E_NOMEM (-2)   /* a device or host allocation failed */
+#define FITRIG_E_HIP (-3)     /* a HIP call failed; fitrig_last_hip_error gives the code */
+#define FITRIG_E_TRUNC (-4)   /* more results than the given or internal capacity */
+#define FITRIG_E_BUSY (-5)    /* serving: admission refused on a non-blocking submit */
+#define FITRIG_E_NOTREADY (-6)/* serving: result not ready on a non-blocking poll */
+
+typedef enum { FITRIG_F32 = 0, FITRIG_F16 = 1, FITRIG_BF16 = 2 } fitrig_dtype;
+
+/* index mode */
+#define FITRIG_SLIDING 0      /* odd window x window centred on every pixel, clipped at the edge */
+#define FITRIG_TILES 1        /* non-overlapping tile x tile tiles, row-major (Sec. 2.2.1, Alg. 1) */
+/* branches (bitmask) */
+#define FITRIG_IMAGE 1        /* image-domain selection, Sec. 2.4.1 */
+#define FITRIG_FREQ 2         /* image-frequency selection, Sec. 2.4.2 (needs n_snap - 2 >= 4) */
+/* spread estimator */
+#define FITRIG_MEAN_STD 0     /* mean and population std (Eq. (8)) */
+#define FITRIG_MEDIAN_MAD 1   /* median and 1.482602218505602 * MAD */
+/* what the optional index map holds */
+#define FITRIG_MAP_QTILDE 0   /* q = mean(Delta) max(Delta) mean(r) */
+#define FITRIG_MAP_TLISI 1    /* 1 - q / M^2 (one extra pass over the map) */
+/* per-triple flags */
+#define FITRIG_FLAG_SIGMA_ZERO 1u  /* zero or non-finite spread: no selection */
+#define FITRIG_FLAG_TRUNC 2u       /* internal selection capacity exceeded */
+
+typedef struct {
+  int32_t abi_version;  /* must be FITRIG_ABI_VERSION */
+  int32_t mode;         /* FITRIG_SLIDING (default) or FITRIG_TILES */
+  int32_t window;       /* sliding window, odd, 1..17 (default 7) */
+  int32_t tile;         /* tile size for FITRIG_TILES and for the frequency branch (default 32) */
+  int32_t branches;     /* FITRIG_IMAGE | FITRIG_FREQ (default both) */
+  int32_t sigma_est;    /* FITRIG_MEAN_STD (default) or FITRIG_MEDIAN_MAD */
+  int32_t harm;         /* 0: eta = max magnitude (default); h >= 2: harmonic sum of h terms */
+  int32_t r_signed;     /* 0: divide by |x_hat| (default); 1: by the signed x_hat (literal Eq. (4)) */
+  int32_t map_kind;     /* FITRIG_MAP_QTILDE (default) or FITRIG_MAP_TLISI */
+  int32_t device;       /* HIP device ordinal (default 0) */
+  double C;             /* the constant of Eqs. (2), (5); > 0 (default 1e-6) */
+  int64_t max_pixels;   /* capacity hint H*W used to size scratch at create (0 = grow on demand) */
+  int32_t max_snap;     /* capacity hint n_snap (0 = grow on demand) */
+  int32_t reserved;
+  int64_t max_segments; /* selection capacity in 64-cell row segments (0 = automatic) */
+} fitrig_config;
+
+/* One candidate: an 8-connected component of selected cells. */
+typedef struct {
+  int32_t branch;       /* FITRIG_IMAGE or FITRIG_FREQ */
+  int32_t triple;       /* first snapshot s of the triple; -1 for FITRIG_FREQ */
+  int64_t label;        /* lowest row-major cell index y * width + x of the component */
+  int32_t n_pix;        /* cells in the component (pixels, or tiles for tile mode / FREQ) */
+  int32_t peak_y, peak_x; /* cell of the largest z (ties: lowest index) */
+  float peak_z;         /* z at the peak */
+  float peak_q;         /* q (or eta) at the peak */
+  int32_t pad0;
+  double cy, cx;        /* z-weighted centroid in cell units */
+  int32_t y0, x0, y1, x1; /* inclusive bounding box */
+} fitrig_candidate;
+
+/* Optional per-call statistics (host memory owned by the caller). */
+typedef struct {
+  double M;             /* max(max over the stack, C) */
+  int32_t n_triples;    /* out: n_snap - 2 */
+  int32_t pad0;
+  double* mu;           /* in: array of >= n_snap - 2, out: per-triple location of q (nullable) */
+  double* sigma;        /* in: array of >= n_snap - 2, out: per-triple spread of q (nullable) */
+  uint32_t* flags;      /* in: array of >= n_snap - 2, out: FITRIG_FLAG_* (nullable) */
+  double eta_mu;        /* frequency branch: location of eta (0 if not run) */
+  double eta_sigma;     /* frequency branch: spread of eta (0 if not run) */
+  int64_t n_image_cand; /* candidates from the image branch */
+  int64_t n_freq_cand;  /* candidates from the frequency branch */
+} fitrig_stats;
+
+typedef struct fitrig_ctx fitrig_ctx;
+
+/* Fills cfg with the defaults listed above. */
+void fitrig_config_default(fitrig_config* cfg);
+
+/*
+ * Creates a context on cfg->device: a HIP stream and a scratch arena sized
+ * from the capacity hints. The context owns both.
+ * Errors: E_INVAL (null pointer, ABI mismatch, bad mode/window/tile/branches/
+ * sigma_est/harm, C <= 0, bad device), E_NOMEM, E_HIP.
+ */
+fitrig_status fitrig_create(const fitrig_config* cfg, fitrig_ctx** out);
+
+/*
+ * Runs the whole path on one stack.
+ *   stack      device, [n_snap][H][W] row-major, dtype as given, read only
+ *   n_snap     >= 3 (the frequency branch runs only when n_snap - 2 >= 4)
+ *   H, W       >= 1, H * W < 2^32
+ *   sigma      the threshold tau of Eqs. (9), (12); finite and > 0
+ *   cand       host, cand_cap records (nullable when cand_cap == 0)
+ *   n_cand     host, out: total number of candidates (always written)
+ *   index_map  device, nullable: [n_snap-2][H][W] floats (sliding) or
+ *              [n_snap-2][ceil(H/tile)][ceil(W/tile)] (tiles)
+ *   eta_map    device, nullable: [ceil(H/tile)][ceil(W/tile)] floats
+ *   stats      host, nullable
+ *   hip_stream hipStream_t to run on; NULL = the context's stream
+ * Candidates come in canonical order: image branch by (triple, label), then
+ * the frequency branch by label. The call returns when every output is
+ * written. Scratch grows (hipMalloc) when a stack exceeds the capacity
+ * hints; with adequate hints a call allocates nothing.
+ * Errors: E_INVAL (argument outside the ranges above, unknown dtype),
+ * E_TRUNC (more candidates than cand_cap: the first cand_cap are written
+ * and *n_cand holds the total; or the internal selection capacity was
+ * exceeded, flagged FITRIG_FLAG_TRUNC), E_NOMEM, E_HIP.
+ */
+fitrig_status fitrig_detect(fitrig_ctx* ctx, const void* stack, fitrig_dtype dtype,
+                            int32_t n_snap, int32_t H, int32_t W, double sigma,
+                            fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand,
+                            float* index_map, float* eta_map, fitrig_stats* stats,
+                            void* hip_stream);
+
+/* Releases the context and its device memory. Errors: E_INVAL (null). */
+fitrig_status fitrig_destroy(fitrig_ctx* ctx);
+
+/* Text of a status code (static storage). */
+const char* fitrig_status_string(fitrig_status s);
+
+/* The last HIP error code seen by the context (0 = none). */
+int32_t fitrig_last_hip_error(const fitrig_ctx* ctx);
+
+/* Library ABI version (FITRIG_ABI_VERSION of the build). */
+int32_t fitrig_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FITRIG_H */

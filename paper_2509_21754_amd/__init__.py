@@ -1,0 +1,8 @@
+"""MI355X (gfx950) FITrig trigger: HIP kernels behind a C ABI (include/fitrig.h).
+
+The Python side only marshals arguments; see ``fitrig.py``.
+"""
+from .fitrig import (  # noqa: F401
+    Context, FitrigError, fitrig_abi_version, fitrig_config_default, fitrig_create, fitrig_destroy,
+    fitrig_detect, fitrig_last_hip_error, fitrig_status_string, load,
+)

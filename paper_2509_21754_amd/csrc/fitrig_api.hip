@@ -1,0 +1,759 @@
+// FITrig host runtime and C ABI: context, scratch arena, launch sequence.
+//
+// One fitrig_detect call enqueues, on one stream:
+//   1. the streaming index kernel (sliding mode) or the tile kernel (tile
+//      mode / frequency-only), which read the stack once;
+//   2. per-triple spread: FP64 moments of the kernel partials (mean / std),
+//      or exact radix selection on the q map (median / MAD);
+//   3. image-branch selection: flags from the 64-cell segment maxima,
+//      deterministic compaction, exact recompute of the flagged segments,
+//      union-find 8-connected components, candidate records;
+//   4. frequency branch: tile cube, eta per tile, spread of eta, selection
+//      and components on the tile grid;
+//   5. small device-to-host copies of counts, candidates and statistics.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "fitrig.h"
+#include "fitrig_internal.h"
+#include "fitrig_kernels.hip"
+
+namespace {
+
+using namespace fitrig;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+enum {
+  CNT_NSEL = 0,    // segments selected in the current run
+  CNT_NCOMP = 1,   // components of the current run
+  CNT_OUTBASE = 3, // candidates written so far
+  CNT_TRUNC = 5,   // internal capacity exceeded
+  CNT_IMG = 6,     // image-branch candidates
+  CNT_FREQ = 7,    // frequency-branch candidates
+  CNT_N = 8
+};
+
+}  // namespace
+
+struct fitrig_ctx {
+  fitrig_config cfg;
+  hipStream_t stream = nullptr;
+  int32_t last_hip = 0;
+  DevBuf stat_part, seg_max, seg_max2, tile_part, wg_max, tile_wgmax, cube, cube_f, eta_d, eta_f, mu, sigma, flags, eta_st, M, qscratch;
+  DevBuf hist, rs_state, rs_med, rs_dev, chunk_cnt, counters;
+  DevBuf seg_entry, seg_mask, cell_q, parent, comp_of, c_root, c_npix, c_key, c_w, c_box, c_out;
+  int64_t seg_cap = 0, comp_cap = 0;
+  void* h_stage = nullptr;
+  size_t h_stage_cap = 0;
+};
+
+namespace {
+
+#define HIP_TRY(ctx, expr)                      \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) {                     \
+      (ctx)->last_hip = (int32_t)e_;            \
+      return (e_ == hipErrorOutOfMemory) ? FITRIG_E_NOMEM : FITRIG_E_HIP; \
+    }                                           \
+  } while (0)
+
+#define LAUNCH_CHECK(ctx) HIP_TRY(ctx, hipGetLastError())
+
+fitrig_status ensure(fitrig_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 64;
+  if (b.cap >= bytes) return FITRIG_OK;
+  if (b.p) {
+    // the buffer may still be in use by work queued on any stream
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  bytes = (bytes + 255) & ~(size_t)255;
+  HIP_TRY(ctx, hipMalloc(&b.p, bytes));
+  b.cap = bytes;
+  return FITRIG_OK;
+}
+
+fitrig_status ensure_host(fitrig_ctx* ctx, size_t bytes) {
+  if (ctx->h_stage_cap >= bytes) return FITRIG_OK;
+  if (ctx->h_stage) {
+    HIP_TRY(ctx, hipHostFree(ctx->h_stage));
+    ctx->h_stage = nullptr;
+    ctx->h_stage_cap = 0;
+  }
+  bytes = std::max<size_t>(bytes, 1 << 16);
+  HIP_TRY(ctx, hipHostMalloc(&ctx->h_stage, bytes, hipHostMallocDefault));
+  ctx->h_stage_cap = bytes;
+  return FITRIG_OK;
+}
+
+template <typename T>
+void launch_stream(int H, dim3 grid, hipStream_t st, const StreamArgs& A) {
+  switch (H) {
+#define CASE(h) \
+  case h: hipLaunchKernelGGL((k_stream<T, h>), grid, dim3(kLanes), 0, st, A); break;
+    CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: break;
+  }
+}
+
+struct RecomputeArgs {
+  const void* base;
+  const void* c0;
+  const void* c1;
+  int ncarry;
+  int64_t plane;
+  int H, W;
+  float Cf;
+  int r_signed;
+};
+
+template <typename T>
+void launch_recompute(int halo, dim3 grid, hipStream_t st, const RecomputeArgs& R, const SegLayout& L,
+                      const int64_t* seg_entry, const int64_t* nsel, int64_t cap, const double* mu,
+                      const double* sigma, double tau, uint64_t* mask, float* cq) {
+  switch (halo) {
+#define CASE(h)                                                                                          \
+  case h:                                                                                                \
+    hipLaunchKernelGGL((k_recompute<T, h>), grid, dim3(64), 0, st, R.base, R.c0, R.c1, R.ncarry, R.plane, \
+                       R.H, R.W, R.Cf, R.r_signed, L, seg_entry, nsel, cap, mu, sigma, tau, mask, cq);  \
+    break;
+    CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: break;
+  }
+}
+
+int grid_for(int64_t n, int per = 256, int maxg = 8192) {
+  int64_t g = (n + per - 1) / per;
+  if (g < 1) g = 1;
+  if (g > maxg) g = maxg;
+  return (int)g;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+// counters[CNT_TRUNC] |= overflow of this run; per-branch count; output base.
+__global__ void k_run_done(int64_t* c, int64_t seg_cap, int64_t comp_cap, int branch) {
+  if (threadIdx.x || blockIdx.x) return;
+  if (c[CNT_NSEL] > seg_cap || c[CNT_NCOMP] > comp_cap) c[CNT_TRUNC] |= 1;
+  const int64_t nc = c[CNT_NCOMP] < comp_cap ? c[CNT_NCOMP] : comp_cap;
+  c[branch == FITRIG_IMAGE ? CNT_IMG : CNT_FREQ] += nc;
+  c[CNT_OUTBASE] += nc;
+}
+template <typename T>
+__global__ void k_stack_max(const T* p, int64_t n, float* wg_max) {
+  __shared__ float sh[256];
+  float m = -INFINITY;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, to_f<T>(p[i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) wg_max[blockIdx.x] = sh[0];
+}
+
+struct Call {
+  const void* stack;
+  fitrig_dtype dtype;
+  int n, H, W;
+  double tau;
+  float* index_map;
+  float* eta_map;
+  hipStream_t st;
+};
+
+// Spread by exact median / MAD of a float array [nsets][per_set].
+fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, int nsets, int64_t per_set,
+                            double* mu, double* sigma, uint32_t* flags) {
+  fitrig_status rc;
+  if ((rc = ensure(ctx, ctx->hist, (size_t)nsets * kHistBins * 4)) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->rs_state, (size_t)nsets * sizeof(RsState))) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->rs_med, (size_t)nsets * 2 * 8)) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->rs_dev, (size_t)nsets * 2 * 8)) != FITRIG_OK) return rc;
+  uint32_t* hist = (uint32_t*)ctx->hist.p;
+  RsState* rs = (RsState*)ctx->rs_state.p;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((int64_t)nsets * kHistBins)), dim3(256), 0, st, hist,
+                     (int64_t)nsets * kHistBins, 0u);
+  const int shifts[3] = {21, 10, 0};
+  const int nbits[3] = {11, 11, 10};
+  const int gx = grid_for(per_set, 256 * 16, 1024);
+  for (int mode = 0; mode < 2; ++mode) {
+    for (int which = 0; which < 2; ++which) {
+      hipLaunchKernelGGL(k_rs_init, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, per_set, which);
+      for (int p = 0; p < 3; ++p) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, mode, (const double*)mu, rs,
+                           shifts[p], nbits[p], hist);
+        hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(64), 0, st, rs, hist, shifts[p], nbits[p]);
+      }
+      hipLaunchKernelGGL(k_rs_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, mode, which,
+                         (double*)(mode ? ctx->rs_dev.p : ctx->rs_med.p));
+    }
+    hipLaunchKernelGGL(k_rs_finish, dim3((nsets + 63) / 64), dim3(64), 0, st, (const double*)ctx->rs_med.p,
+                       (const double*)ctx->rs_dev.p, nsets, mu, sigma, flags, mode);
+  }
+  LAUNCH_CHECK(ctx);
+  return FITRIG_OK;
+}
+
+// Deterministic compaction: count, scan, write.
+template <class F, class E>
+fitrig_status compact(fitrig_ctx* ctx, hipStream_t st, F f, E e, int64_t ne_static, const int64_t* ne_dyn,
+                      int64_t cap, int mult, int64_t* total) {
+  const int64_t ne_max = ne_dyn ? cap * mult : ne_static;
+  const int64_t nch = std::max<int64_t>(1, (ne_max + kChunk - 1) / kChunk);
+  fitrig_status rc;
+  if ((rc = ensure(ctx, ctx->chunk_cnt, (size_t)nch * 4)) != FITRIG_OK) return rc;
+  uint32_t* cnt = (uint32_t*)ctx->chunk_cnt.p;
+  hipLaunchKernelGGL((k_compact_count<F>), dim3((unsigned)nch), dim3(256), 0, st, f, ne_static, ne_dyn, cap, mult,
+                     cnt);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, cnt, nch, total);
+  hipLaunchKernelGGL((k_compact_write<F, E>), dim3((unsigned)nch), dim3(256), 0, st, f, e, ne_static, ne_dyn, cap,
+                     mult, (const uint32_t*)cnt);
+  LAUNCH_CHECK(ctx);
+  return FITRIG_OK;
+}
+
+// One selection run over a segment layout: flags -> segments -> cells ->
+// components -> candidate records appended at counters[CNT_OUTBASE].
+fitrig_status select_run(fitrig_ctx* ctx, const Call& c, const SegLayout& L, float* seg_max, const double* mu,
+                         const double* sigma, const uint32_t* flags, int branch, const float* direct_vals,
+                         int halo) {
+  hipStream_t st = c.st;
+  int64_t* cnt = (int64_t*)ctx->counters.p;
+  const int64_t NE = (int64_t)L.nsets * L.Ho * L.nseg_row;
+  const int64_t cap = ctx->seg_cap;
+  int64_t* seg_entry = (int64_t*)ctx->seg_entry.p;
+  uint64_t* mask = (uint64_t*)ctx->seg_mask.p;
+  float* cq = (float*)ctx->cell_q.p;
+  int32_t* parent = (int32_t*)ctx->parent.p;
+  fitrig_status rc;
+
+  SegFlag fl{seg_max, mu, sigma, flags, c.tau, L};
+  SegEmit em{(int32_t*)seg_max, seg_entry, cap};
+  if ((rc = compact(ctx, st, fl, em, NE, nullptr, 0, 1, cnt + CNT_NSEL)) != FITRIG_OK) return rc;
+
+  const int gsel = (int)std::min<int64_t>(cap, 4096);
+  if (direct_vals) {
+    hipLaunchKernelGGL(k_fill_direct, dim3(gsel), dim3(64), 0, st, direct_vals, L, (const int64_t*)seg_entry,
+                       (const int64_t*)(cnt + CNT_NSEL), cap, mu, sigma, c.tau, mask, cq);
+  } else {
+    RecomputeArgs R{c.stack, nullptr, nullptr, 0, (int64_t)c.H * c.W, c.H, c.W, (float)ctx->cfg.C,
+                    ctx->cfg.r_signed};
+    switch (c.dtype) {
+      case FITRIG_F32:
+        launch_recompute<float>(halo, dim3(gsel), st, R, L, seg_entry, cnt + CNT_NSEL, cap, mu, sigma, c.tau, mask,
+                                cq);
+        break;
+      case FITRIG_F16:
+        launch_recompute<__half>(halo, dim3(gsel), st, R, L, seg_entry, cnt + CNT_NSEL, cap, mu, sigma, c.tau, mask,
+                                 cq);
+        break;
+      default:
+        launch_recompute<bf16_t>(halo, dim3(gsel), st, R, L, seg_entry, cnt + CNT_NSEL, cap, mu, sigma, c.tau, mask,
+                                 cq);
+        break;
+    }
+  }
+  LAUNCH_CHECK(ctx);
+  const int gcell = grid_for(cap * 64, 256, 4096);
+  hipLaunchKernelGGL(k_uf_init, dim3(gcell), dim3(256), 0, st, (const uint64_t*)mask, (const int64_t*)(cnt + CNT_NSEL),
+                     cap, parent);
+  hipLaunchKernelGGL(k_uf_union, dim3(gcell), dim3(256), 0, st, (const int32_t*)seg_max, (const uint64_t*)mask,
+                     (const int64_t*)seg_entry, L, (const int64_t*)(cnt + CNT_NSEL), cap, parent);
+  hipLaunchKernelGGL(k_uf_flatten, dim3(gcell), dim3(256), 0, st, (const int64_t*)(cnt + CNT_NSEL), cap, parent);
+  LAUNCH_CHECK(ctx);
+
+  RootFlag rf{(const uint64_t*)mask, (const int32_t*)parent};
+  RootEmit re{(int32_t*)ctx->comp_of.p, (int32_t*)ctx->c_root.p, ctx->comp_cap};
+  if ((rc = compact(ctx, st, rf, re, 0, cnt + CNT_NSEL, cap, 64, cnt + CNT_NCOMP)) != FITRIG_OK) return rc;
+
+  const int64_t ccap = ctx->comp_cap;
+  const int gcomp = grid_for(ccap, 256, 4096);
+  hipLaunchKernelGGL(k_comp_init, dim3(gcomp), dim3(256), 0, st, (const int64_t*)(cnt + CNT_NCOMP), ccap,
+                     (int32_t*)ctx->c_npix.p, (unsigned long long*)ctx->c_key.p, (unsigned long long*)ctx->c_w.p,
+                     (int32_t*)ctx->c_box.p);
+  hipLaunchKernelGGL(k_comp_accum, dim3(gcell), dim3(256), 0, st, (const uint64_t*)mask, (const int64_t*)seg_entry,
+                     (const float*)cq, L, (const int64_t*)(cnt + CNT_NSEL), cap, (const int32_t*)parent,
+                     (const int32_t*)ctx->comp_of.p, mu, sigma, (int32_t*)ctx->c_npix.p,
+                     (unsigned long long*)ctx->c_key.p, (unsigned long long*)ctx->c_w.p, (int32_t*)ctx->c_box.p);
+  hipLaunchKernelGGL(k_comp_finalize, dim3(gcomp), dim3(256), 0, st, (const int64_t*)(cnt + CNT_NCOMP), ccap,
+                     (const int32_t*)ctx->c_root.p, (const int64_t*)seg_entry, L, mu, sigma, branch,
+                     (const int32_t*)ctx->c_npix.p, (const unsigned long long*)ctx->c_key.p,
+                     (const unsigned long long*)ctx->c_w.p, (const int32_t*)ctx->c_box.p, cnt + CNT_OUTBASE,
+                     (fitrig_candidate*)ctx->c_out.p, 2 * ccap);
+  hipLaunchKernelGGL(k_run_done, dim3(1), dim3(64), 0, st, cnt, cap, ccap, branch);
+  LAUNCH_CHECK(ctx);
+  return FITRIG_OK;
+}
+
+fitrig_status ensure_selection(fitrig_ctx* ctx, int64_t ne_total) {
+  int64_t want = ctx->cfg.max_segments > 0 ? ctx->cfg.max_segments
+                                           : std::max<int64_t>(65536, std::min<int64_t>(ne_total / 64, 1 << 22));
+  if (want > ctx->seg_cap) {
+    fitrig_status rc;
+    const int64_t comp = 2 * want;
+    if ((rc = ensure(ctx, ctx->seg_entry, want * 8)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->seg_mask, want * 8)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->cell_q, want * 64 * 4)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->parent, want * 64 * 4)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->comp_of, want * 64 * 4)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->c_root, comp * 4)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->c_npix, comp * 4)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->c_key, comp * 8)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->c_w, comp * 6 * 8)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->c_box, comp * 4 * 4)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->c_out, 2 * comp * sizeof(fitrig_candidate))) != FITRIG_OK) return rc;
+    ctx->seg_cap = want;
+    ctx->comp_cap = comp;
+  }
+  return FITRIG_OK;
+}
+
+template <typename T>
+fitrig_status run_tile_kernel(fitrig_ctx* ctx, const Call& c, int tile, int Ty, int nchunk, int pieces) {
+  TileArgs A;
+  A.base = c.stack;
+  A.carry0 = A.carry1 = nullptr;
+  A.ncarry = 0;
+  A.n = c.n;
+  A.plane = (int64_t)c.H * c.W;
+  A.H = c.H;
+  A.W = c.W;
+  A.tile = tile;
+  A.nchunk = nchunk;
+  A.pieces = pieces;
+  A.r_signed = ctx->cfg.r_signed;
+  A.Cf = (float)ctx->cfg.C;
+  A.tile_part = (double*)ctx->tile_part.p;
+  A.wg_max = (float*)ctx->tile_wgmax.p;
+  hipLaunchKernelGGL((k_tile<T>), dim3(nchunk, Ty, c.n - 2), dim3(kLanes), 0, c.st, A);
+  LAUNCH_CHECK(ctx);
+  return FITRIG_OK;
+}
+
+fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand,
+                          fitrig_stats* stats) {
+  const fitrig_config& cfg = ctx->cfg;
+  hipStream_t st = c.st;
+  const int np = c.n - 2;
+  const int halo = cfg.window / 2;
+  const int64_t plane = (int64_t)c.H * c.W;
+  const bool img = (cfg.branches & FITRIG_IMAGE) != 0;
+  const bool freq = (cfg.branches & FITRIG_FREQ) != 0 && np >= 4 && np <= 2048;
+  const bool sliding = cfg.mode == FITRIG_SLIDING;
+  const int tile = cfg.tile;
+  const int Ty = (c.H + tile - 1) / tile, Tx = (c.W + tile - 1) / tile;
+  fitrig_status rc;
+
+  if ((rc = ensure(ctx, ctx->counters, CNT_N * 8)) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->mu, (size_t)np * 8)) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->sigma, (size_t)np * 8)) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->flags, (size_t)np * 4)) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->eta_st, 32)) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->M, 8)) != FITRIG_OK) return rc;
+  int64_t* cnt = (int64_t*)ctx->counters.p;
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, cnt, (int64_t)CNT_N, (int64_t)0);
+  double* mu = (double*)ctx->mu.p;
+  double* sigma = (double*)ctx->sigma.p;
+  uint32_t* flags = (uint32_t*)ctx->flags.p;
+  double* eta_mu = (double*)ctx->eta_st.p;
+  double* eta_sig = eta_mu + 1;
+  uint32_t* eta_flag = (uint32_t*)(eta_mu + 2);
+
+  // ---- pass over the stack -------------------------------------------------
+  bool have_cube = false;
+  int64_t nwg_max = 0;
+  const float* max_src = nullptr;
+  const int out_w = out_width(halo);
+  const int ncol = (c.W + out_w - 1) / out_w;
+  const int nbands = (c.H + kBand - 1) / kBand;
+  const int nseg_row = ncol * kSegsPerGroup;
+  float* qmap = nullptr;
+  const bool robust = cfg.sigma_est == FITRIG_MEDIAN_MAD;
+
+  if (img && sliding) {
+    const int64_t nwg = (int64_t)ncol * nbands;
+    if (nwg > INT32_MAX) return FITRIG_E_INVAL;
+    const bool byprod = freq && tile == 32;
+    if ((rc = ensure(ctx, ctx->stat_part, (size_t)np * nwg * 16)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->seg_max, (size_t)np * c.H * nseg_row * 4)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->wg_max, (size_t)nwg * 4)) != FITRIG_OK) return rc;
+    if (byprod && (rc = ensure(ctx, ctx->tile_part, (size_t)np * nbands * ncol * kPieces * 3 * 8)) != FITRIG_OK)
+      return rc;
+    qmap = c.index_map;
+    if (robust && !qmap) {
+      if ((rc = ensure(ctx, ctx->qscratch, (size_t)np * plane * 4)) != FITRIG_OK) return rc;
+      qmap = (float*)ctx->qscratch.p;
+    }
+    StreamArgs A;
+    A.base = c.stack;
+    A.carry0 = A.carry1 = nullptr;
+    A.ncarry = 0;
+    A.n = c.n;
+    A.plane = plane;
+    A.H = c.H;
+    A.W = c.W;
+    A.ncol = ncol;
+    A.nbands = nbands;
+    A.out_w = out_w;
+    A.r_signed = cfg.r_signed;
+    A.Cf = (float)cfg.C;
+    A.qmap = qmap;
+    A.stat_part = (double*)ctx->stat_part.p;
+    A.seg_max = (float*)ctx->seg_max.p;
+    A.tile_part = byprod ? (double*)ctx->tile_part.p : nullptr;
+    A.wg_max = (float*)ctx->wg_max.p;
+    switch (c.dtype) {
+      case FITRIG_F32: launch_stream<float>(halo, dim3((unsigned)nwg), st, A); break;
+      case FITRIG_F16: launch_stream<__half>(halo, dim3((unsigned)nwg), st, A); break;
+      default: launch_stream<bf16_t>(halo, dim3((unsigned)nwg), st, A); break;
+    }
+    LAUNCH_CHECK(ctx);
+    nwg_max = nwg;
+    max_src = (const float*)ctx->wg_max.p;
+    if (byprod) {
+      if ((rc = ensure(ctx, ctx->cube, (size_t)np * Ty * Tx * 8)) != FITRIG_OK) return rc;
+      if ((rc = ensure(ctx, ctx->cube_f, (size_t)np * Ty * Tx * 4)) != FITRIG_OK) return rc;
+      hipLaunchKernelGGL(k_tile_merge, dim3(grid_for((int64_t)np * Ty * Tx)), dim3(256), 0, st,
+                         (const double*)ctx->tile_part.p, np, nbands, 2, ncol, out_w, kPieces, 32, c.H, c.W, Ty, Tx,
+                         (double*)ctx->cube.p, (float*)ctx->cube_f.p);
+      LAUNCH_CHECK(ctx);
+      have_cube = true;
+    }
+    // per-triple spread
+    if (!robust) {
+      hipLaunchKernelGGL(k_moments, dim3(np), dim3(256), 0, st, (const double*)ctx->stat_part.p, nwg, 0, plane, mu,
+                         sigma, flags);
+      LAUNCH_CHECK(ctx);
+    } else {
+      if ((rc = robust_spread(ctx, st, qmap, np, plane, mu, sigma, flags)) != FITRIG_OK) return rc;
+    }
+  }
+
+  if ((!have_cube && (freq || (img && !sliding)))) {
+    const int nchunk = (c.W + kLanes - 1) / kLanes;
+    const int pieces = (kLanes + tile - 1) / tile + 1;
+    if ((rc = ensure(ctx, ctx->tile_part, (size_t)np * Ty * nchunk * pieces * 3 * 8)) != FITRIG_OK) return rc;
+    const int64_t nwg = (int64_t)np * Ty * nchunk;
+    if ((rc = ensure(ctx, ctx->tile_wgmax, (size_t)nwg * 4)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->cube, (size_t)np * Ty * Tx * 8)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->cube_f, (size_t)np * Ty * Tx * 4)) != FITRIG_OK) return rc;
+    switch (c.dtype) {
+      case FITRIG_F32: rc = run_tile_kernel<float>(ctx, c, tile, Ty, nchunk, pieces); break;
+      case FITRIG_F16: rc = run_tile_kernel<__half>(ctx, c, tile, Ty, nchunk, pieces); break;
+      default: rc = run_tile_kernel<bf16_t>(ctx, c, tile, Ty, nchunk, pieces); break;
+    }
+    if (nwg_max == 0) {
+      max_src = (const float*)ctx->tile_wgmax.p;
+      nwg_max = nwg;
+    }
+    if (rc != FITRIG_OK) return rc;
+    hipLaunchKernelGGL(k_tile_merge, dim3(grid_for((int64_t)np * Ty * Tx)), dim3(256), 0, st,
+                       (const double*)ctx->tile_part.p, np, Ty, 1, nchunk, kLanes, pieces, tile, c.H, c.W, Ty, Tx,
+                       (double*)ctx->cube.p, (float*)ctx->cube_f.p);
+    LAUNCH_CHECK(ctx);
+    have_cube = true;
+  }
+  if (nwg_max == 0) {
+    // no pass produced the maximum (e.g. frequency branch only, n' < 4)
+    const int g = 1024;
+    if ((rc = ensure(ctx, ctx->wg_max, g * 4)) != FITRIG_OK) return rc;
+    switch (c.dtype) {
+      case FITRIG_F32:
+        hipLaunchKernelGGL(k_stack_max<float>, dim3(g), dim3(256), 0, st, (const float*)c.stack, (int64_t)c.n * plane,
+                           (float*)ctx->wg_max.p);
+        break;
+      case FITRIG_F16:
+        hipLaunchKernelGGL(k_stack_max<__half>, dim3(g), dim3(256), 0, st, (const __half*)c.stack,
+                           (int64_t)c.n * plane, (float*)ctx->wg_max.p);
+        break;
+      default:
+        hipLaunchKernelGGL(k_stack_max<bf16_t>, dim3(g), dim3(256), 0, st, (const bf16_t*)c.stack,
+                           (int64_t)c.n * plane, (float*)ctx->wg_max.p);
+        break;
+    }
+    nwg_max = g;
+    max_src = (const float*)ctx->wg_max.p;
+  }
+  hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(256), 0, st, max_src, nwg_max, cfg.C,
+                     (double*)ctx->M.p);
+  LAUNCH_CHECK(ctx);
+
+  // ---- image-branch selection ---------------------------------------------
+  if (img) {
+    if (sliding) {
+      SegLayout L{c.H, c.W, np, kSegsPerGroup, out_w, nseg_row};
+      if ((rc = ensure_selection(ctx, (int64_t)np * c.H * nseg_row)) != FITRIG_OK) return rc;
+      if ((rc = select_run(ctx, c, L, (float*)ctx->seg_max.p, mu, sigma, flags, FITRIG_IMAGE, nullptr, halo)) !=
+          FITRIG_OK)
+        return rc;
+    } else {
+      const int64_t ncell = (int64_t)Ty * Tx;
+      if (!robust) {
+        hipLaunchKernelGGL(k_moments, dim3(np), dim3(256), 0, st, (const double*)ctx->cube.p, ncell, 1, ncell, mu,
+                           sigma, flags);
+        LAUNCH_CHECK(ctx);
+      } else {
+        if ((rc = robust_spread(ctx, st, (const float*)ctx->cube_f.p, np, ncell, mu, sigma, flags)) != FITRIG_OK)
+          return rc;
+      }
+      SegLayout L{Ty, Tx, np, 1, 64, (Tx + 63) / 64};
+      if ((rc = ensure(ctx, ctx->seg_max, (size_t)np * Ty * L.nseg_row * 4)) != FITRIG_OK) return rc;
+      hipLaunchKernelGGL(k_segmax_direct, dim3(grid_for((int64_t)np * Ty * L.nseg_row)), dim3(256), 0, st,
+                         (const float*)ctx->cube_f.p, L, (float*)ctx->seg_max.p);
+      if ((rc = ensure_selection(ctx, (int64_t)np * Ty * L.nseg_row)) != FITRIG_OK) return rc;
+      if ((rc = select_run(ctx, c, L, (float*)ctx->seg_max.p, mu, sigma, flags, FITRIG_IMAGE,
+                           (const float*)ctx->cube_f.p, halo)) != FITRIG_OK)
+        return rc;
+      if (c.index_map)
+        HIP_TRY(ctx, hipMemcpyAsync(c.index_map, ctx->cube_f.p, (size_t)np * ncell * 4, hipMemcpyDeviceToDevice, st));
+    }
+  }
+
+  // ---- frequency branch ----------------------------------------------------
+  if (freq) {
+    const int64_t ntiles = (int64_t)Ty * Tx;
+    if ((rc = ensure(ctx, ctx->eta_d, ntiles * 8)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->eta_f, ntiles * 4)) != FITRIG_OK) return rc;
+    hipLaunchKernelGGL(k_eta, dim3(grid_for(ntiles, 256, 4096)), dim3(256), (size_t)2 * np * 8, st,
+                       (const double*)ctx->cube.p, np, ntiles, cfg.harm, (double*)ctx->eta_d.p,
+                       (float*)ctx->eta_f.p);
+    LAUNCH_CHECK(ctx);
+    if (!robust) {
+      hipLaunchKernelGGL(k_moments, dim3(1), dim3(256), 0, st, (const double*)ctx->eta_d.p, ntiles, 1, ntiles, eta_mu,
+                         eta_sig, eta_flag);
+      LAUNCH_CHECK(ctx);
+    } else {
+      if ((rc = robust_spread(ctx, st, (const float*)ctx->eta_f.p, 1, ntiles, eta_mu, eta_sig, eta_flag)) != FITRIG_OK)
+        return rc;
+    }
+    SegLayout L{Ty, Tx, 1, 1, 64, (Tx + 63) / 64};
+    // segment maxima of eta go to a region of seg_max past anything still in use
+    const int64_t ne = (int64_t)Ty * L.nseg_row;
+    if ((rc = ensure(ctx, ctx->seg_max2, (size_t)ne * 4)) != FITRIG_OK) return rc;
+    float* smax = (float*)ctx->seg_max2.p;
+    hipLaunchKernelGGL(k_segmax_direct, dim3(grid_for(ne)), dim3(256), 0, st, (const float*)ctx->eta_f.p, L, smax);
+    if ((rc = ensure_selection(ctx, ne)) != FITRIG_OK) return rc;
+    if ((rc = select_run(ctx, c, L, smax, eta_mu, eta_sig, eta_flag, FITRIG_FREQ, (const float*)ctx->eta_f.p, halo)) !=
+        FITRIG_OK)
+      return rc;
+    if (c.eta_map)
+      HIP_TRY(ctx, hipMemcpyAsync(c.eta_map, ctx->eta_f.p, (size_t)ntiles * 4, hipMemcpyDeviceToDevice, st));
+  }
+
+  if (c.index_map && sliding && img && cfg.map_kind == FITRIG_MAP_TLISI) {
+    hipLaunchKernelGGL(k_to_tlisi, dim3(grid_for((int64_t)np * plane, 256, 8192)), dim3(256), 0, st, c.index_map,
+                       (int64_t)np * plane, (const double*)ctx->M.p);
+    LAUNCH_CHECK(ctx);
+  }
+
+  // ---- results to the host --------------------------------------------------
+  const size_t small = CNT_N * 8 + 8 + 32 + (size_t)np * (8 + 8 + 4);
+  if ((rc = ensure_host(ctx, small)) != FITRIG_OK) return rc;
+  char* h = (char*)ctx->h_stage;
+  int64_t* h_cnt = (int64_t*)h;
+  double* h_M = (double*)(h + CNT_N * 8);
+  double* h_eta = (double*)(h + CNT_N * 8 + 8);
+  double* h_mu = (double*)(h + CNT_N * 8 + 8 + 32);
+  double* h_sig = h_mu + np;
+  uint32_t* h_fl = (uint32_t*)(h_sig + np);
+  HIP_TRY(ctx, hipMemcpyAsync(h_cnt, cnt, CNT_N * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(h_M, ctx->M.p, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(h_eta, ctx->eta_st.p, 24, hipMemcpyDeviceToHost, st));
+  if (img && sliding) {
+    HIP_TRY(ctx, hipMemcpyAsync(h_mu, mu, (size_t)np * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(h_sig, sigma, (size_t)np * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(h_fl, flags, (size_t)np * 4, hipMemcpyDeviceToHost, st));
+  } else if (img) {
+    HIP_TRY(ctx, hipMemcpyAsync(h_mu, mu, (size_t)np * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(h_sig, sigma, (size_t)np * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(h_fl, flags, (size_t)np * 4, hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  const int64_t total = h_cnt[CNT_OUTBASE];
+  const bool trunc_internal = h_cnt[CNT_TRUNC] != 0;
+  const int64_t ncopy = std::min<int64_t>(total, cand_cap);
+  if (ncopy > 0 && cand) {
+    HIP_TRY(ctx, hipMemcpyAsync(cand, ctx->c_out.p, (size_t)ncopy * sizeof(fitrig_candidate),
+                                hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+  }
+  *n_cand = total;
+  if (stats) {
+    stats->M = *h_M;
+    stats->n_triples = np;
+    stats->eta_mu = freq ? h_eta[0] : 0.0;
+    stats->eta_sigma = freq ? h_eta[1] : 0.0;
+    stats->n_image_cand = h_cnt[CNT_IMG];
+    stats->n_freq_cand = h_cnt[CNT_FREQ];
+    for (int s = 0; s < np; ++s) {
+      const uint32_t tf = trunc_internal ? FITRIG_FLAG_TRUNC : 0u;
+      if (stats->mu) stats->mu[s] = img ? h_mu[s] : 0.0;
+      if (stats->sigma) stats->sigma[s] = img ? h_sig[s] : 0.0;
+      if (stats->flags) stats->flags[s] = (img ? h_fl[s] : 0u) | tf;
+    }
+  }
+  if (trunc_internal || total > cand_cap) return FITRIG_E_TRUNC;
+  return FITRIG_OK;
+}
+
+fitrig_status validate_cfg(const fitrig_config* c) {
+  if (!c || c->abi_version != FITRIG_ABI_VERSION) return FITRIG_E_INVAL;
+  if (c->mode != FITRIG_SLIDING && c->mode != FITRIG_TILES) return FITRIG_E_INVAL;
+  if (c->window < 1 || c->window % 2 == 0 || c->window > 2 * kMaxHalo + 1) return FITRIG_E_INVAL;
+  if (c->tile < 1) return FITRIG_E_INVAL;
+  if (c->branches < 1 || c->branches > 3) return FITRIG_E_INVAL;
+  if (c->sigma_est != FITRIG_MEAN_STD && c->sigma_est != FITRIG_MEDIAN_MAD) return FITRIG_E_INVAL;
+  if (c->harm < 0 || c->harm == 1 || c->harm > 64) return FITRIG_E_INVAL;
+  if (c->r_signed != 0 && c->r_signed != 1) return FITRIG_E_INVAL;
+  if (c->map_kind != FITRIG_MAP_QTILDE && c->map_kind != FITRIG_MAP_TLISI) return FITRIG_E_INVAL;
+  if (!(c->C > 0.0) || !isfinite(c->C)) return FITRIG_E_INVAL;
+  if (c->max_pixels < 0 || c->max_snap < 0 || c->max_segments < 0) return FITRIG_E_INVAL;
+  return FITRIG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fitrig_config_default(fitrig_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->abi_version = FITRIG_ABI_VERSION;
+  cfg->mode = FITRIG_SLIDING;
+  cfg->window = 7;
+  cfg->tile = 32;
+  cfg->branches = FITRIG_IMAGE | FITRIG_FREQ;
+  cfg->sigma_est = FITRIG_MEAN_STD;
+  cfg->harm = 0;
+  cfg->r_signed = 0;
+  cfg->map_kind = FITRIG_MAP_QTILDE;
+  cfg->device = 0;
+  cfg->C = 1e-6;
+}
+
+int32_t fitrig_abi_version(void) { return FITRIG_ABI_VERSION; }
+
+const char* fitrig_status_string(fitrig_status s) {
+  switch (s) {
+    case FITRIG_OK: return "ok";
+    case FITRIG_E_INVAL: return "invalid argument";
+    case FITRIG_E_NOMEM: return "out of memory";
+    case FITRIG_E_HIP: return "HIP runtime error";
+    case FITRIG_E_TRUNC: return "results truncated (capacity exceeded)";
+    case FITRIG_E_BUSY: return "admission refused (busy)";
+    case FITRIG_E_NOTREADY: return "result not ready";
+    default: return "unknown status";
+  }
+}
+
+int32_t fitrig_last_hip_error(const fitrig_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+fitrig_status fitrig_create(const fitrig_config* cfg, fitrig_ctx** out) {
+  if (!out) return FITRIG_E_INVAL;
+  *out = nullptr;
+  fitrig_status rc = validate_cfg(cfg);
+  if (rc != FITRIG_OK) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return FITRIG_E_INVAL;
+  fitrig_ctx* ctx = new (std::nothrow) fitrig_ctx();
+  if (!ctx) return FITRIG_E_NOMEM;
+  ctx->cfg = *cfg;
+  hipError_t e = hipSetDevice(cfg->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete ctx;
+    return FITRIG_E_HIP;
+  }
+  // Scratch sized from the capacity hints, so warm calls allocate nothing.
+  if (cfg->max_pixels > 0 && cfg->max_snap >= 3) {
+    const int64_t np = cfg->max_snap - 2;
+    const int halo = cfg->window / 2;
+    const int64_t Wd = (int64_t)ceil(sqrt((double)cfg->max_pixels));
+    const int out_w = out_width(halo);
+    const int64_t ncol = (Wd + out_w - 1) / out_w + 1;
+    const int64_t nbands = (Wd + kBand - 1) / kBand + 1;
+    const int64_t nwg = ncol * nbands;
+    const int64_t nseg = np * (cfg->max_pixels / out_w + Wd) * kSegsPerGroup;
+    if ((rc = ensure(ctx, ctx->stat_part, (size_t)(np * nwg * 16))) != FITRIG_OK ||
+        (rc = ensure(ctx, ctx->seg_max, (size_t)(nseg * 4))) != FITRIG_OK ||
+        (rc = ensure(ctx, ctx->wg_max, (size_t)(nwg * 4))) != FITRIG_OK ||
+        (rc = ensure_selection(ctx, nseg)) != FITRIG_OK) {
+      fitrig_destroy(ctx);
+      return rc;
+    }
+  }
+  *out = ctx;
+  return FITRIG_OK;
+}
+
+fitrig_status fitrig_destroy(fitrig_ctx* ctx) {
+  if (!ctx) return FITRIG_E_INVAL;
+  (void)hipSetDevice(ctx->cfg.device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  DevBuf* bufs[] = {&ctx->seg_max2, &ctx->tile_wgmax, &ctx->stat_part, &ctx->seg_max,  &ctx->tile_part, &ctx->wg_max,   &ctx->cube,    &ctx->cube_f,
+                    &ctx->eta_d,     &ctx->eta_f,    &ctx->mu,        &ctx->sigma,    &ctx->flags,   &ctx->eta_st,
+                    &ctx->M,         &ctx->qscratch, &ctx->hist,      &ctx->rs_state, &ctx->rs_med,  &ctx->rs_dev,
+                    &ctx->chunk_cnt, &ctx->counters, &ctx->seg_entry, &ctx->seg_mask, &ctx->cell_q,  &ctx->parent,
+                    &ctx->comp_of,   &ctx->c_root,   &ctx->c_npix,    &ctx->c_key,    &ctx->c_w,     &ctx->c_box,
+                    &ctx->c_out};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return FITRIG_OK;
+}
+
+fitrig_status fitrig_detect(fitrig_ctx* ctx, const void* stack, fitrig_dtype dtype, int32_t n_snap, int32_t H,
+                            int32_t W, double sigma, fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand,
+                            float* index_map, float* eta_map, fitrig_stats* stats, void* hip_stream) {
+  if (!ctx || !stack || !n_cand) return FITRIG_E_INVAL;
+  if (dtype != FITRIG_F32 && dtype != FITRIG_F16 && dtype != FITRIG_BF16) return FITRIG_E_INVAL;
+  if (n_snap < 3 || H < 1 || W < 1) return FITRIG_E_INVAL;
+  if ((uint64_t)H * (uint64_t)W >= (1ull << 32)) return FITRIG_E_INVAL;
+  if (!(sigma > 0.0) || !isfinite(sigma)) return FITRIG_E_INVAL;
+  if (cand_cap < 0 || (cand_cap > 0 && !cand)) return FITRIG_E_INVAL;
+  *n_cand = 0;
+  if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FITRIG_E_HIP;
+  Call c;
+  c.stack = stack;
+  c.dtype = dtype;
+  c.n = n_snap;
+  c.H = H;
+  c.W = W;
+  c.tau = sigma;
+  c.index_map = index_map;
+  c.eta_map = eta_map;
+  c.st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+  return detect_impl(ctx, c, cand, cand_cap, n_cand, stats);
+}
+
+}  // extern "C"

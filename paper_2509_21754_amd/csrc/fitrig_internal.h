@@ -1,0 +1,101 @@
+// Internal declarations shared by the FITrig device code and its host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fitrig {
+
+// Output rows per band of the streaming kernel, lanes (input columns) per
+// workgroup, 64-cell row segments per column group.
+constexpr int kBand = 16;
+constexpr int kLanes = 256;
+constexpr int kSegsPerGroup = 4;
+constexpr int kMaxHalo = 8;          // window <= 17
+constexpr int kPieces = 9;           // 32-wide tile pieces a column group can touch
+constexpr int kHistBins = 2048;      // radix-select digit bins (11 bits)
+
+inline int out_width(int halo) { return halo <= 4 ? kLanes - 8 : kLanes - 16; }
+
+// Streaming index kernel arguments (one launch covers every triple).
+struct StreamArgs {
+  const void* base;      // first frame of the new stack
+  const void* carry0;    // frames carried in front of the stack (serving), nullable
+  const void* carry1;
+  int32_t ncarry;
+  int32_t n;             // total frames seen by the kernel = ncarry + new frames
+  int64_t plane;         // H * W
+  int32_t H, W;
+  int32_t ncol, nbands, out_w;
+  int32_t r_signed;
+  float Cf;
+  float* qmap;           // nullable [n-2][H][W]
+  double* stat_part;     // [n-2][nwg][2]  (sum q, sum q^2)
+  float* seg_max;        // [n-2][H][ncol*4]
+  double* tile_part;     // nullable [n-2][nbands][ncol][kPieces][3]
+  float* wg_max;         // [nwg]
+};
+
+// Generic tile-mode kernel arguments (re-reads the three frames of a triple).
+struct TileArgs {
+  const void* base;
+  const void* carry0;
+  const void* carry1;
+  int32_t ncarry;
+  int32_t n;
+  int64_t plane;
+  int32_t H, W;
+  int32_t tile;
+  int32_t nchunk;        // ceil(W / 256)
+  int32_t pieces;        // tiles a 256-column chunk can touch
+  int32_t r_signed;
+  float Cf;
+  double* tile_part;     // [n-2][Ty][nchunk][pieces][3]
+  float* wg_max;         // [grid]
+};
+
+// Layout of the 64-cell row segments a selection works on.
+struct SegLayout {
+  int32_t Ho, Wo;        // cell grid of one set (one triple)
+  int32_t nsets;         // number of sets (triples)
+  int32_t spg;           // segments per column group
+  int32_t gw;            // column-group width (cells)
+  int32_t nseg_row;      // segments per row
+};
+
+__host__ __device__ inline int seg_x0(const SegLayout& L, int g) {
+  return (g / L.spg) * L.gw + (g % L.spg) * 64;
+}
+__host__ __device__ inline int seg_width(const SegLayout& L, int g) {
+  int x0 = seg_x0(L, g);
+  int w = L.gw - (g % L.spg) * 64;
+  if (w > 64) w = 64;
+  if (x0 + w > L.Wo) w = L.Wo - x0;
+  return w < 0 ? 0 : w;
+}
+__host__ __device__ inline int seg_of_x(const SegLayout& L, int x) {
+  return (x / L.gw) * L.spg + (x % L.gw) / 64;
+}
+
+// Device-side scratch used by a selection pipeline run.
+struct SelBuffers {
+  int64_t seg_cap;       // capacity in segments
+  int64_t comp_cap;      // capacity in components
+  int64_t* seg_entry;    // [seg_cap] entry index (set * Ho * nseg_row + y * nseg_row + g)
+  uint64_t* seg_mask;    // [seg_cap]
+  float* cell_q;         // [seg_cap * 64]
+  int32_t* parent;       // [seg_cap * 64]
+  int32_t* comp_of;      // [seg_cap * 64]
+  uint32_t* chunk_cnt;   // scan workspace
+  int64_t chunk_cap;
+  int64_t* counters;     // [0]=segments selected, [1]=components, [2]=trunc flag, [3]=comps written
+  // component accumulators [comp_cap]
+  int32_t* c_root;
+  int32_t* c_npix;
+  unsigned long long* c_key;
+  unsigned long long* c_w;     // 128-bit pairs: w, w*y, w*x -> 6 per component
+  int32_t* c_box;              // 4 per component
+  void* c_out;                 // fitrig_candidate[comp_cap]
+};
+
+}  // namespace fitrig

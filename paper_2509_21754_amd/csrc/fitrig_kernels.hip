@@ -1,0 +1,1093 @@
+// FITrig device code for CDNA4 (gfx950): streaming index kernel, tile-mode
+// kernel, statistics, exact selection by recompute, union-find components,
+// image-frequency transform and radix selection for the robust spread.
+//
+// Method (Li, Adamek & Armour, arXiv 2509.21754):
+//   Delta = ||x(s+2)-x(s+1)| - |x(s+1)-x(s)||, reference x(s+1)  Sec. 2.2.4, Eqs. (3)-(5)
+//   r = min(Delta / |x_hat|, 1), x_hat = C where x(s+1) == 0       Eqs. (4)-(5)
+//   q = mean(Delta) max(Delta) mean(r) over the window / tile       Eq. (2), Eq. (6)
+//   z = (q - mean q) / std q per triple, select z > tau             Sec. 2.4.1, Eqs. (8)-(9)
+//   eta = h(|DFT_s[q(s) - mean q]|) per tile, z on eta               Sec. 2.4.2, Eqs. (10)-(12)
+//
+// Window sums use 8-row / 8-column blocks aligned to absolute multiples of
+// 8: a window [L, R] is suffix(block of L) + totals of whole blocks +
+// prefix(block of R), with prefix / suffix defined by fixed left-to-right /
+// right-to-left recurrences. The value of a cell therefore depends only on
+// its absolute position, so the exact selection kernel recomputes it to the
+// same bits as the streaming kernel.
+#include <hip/hip_fp16.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "fitrig.h"
+#include "fitrig_internal.h"
+
+namespace fitrig {
+
+struct bf16_t {
+  uint16_t v;
+};
+
+template <typename T>
+__device__ __forceinline__ float to_f(T v);
+template <>
+__device__ __forceinline__ float to_f<float>(float v) {
+  return v;
+}
+template <>
+__device__ __forceinline__ float to_f<__half>(__half v) {
+  return __half2float(v);
+}
+template <>
+__device__ __forceinline__ float to_f<bf16_t>(bf16_t v) {
+  return __uint_as_float(((uint32_t)v.v) << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ const T* frame_ptr(const void* base, const void* c0, const void* c1,
+                                              int ncarry, int64_t plane, int k) {
+  if (k < ncarry) return (const T*)(k == 0 ? c0 : c1);
+  return (const T*)base + (int64_t)(k - ncarry) * plane;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous run of logical tiles so neighbours share halo lines in its L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = bid & 7, k = bid >> 3;
+  return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
+constexpr int fdiv8(int a) { return a >= 0 ? a / 8 : -((-a + 7) / 8); }
+
+// Window reduction over a register array.
+//   a[i] holds the value at relative position P = i - H (P in [-H, NOUT+H-1]),
+//   the base position (P = 0) being a multiple of 8 in absolute coordinates.
+//   o[c] = op over positions [c-H, c+H]; tot[j] = prefix of block j at 7
+//   (sum / max of the 8 positions [8j, 8j+7]).
+template <int H, int NOUT, bool MAXOP>
+struct Win {
+  static constexpr int NIN = NOUT + 2 * H;
+  static constexpr int MLO = -1;
+  static constexpr int MHI = fdiv8(NOUT - 1 + H);
+  static constexpr int NB = MHI - MLO + 1;
+  __device__ static __forceinline__ float op(float x, float y) { return MAXOP ? fmaxf(x, y) : x + y; }
+
+  __device__ static __forceinline__ void run(const float* a, float* o, float* tot) {
+    if constexpr (H <= 2) {
+#pragma unroll
+      for (int c = 0; c < NOUT; ++c) {
+        float s = a[c];
+#pragma unroll
+        for (int j = 1; j <= 2 * H; ++j) s = op(s, a[c + j]);
+        o[c] = s;
+      }
+      if (tot) {
+#pragma unroll
+        for (int j = 0; j < NOUT / 8; ++j) {
+          float s = a[H + 8 * j];
+#pragma unroll
+          for (int p = 1; p < 8; ++p) s = op(s, a[H + 8 * j + p]);
+          tot[j] = s;
+        }
+      }
+    } else {
+      float pre[NB][8] = {};
+      float suf[NB][8] = {};
+#pragma unroll
+      for (int mi = 0; mi < NB; ++mi) {
+        const int m = mi + MLO;
+        const int st = H + 8 * m;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const int idx = st + p;
+          if (st >= 0 && idx < NIN) pre[mi][p] = (p == 0) ? a[idx] : op(pre[mi][p - 1], a[idx]);
+        }
+#pragma unroll
+        for (int p = 7; p >= 0; --p) {
+          const int idx = st + p;
+          if (st + 7 < NIN && idx >= 0) suf[mi][p] = (p == 7) ? a[idx] : op(a[idx], suf[mi][p + 1]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NOUT; ++c) {
+        const int L = c - H, R = c + H;
+        const int bs = fdiv8(L), be = fdiv8(R);
+        const int ps = L - 8 * bs, pe = R - 8 * be;
+        if (bs == be) {
+          o[c] = (ps == 0) ? pre[bs - MLO][pe] : suf[bs - MLO][ps];
+        } else {
+          float s = suf[bs - MLO][ps];
+#pragma unroll
+          for (int m = bs + 1; m < be; ++m) s = op(s, pre[m - MLO][7]);
+          o[c] = op(s, pre[be - MLO][pe]);
+        }
+      }
+      if (tot) {
+#pragma unroll
+        for (int j = 0; j < NOUT / 8; ++j) tot[j] = pre[j - MLO][7];
+      }
+    }
+  }
+};
+
+// Maximum over each aligned group of 8 lanes (DPP quad xor 1, xor 2, half-row mirror).
+__device__ __forceinline__ float group8_max(float v) {
+  float t = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v = fmaxf(v, t);
+  t = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v = fmaxf(v, t);
+  t = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+  return fmaxf(v, t);
+}
+
+// Pointwise terms of one pixel: Delta from the two frame differences, r from
+// the reference pixel (Eqs. (3)-(5)).
+__device__ __forceinline__ void pix_terms(float d_new, float d_old, float ref, float Cf, int r_signed,
+                                          float& dl, float& rl) {
+  dl = fabsf(fabsf(d_new) - fabsf(d_old));
+  float den = (ref == 0.0f) ? Cf : ref;
+  if (!r_signed) den = fabsf(den);
+  rl = fminf(dl * __builtin_amdgcn_rcpf(den), 1.0f);
+}
+
+// 1 / n^2 for a window of n in-image cells (n = rows * cols).
+__device__ __forceinline__ float inv_count2(int y, int x, int H, int Hh, int Wh) {
+  const int cy = min(y + H, Hh - 1) - max(y - H, 0) + 1;
+  const int cx = min(x + H, Wh - 1) - max(x - H, 0) + 1;
+  const int nn = cy * cx;
+  return 1.0f / (float)(nn * nn);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming index kernel (sliding window). One workgroup owns 16 output rows
+// x out_w output columns and walks every frame once, keeping the previous
+// frame and the previous difference of its (16 + 2H) x 256 input pixels in
+// registers. Per triple it writes FP64 moment partials, the maximum q of
+// every 64-cell row segment, optional q map rows, and (tile == 32) the
+// per-column sums of the 32-row tiles for the frequency branch.
+// ---------------------------------------------------------------------------
+template <typename T, int H>
+__global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
+  constexpr int NR = kBand + 2 * H;
+  constexpr int NH = 8 + 2 * H;
+  constexpr int LDW = kLanes + 4;
+  __shared__ float sV[3][kBand][LDW];
+  __shared__ float sCol[3][kLanes];
+  __shared__ double sRed[2][kLanes / 64];
+  __shared__ float sMax[kLanes / 64];
+
+  const int lane = threadIdx.x;
+  const int wave = lane >> 6;
+  const int nwg = gridDim.x;
+  const int bid = xcd_remap(blockIdx.x, nwg);
+  const int band = bid / A.ncol;
+  const int grp = bid - band * A.ncol;
+  const int y0 = band * kBand;
+  const int x0 = grp * A.out_w;
+  const int xin = x0 - H + lane;
+  const bool colv = (lane < A.out_w + 2 * H) && xin >= 0 && xin < A.W;
+  const int nseg_row = A.ncol * kSegsPerGroup;
+  const bool interior =
+      (y0 - H >= 0) && (y0 + kBand - 1 + H < A.H) && (x0 - H >= 0) && (x0 + A.out_w - 1 + H < A.W);
+  constexpr int WN = (2 * H + 1) * (2 * H + 1);
+  const float inv_full = 1.0f / (float)(WN * WN);
+
+  float xp[NR], dp[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    xp[i] = 0.0f;
+    dp[i] = 0.0f;
+  }
+  float mx = -INFINITY;
+
+  for (int k = 0; k < A.n; ++k) {
+    const T* fr = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, k);
+    float xn[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int y = y0 - H + i;
+      float v = 0.0f;
+      if (colv && y >= 0 && y < A.H) v = to_f<T>(fr[(int64_t)y * A.W + xin]);
+      xn[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < NR; i += 2) mx = (i + 1 < NR) ? fmaxf(mx, fmaxf(xn[i], xn[i + 1])) : fmaxf(mx, xn[i]);
+    float d[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) d[i] = xn[i] - xp[i];
+
+    if (k >= 2) {
+      const int s = k - 2;
+      float dl[NR], rl[NR];
+#pragma unroll
+      for (int i = 0; i < NR; ++i) pix_terms(d[i], dp[i], xp[i], A.Cf, A.r_signed, dl[i], rl[i]);
+      {
+        float vs[kBand], vm[kBand], vr[kBand], ts[kBand / 8], tm[kBand / 8], tr[kBand / 8];
+        Win<H, kBand, false>::run(dl, vs, ts);
+        Win<H, kBand, true>::run(dl, vm, tm);
+        Win<H, kBand, false>::run(rl, vr, tr);
+#pragma unroll
+        for (int c = 0; c < kBand; ++c) {
+          sV[0][c][lane] = vs[c];
+          sV[1][c][lane] = vm[c];
+          sV[2][c][lane] = vr[c];
+        }
+        if (A.tile_part) {
+          const int ox = lane - H;
+          if (ox >= 0 && ox < A.out_w) {
+            sCol[0][ox] = colv ? ts[0] + ts[1] : 0.0f;
+            sCol[1][ox] = colv ? fmaxf(tm[0], tm[1]) : 0.0f;
+            sCol[2][ox] = colv ? tr[0] + tr[1] : 0.0f;
+          }
+        }
+      }
+      __syncthreads();
+
+      double ssum = 0.0, ssq = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int task = lane + kLanes * t;
+        const int r = task >> 5, ch = task & 31;
+        const int y = y0 + r;
+        const int xc = x0 + 8 * ch;
+        const bool chv = (8 * ch < A.out_w) && (xc < A.W) && (y < A.H);
+        const int cb = chv ? 8 * ch : 0;
+        float hs[NH], hm[NH], hr[NH];
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+          hs[i] = sV[0][r][cb + i];
+          hm[i] = sV[1][r][cb + i];
+          hr[i] = sV[2][r][cb + i];
+        }
+        float os[8], om[8], orr[8];
+        Win<H, 8, false>::run(hs, os, nullptr);
+        Win<H, 8, true>::run(hm, om, nullptr);
+        Win<H, 8, false>::run(hr, orr, nullptr);
+        float qv[8];
+        float gmax = -INFINITY;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int x = xc + c;
+          const bool v = chv && x < A.W;
+          float inv = inv_full;
+          if (!interior) inv = inv_count2(y, x, H, A.H, A.W);
+          const float q = ((os[c] * om[c]) * orr[c]) * inv;
+          qv[c] = q;
+          if (v) {
+            const double qd = (double)q;
+            ssum += qd;
+            ssq = fma(qd, qd, ssq);
+            gmax = fmaxf(gmax, q);
+          }
+        }
+        gmax = group8_max(gmax);
+        if (chv && (ch & 7) == 0)
+          A.seg_max[((int64_t)s * A.H + y) * nseg_row + grp * kSegsPerGroup + (ch >> 3)] = gmax;
+        if (A.qmap && chv) {
+          float* dst = A.qmap + ((int64_t)s * A.H + y) * A.W + xc;
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            if (xc + c < A.W) dst[c] = qv[c];
+        }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        ssum += __shfl_xor(ssum, off);
+        ssq += __shfl_xor(ssq, off);
+      }
+      if ((lane & 63) == 0) {
+        sRed[0][wave] = ssum;
+        sRed[1][wave] = ssq;
+      }
+      __syncthreads();
+      if (lane == 0) {
+        double a0 = sRed[0][0], a1 = sRed[1][0];
+#pragma unroll
+        for (int w = 1; w < kLanes / 64; ++w) {
+          a0 += sRed[0][w];
+          a1 += sRed[1][w];
+        }
+        A.stat_part[((int64_t)s * nwg + bid) * 2 + 0] = a0;
+        A.stat_part[((int64_t)s * nwg + bid) * 2 + 1] = a1;
+      }
+      if (A.tile_part && lane < kPieces * 3) {
+        const int p = lane / 3, qd = lane - 3 * (lane / 3);
+        const int tx = x0 / 32 + p;
+        const int ca = max(tx * 32, x0) - x0;
+        const int cbnd = min(min(tx * 32 + 32, x0 + A.out_w), A.W) - x0;
+        double acc = 0.0;
+        for (int c = ca; c < cbnd; ++c) {
+          const double v = (double)sCol[qd][c];
+          acc = (qd == 1) ? fmax(acc, v) : acc + v;
+        }
+        A.tile_part[((((int64_t)s * A.nbands + band) * A.ncol + grp) * kPieces + p) * 3 + qd] = acc;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      dp[i] = d[i];
+      xp[i] = xn[i];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  if ((lane & 63) == 0) sMax[wave] = mx;
+  __syncthreads();
+  if (lane == 0) {
+    float m = sMax[0];
+    for (int w = 1; w < kLanes / 64; ++w) m = fmaxf(m, sMax[w]);
+    A.wg_max[bid] = m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile-mode kernel: one workgroup per (256-column chunk, tile row, triple).
+// Each lane owns a column, reads the three frames of the triple over the
+// tile row and accumulates sum Delta, max Delta and sum r in FP64; per tile
+// piece of the chunk the columns are summed in order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kLanes) void k_tile(TileArgs A) {
+  __shared__ double sCol[3][kLanes];
+  __shared__ float sMax[kLanes / 64];
+  const int lane = threadIdx.x;
+  const int chunk = blockIdx.x, ty = blockIdx.y, s = blockIdx.z;
+  const int x = chunk * kLanes + lane;
+  const bool cv = x < A.W;
+  const T* f0 = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, s);
+  const T* f1 = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, s + 1);
+  const T* f2 = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, s + 2);
+  const int ya = ty * A.tile;
+  const int yb = min(ya + A.tile, A.H);
+  double sd = 0.0, md = 0.0, sr = 0.0;
+  float mx = -INFINITY;
+  if (cv) {
+    for (int y = ya; y < yb; ++y) {
+      const int64_t o = (int64_t)y * A.W + x;
+      const float a = to_f<T>(f0[o]), b = to_f<T>(f1[o]), c = to_f<T>(f2[o]);
+      mx = fmaxf(mx, fmaxf(a, fmaxf(b, c)));
+      float dl, rl;
+      pix_terms(c - b, b - a, b, A.Cf, A.r_signed, dl, rl);
+      sd += (double)dl;
+      md = fmax(md, (double)dl);
+      sr += (double)rl;
+    }
+  }
+  sCol[0][lane] = sd;
+  sCol[1][lane] = md;
+  sCol[2][lane] = sr;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  if ((lane & 63) == 0) sMax[lane >> 6] = mx;
+  __syncthreads();
+  const int x0 = chunk * kLanes;
+  for (int job = lane; job < A.pieces * 3; job += kLanes) {
+    const int p = job / 3, qd = job - 3 * (job / 3);
+    const int tx = x0 / A.tile + p;
+    const int ca = max(tx * A.tile, x0) - x0;
+    const int cb = min(min(tx * A.tile + A.tile, x0 + kLanes), A.W) - x0;
+    double acc = 0.0;
+    for (int c = ca; c < cb; ++c) acc = (qd == 1) ? fmax(acc, sCol[1][c]) : acc + sCol[qd][c];
+    A.tile_part[((((int64_t)s * gridDim.y + ty) * A.nchunk + chunk) * A.pieces + p) * 3 + qd] = acc;
+  }
+  if (lane == 0) {
+    float m = sMax[0];
+    for (int w = 1; w < kLanes / 64; ++w) m = fmaxf(m, sMax[w]);
+    A.wg_max[((int64_t)s * gridDim.y + ty) * A.nchunk + chunk] = m;
+  }
+}
+
+// Tile q from pieces: (sum Delta / n) max Delta (sum r / n), n = cells of the
+// (possibly partial) tile in the image (Eq. (6) with the actual count).
+__global__ void k_tile_merge(const double* part, int nsets, int nbands_part, int bpt, int nchunk, int cw,
+                             int pieces, int tile, int H, int W, int Ty, int Tx, double* cube,
+                             float* cube_f) {
+  const int64_t total = (int64_t)nsets * Ty * Tx;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int tx = (int)(i % Tx);
+    const int ty = (int)((i / Tx) % Ty);
+    const int s = (int)(i / ((int64_t)Tx * Ty));
+    double sd = 0.0, mx = 0.0, sr = 0.0;
+    const int b1 = min(ty * bpt + bpt, nbands_part);
+    const int xa = tx * tile, xb = min(xa + tile, W);
+    for (int b = ty * bpt; b < b1; ++b) {
+      for (int ch = xa / cw; ch <= (xb - 1) / cw; ++ch) {
+        const int p = tx - (ch * cw) / tile;
+        const double* q = part + ((((int64_t)s * nbands_part + b) * nchunk + ch) * pieces + p) * 3;
+        sd += q[0];
+        mx = fmax(mx, q[1]);
+        sr += q[2];
+      }
+    }
+    const double n = (double)(min(ty * tile + tile, H) - ty * tile) * (double)(xb - xa);
+    const double v = (sd / n) * mx * (sr / n);
+    cube[i] = v;
+    if (cube_f) cube_f[i] = (float)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Statistics.
+// ---------------------------------------------------------------------------
+// Fixed-order FP64 reduction of a workgroup (256 threads).
+__device__ double wg_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Per set: mean and population std from moment partials [set][nparts][2]
+// (raw = 0) or from raw values [set][nparts] (raw = 1).
+__global__ __launch_bounds__(256) void k_moments(const double* src, int64_t nparts, int raw, int64_t count,
+                                                 double* mu, double* sigma, uint32_t* flags) {
+  __shared__ double sh[256];
+  const int s = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < nparts; i += 256) {
+    if (raw) {
+      const double v = src[(int64_t)s * nparts + i];
+      a += v;
+      b = fma(v, v, b);
+    } else {
+      a += src[((int64_t)s * nparts + i) * 2 + 0];
+      b += src[((int64_t)s * nparts + i) * 2 + 1];
+    }
+  }
+  a = wg_sum(a, sh);
+  b = wg_sum(b, sh);
+  if (threadIdx.x == 0) {
+    const double m = a / (double)count;
+    double var = b / (double)count - m * m;
+    if (!(var > 0.0)) var = 0.0;
+    const double sg = sqrt(var);
+    mu[s] = m;
+    sigma[s] = sg;
+    flags[s] = (sg > 0.0 && isfinite(sg) && isfinite(m)) ? 0u : (uint32_t)FITRIG_FLAG_SIGMA_ZERO;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_max_finalize(const float* wg_max, int64_t n, double C, double* M) {
+  __shared__ float sh[256];
+  float m = -INFINITY;
+  for (int64_t i = threadIdx.x; i < n; i += 256) m = fmaxf(m, wg_max[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) M[0] = fmax((double)sh[0], C);
+}
+
+__global__ void k_to_tlisi(float* map, int64_t n, const double* M) {
+  const double m2 = M[0] * M[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    map[i] = (float)(1.0 - (double)map[i] / m2);
+}
+
+__global__ void k_f64_to_f32(const double* src, float* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Radix selection (exact order statistics of a float array per set) for the
+// median / MAD spread. Keys: orderable bits of q (mode 0) or bits of
+// float(|q - med|) (mode 1). Three passes of 11, 11, 10 bits.
+// ---------------------------------------------------------------------------
+struct RsState {
+  uint32_t prefix;
+  uint32_t known;
+  int64_t rank;
+};
+
+__device__ __forceinline__ uint32_t ord_key(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord_val(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+__global__ __launch_bounds__(256) void k_rs_hist(const float* vals, int64_t per_set, int mode, const double* med,
+                                                 const RsState* st, int shift, int nbits, uint32_t* hist) {
+  __shared__ uint32_t h[kHistBins];
+  const int s = blockIdx.y;
+  for (int i = threadIdx.x; i < kHistBins; i += 256) h[i] = 0;
+  __syncthreads();
+  const RsState S = st[s];
+  const uint32_t dmask = (1u << nbits) - 1u;
+  const float* v = vals + (int64_t)s * per_set;
+  const double m = mode ? med[s] : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < per_set; i += (int64_t)gridDim.x * 256) {
+    const float q = v[i];
+    const uint32_t key = mode ? __float_as_uint((float)fabs((double)q - m)) : ord_key(q);
+    if ((key & S.known) == S.prefix) atomicAdd(&h[(key >> shift) & dmask], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= (int)dmask; i += 256)
+    if (h[i]) atomicAdd(&hist[(int64_t)s * kHistBins + i], h[i]);
+}
+
+__global__ void k_rs_pick(RsState* st, uint32_t* hist, int shift, int nbits) {
+  const int s = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  RsState S = st[s];
+  uint32_t* h = hist + (int64_t)s * kHistBins;
+  const int nb = 1 << nbits;
+  int64_t acc = 0;
+  int dig = nb - 1;
+  for (int i = 0; i < nb; ++i) {
+    if (acc + (int64_t)h[i] > S.rank) {
+      dig = i;
+      break;
+    }
+    acc += h[i];
+  }
+  S.rank -= acc;
+  S.prefix |= ((uint32_t)dig) << shift;
+  S.known |= ((uint32_t)(nb - 1)) << shift;
+  st[s] = S;
+  for (int i = 0; i < nb; ++i) h[i] = 0;
+}
+
+__global__ void k_rs_init(RsState* st, int nsets, int64_t per_set, int which) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  RsState S;
+  S.prefix = 0;
+  S.known = 0;
+  S.rank = which ? per_set / 2 : (per_set - 1) / 2;
+  st[s] = S;
+}
+
+// value of the selected key: mode 0 -> q, mode 1 -> |q - med| (as float)
+__global__ void k_rs_store(const RsState* st, int nsets, int mode, int which, double* out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  const uint32_t k = st[s].prefix;
+  const double v = mode ? (double)__uint_as_float(k) : (double)ord_val(k);
+  out[2 * s + which] = v;
+}
+
+__global__ void k_rs_finish(const double* lohi_med, const double* lohi_dev, int nsets, double* mu, double* sigma,
+                            uint32_t* flags, int dev_stage) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  if (!dev_stage) {
+    mu[s] = 0.5 * (lohi_med[2 * s] + lohi_med[2 * s + 1]);
+  } else {
+    const double mad = 0.5 * (lohi_dev[2 * s] + lohi_dev[2 * s + 1]);
+    const double sg = 1.482602218505602 * mad;
+    sigma[s] = sg;
+    flags[s] = (sg > 0.0 && isfinite(sg) && isfinite(mu[s])) ? 0u : (uint32_t)FITRIG_FLAG_SIGMA_ZERO;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Selection: segment maxima of a direct value array, flags, deterministic
+// compaction, exact cell recompute, union-find components.
+// ---------------------------------------------------------------------------
+__global__ void k_segmax_direct(const float* vals, SegLayout L, float* seg_max) {
+  const int64_t total = (int64_t)L.nsets * L.Ho * L.nseg_row;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int g = (int)(e % L.nseg_row);
+    const int64_t row = e / L.nseg_row;  // set * Ho + y
+    const int x0 = seg_x0(L, g), w = seg_width(L, g);
+    float m = -INFINITY;
+    const float* v = vals + row * L.Wo;
+    for (int i = 0; i < w; ++i) m = fmaxf(m, v[x0 + i]);
+    seg_max[e] = m;
+  }
+}
+
+__device__ __forceinline__ bool zsel(float q, double mu, double sg, double tau) {
+  return ((double)q - mu) / sg > tau;
+}
+
+struct SegFlag {
+  const float* seg_max;
+  const double* mu;
+  const double* sigma;
+  const uint32_t* flags;
+  double tau;
+  SegLayout L;
+  __device__ bool operator()(int64_t e) const {
+    const int g = (int)(e % L.nseg_row);
+    const int s = (int)(e / ((int64_t)L.Ho * L.nseg_row));
+    if (seg_width(L, g) <= 0 || flags[s]) return false;
+    return zsel(seg_max[e], mu[s], sigma[s], tau);
+  }
+};
+
+struct SegEmit {
+  int32_t* slot_of;  // aliases seg_max
+  int64_t* seg_entry;
+  int64_t cap;
+  __device__ void operator()(int64_t e, bool f, int64_t pos) const {
+    if (f && pos < cap) {
+      seg_entry[pos] = e;
+      slot_of[e] = (int32_t)pos;
+    } else {
+      slot_of[e] = -1;
+    }
+  }
+};
+
+struct RootFlag {
+  const uint64_t* mask;
+  const int32_t* parent;
+  __device__ bool operator()(int64_t slot) const {
+    return ((mask[slot >> 6] >> (slot & 63)) & 1ull) && parent[slot] == (int32_t)slot;
+  }
+};
+
+struct RootEmit {
+  int32_t* comp_of;
+  int32_t* c_root;
+  int64_t cap;
+  __device__ void operator()(int64_t slot, bool f, int64_t pos) const {
+    if (f) {
+      comp_of[slot] = (pos < cap) ? (int32_t)pos : -1;
+      if (pos < cap) c_root[pos] = (int32_t)slot;
+    }
+  }
+};
+
+constexpr int kPerThread = 16;
+constexpr int kChunk = 256 * kPerThread;
+
+__device__ __forceinline__ int64_t dyn_count(int64_t ne_static, const int64_t* ne_dyn, int64_t cap, int mult) {
+  if (!ne_dyn) return ne_static;
+  int64_t n = ne_dyn[0];
+  if (n > cap) n = cap;
+  return n * mult;
+}
+
+template <class F>
+__global__ __launch_bounds__(256) void k_compact_count(F f, int64_t ne_static, const int64_t* ne_dyn, int64_t cap,
+                                                       int mult, uint32_t* cnt) {
+  __shared__ uint32_t sh[256];
+  const int64_t ne = dyn_count(ne_static, ne_dyn, cap, mult);
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  uint32_t c = 0;
+  if (base < ne) {
+    const int64_t a = base + (int64_t)threadIdx.x * kPerThread;
+    for (int j = 0; j < kPerThread; ++j)
+      if (a + j < ne && f(a + j)) ++c;
+  }
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[blockIdx.x] = sh[0];
+}
+
+// Exclusive scan of nchunks counts in place (one workgroup of 1024); total -> out[0].
+__global__ __launch_bounds__(1024) void k_compact_scan(uint32_t* cnt, int64_t nchunks, int64_t* out) {
+  __shared__ int64_t sh[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (nchunks + 1023) / 1024;
+  const int64_t a = t * per, b = min(a + per, nchunks);
+  int64_t loc = 0;
+  for (int64_t i = a; i < b; ++i) loc += cnt[i];
+  sh[t] = loc;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int64_t v = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  int64_t run = sh[t] - loc;
+  for (int64_t i = a; i < b; ++i) {
+    const uint32_t c = cnt[i];
+    cnt[i] = (uint32_t)run;  // offsets fit: callers cap totals below 2^32
+    run += c;
+  }
+  if (t == 1023) out[0] = sh[1023];
+}
+
+template <class F, class E>
+__global__ __launch_bounds__(256) void k_compact_write(F f, E emit, int64_t ne_static, const int64_t* ne_dyn,
+                                                       int64_t cap, int mult, const uint32_t* cnt) {
+  __shared__ uint32_t sh[256];
+  const int64_t ne = dyn_count(ne_static, ne_dyn, cap, mult);
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  if (base >= ne) return;
+  const int64_t a = base + (int64_t)threadIdx.x * kPerThread;
+  uint32_t bits = 0, c = 0;
+  for (int j = 0; j < kPerThread; ++j) {
+    if (a + j < ne && f(a + j)) {
+      bits |= 1u << j;
+      ++c;
+    }
+  }
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  // inclusive scan (Hillis-Steele)
+  for (int off = 1; off < 256; off <<= 1) {
+    uint32_t v = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t pos = (int64_t)cnt[blockIdx.x] + sh[threadIdx.x] - c;
+  for (int j = 0; j < kPerThread; ++j) {
+    if (a + j >= ne) break;
+    const bool fl = (bits >> j) & 1u;
+    emit(a + j, fl, pos);
+    if (fl) ++pos;
+  }
+}
+
+// Exact q of the cells of each selected segment, recomputed with the same
+// arithmetic as k_stream; mask of z > tau.
+template <typename T, int H>
+__global__ __launch_bounds__(64) void k_recompute(const void* base, const void* c0, const void* c1, int ncarry,
+                                                  int64_t plane, int Hh, int Wh, float Cf, int r_signed,
+                                                  SegLayout L, const int64_t* seg_entry, const int64_t* nsel_p,
+                                                  int64_t cap, const double* mu, const double* sigma, double tau,
+                                                  uint64_t* seg_mask, float* cell_q) {
+  constexpr int NV = 8 + 2 * H;
+  __shared__ float sv[3][64 + 32 + 2 * kMaxHalo];
+  const int lane = threadIdx.x;
+  int64_t nsel = nsel_p[0];
+  if (nsel > cap) nsel = cap;
+  for (int64_t i = blockIdx.x; i < nsel; i += gridDim.x) {
+    const int64_t e = seg_entry[i];
+    const int g = (int)(e % L.nseg_row);
+    const int64_t row = e / L.nseg_row;
+    const int y = (int)(row % L.Ho);
+    const int s = (int)(row / L.Ho);
+    const int xs = seg_x0(L, g), wd = seg_width(L, g);
+    const int cmin = 8 * (xs / 8) - H;
+    const int ncols = 8 * ((xs + wd - 1) / 8) + 7 + H - cmin + 1;
+    const int by = 8 * (y / 8);
+    const T* f0 = frame_ptr<T>(base, c0, c1, ncarry, plane, s);
+    const T* f1 = frame_ptr<T>(base, c0, c1, ncarry, plane, s + 1);
+    const T* f2 = frame_ptr<T>(base, c0, c1, ncarry, plane, s + 2);
+    for (int cc = lane; cc < ncols; cc += 64) {
+      const int col = cmin + cc;
+      float dl[NV], rl[NV];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        const int yy = by - H + j;
+        float a = 0.0f, b = 0.0f, c = 0.0f;
+        if (col >= 0 && col < Wh && yy >= 0 && yy < Hh) {
+          const int64_t o = (int64_t)yy * Wh + col;
+          a = to_f<T>(f0[o]);
+          b = to_f<T>(f1[o]);
+          c = to_f<T>(f2[o]);
+        }
+        pix_terms(c - b, b - a, b, Cf, r_signed, dl[j], rl[j]);
+      }
+      float o8[8];
+      Win<H, 8, false>::run(dl, o8, nullptr);
+      sv[0][cc] = o8[y - by];
+      Win<H, 8, true>::run(dl, o8, nullptr);
+      sv[1][cc] = o8[y - by];
+      Win<H, 8, false>::run(rl, o8, nullptr);
+      sv[2][cc] = o8[y - by];
+    }
+    __syncthreads();
+    bool sel = false;
+    float q = 0.0f;
+    if (lane < wd) {
+      const int x = xs + lane;
+      const int bx = 8 * (x / 8);
+      float hs[NV], hm[NV], hr[NV], os[8], om[8], orr[8];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        const int ci = bx - H + j - cmin;
+        hs[j] = sv[0][ci];
+        hm[j] = sv[1][ci];
+        hr[j] = sv[2][ci];
+      }
+      Win<H, 8, false>::run(hs, os, nullptr);
+      Win<H, 8, true>::run(hm, om, nullptr);
+      Win<H, 8, false>::run(hr, orr, nullptr);
+      const int c = x - bx;
+      // same association as k_stream: ((sum * max) * sum_r) * 1/n^2
+      const float inv = inv_count2(y, x, H, Hh, Wh);
+      q = ((os[c] * om[c]) * orr[c]) * inv;
+      sel = zsel(q, mu[s], sigma[s], tau);
+    }
+    const uint64_t m = __ballot(sel);
+    cell_q[i * 64 + lane] = q;
+    if (lane == 0) seg_mask[i] = m;
+    __syncthreads();
+  }
+}
+
+// Cells of each selected segment taken from a value array (tiles / eta).
+__global__ __launch_bounds__(64) void k_fill_direct(const float* vals, SegLayout L, const int64_t* seg_entry,
+                                                    const int64_t* nsel_p, int64_t cap, const double* mu,
+                                                    const double* sigma, double tau, uint64_t* seg_mask,
+                                                    float* cell_q) {
+  const int lane = threadIdx.x;
+  int64_t nsel = nsel_p[0];
+  if (nsel > cap) nsel = cap;
+  for (int64_t i = blockIdx.x; i < nsel; i += gridDim.x) {
+    const int64_t e = seg_entry[i];
+    const int g = (int)(e % L.nseg_row);
+    const int64_t row = e / L.nseg_row;
+    const int s = (int)(row / L.Ho);
+    const int xs = seg_x0(L, g), wd = seg_width(L, g);
+    float q = 0.0f;
+    bool sel = false;
+    if (lane < wd) {
+      q = vals[row * L.Wo + xs + lane];
+      sel = zsel(q, mu[s], sigma[s], tau);
+    }
+    const uint64_t m = __ballot(sel);
+    cell_q[i * 64 + lane] = q;
+    if (lane == 0) seg_mask[i] = m;
+  }
+}
+
+__device__ __forceinline__ int32_t ld_parent(const int32_t* p, int64_t i) {
+  return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ int32_t uf_find(const int32_t* parent, int32_t p) {
+  int32_t q = ld_parent(parent, p);
+  while (q != p) {
+    p = q;
+    q = ld_parent(parent, p);
+  }
+  return p;
+}
+
+// Link the larger root under the smaller one; the surviving root of a
+// component is its lowest slot, i.e. its lowest row-major cell.
+__device__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
+  while (true) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a < b) {
+      const int32_t t = a;
+      a = b;
+      b = t;
+    }
+    const int32_t old = atomicMin(parent + a, b);
+    if (old == a) return;
+    a = old;
+  }
+}
+
+__global__ void k_uf_init(const uint64_t* seg_mask, const int64_t* nsel_p, int64_t cap, int32_t* parent) {
+  int64_t nsel = nsel_p[0];
+  if (nsel > cap) nsel = cap;
+  const int64_t ns = nsel * 64;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x)
+    parent[i] = ((seg_mask[i >> 6] >> (i & 63)) & 1ull) ? (int32_t)i : -1;
+}
+
+__device__ __forceinline__ int32_t slot_at(const int32_t* slot_of, const uint64_t* seg_mask, const SegLayout& L,
+                                           int64_t set, int y, int x) {
+  if (y < 0 || y >= L.Ho || x < 0 || x >= L.Wo) return -1;
+  const int g = seg_of_x(L, x);
+  const int32_t si = slot_of[(set * L.Ho + y) * L.nseg_row + g];
+  if (si < 0) return -1;
+  const int off = x - seg_x0(L, g);
+  if (!((seg_mask[si] >> off) & 1ull)) return -1;
+  return si * 64 + off;
+}
+
+__device__ __forceinline__ void slot_pos(const int64_t* seg_entry, const SegLayout& L, int64_t slot, int64_t& set,
+                                         int& y, int& x) {
+  const int64_t e = seg_entry[slot >> 6];
+  const int g = (int)(e % L.nseg_row);
+  const int64_t row = e / L.nseg_row;
+  y = (int)(row % L.Ho);
+  set = row / L.Ho;
+  x = seg_x0(L, g) + (int)(slot & 63);
+}
+
+__global__ void k_uf_union(const int32_t* slot_of, const uint64_t* seg_mask, const int64_t* seg_entry, SegLayout L,
+                           const int64_t* nsel_p, int64_t cap, int32_t* parent) {
+  int64_t nsel = nsel_p[0];
+  if (nsel > cap) nsel = cap;
+  const int64_t ns = nsel * 64;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!((seg_mask[i >> 6] >> (i & 63)) & 1ull)) continue;
+    int64_t set;
+    int y, x;
+    slot_pos(seg_entry, L, i, set, y, x);
+    const int dy[4] = {0, 1, 1, 1};
+    const int dx[4] = {1, -1, 0, 1};
+    for (int k = 0; k < 4; ++k) {
+      const int32_t nb = slot_at(slot_of, seg_mask, L, set, y + dy[k], x + dx[k]);
+      if (nb >= 0) uf_union(parent, (int32_t)i, nb);
+    }
+  }
+}
+
+__global__ void k_uf_flatten(const int64_t* nsel_p, int64_t cap, int32_t* parent) {
+  int64_t nsel = nsel_p[0];
+  if (nsel > cap) nsel = cap;
+  const int64_t ns = nsel * 64;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = parent[i];
+    if (p >= 0) parent[i] = uf_find(parent, (int32_t)i);
+  }
+}
+
+__global__ void k_comp_init(const int64_t* ncomp_p, int64_t cap, int32_t* npix, unsigned long long* key,
+                            unsigned long long* w, int32_t* box) {
+  int64_t n = ncomp_p[0];
+  if (n > cap) n = cap;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    npix[i] = 0;
+    key[i] = 0ull;
+    for (int j = 0; j < 6; ++j) w[i * 6 + j] = 0ull;
+    box[i * 4 + 0] = INT32_MAX;
+    box[i * 4 + 1] = INT32_MAX;
+    box[i * 4 + 2] = INT32_MIN;
+    box[i * 4 + 3] = INT32_MIN;
+  }
+}
+
+__device__ __forceinline__ void add128(unsigned long long* p, unsigned long long v) {
+  const unsigned long long old = atomicAdd(p, v);
+  if (old + v < old) atomicAdd(p + 1, 1ull);
+}
+
+// Per cell: component statistics with order-independent integer atomics
+// (counts, bounding box, packed argmax key, 128-bit fixed-point z sums).
+__global__ void k_comp_accum(const uint64_t* seg_mask, const int64_t* seg_entry, const float* cell_q, SegLayout L,
+                             const int64_t* nsel_p, int64_t cap, const int32_t* parent, const int32_t* comp_of,
+                             const double* mu, const double* sigma, int32_t* npix, unsigned long long* key,
+                             unsigned long long* w, int32_t* box) {
+  int64_t nsel = nsel_p[0];
+  if (nsel > cap) nsel = cap;
+  const int64_t ns = nsel * 64;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!((seg_mask[i >> 6] >> (i & 63)) & 1ull)) continue;
+    const int32_t c = comp_of[parent[i]];
+    if (c < 0) continue;
+    int64_t set;
+    int y, x;
+    slot_pos(seg_entry, L, i, set, y, x);
+    const float q = cell_q[i];
+    const double z = ((double)q - mu[set]) / sigma[set];
+    atomicAdd(npix + c, 1);
+    const uint32_t lin = (uint32_t)((int64_t)y * L.Wo + x);
+    const unsigned long long k = ((unsigned long long)ord_key(q) << 32) | (unsigned long long)(0xFFFFFFFFu - lin);
+    atomicMax(key + c, k);
+    const unsigned long long wz = (unsigned long long)llround(z * 1048576.0);
+    add128(w + c * 6 + 0, wz);
+    add128(w + c * 6 + 2, wz * (unsigned long long)y);
+    add128(w + c * 6 + 4, wz * (unsigned long long)x);
+    atomicMin(box + c * 4 + 0, y);
+    atomicMin(box + c * 4 + 1, x);
+    atomicMax(box + c * 4 + 2, y);
+    atomicMax(box + c * 4 + 3, x);
+  }
+}
+
+__device__ __forceinline__ double u128_to_d(const unsigned long long* p) {
+  return (double)p[1] * 18446744073709551616.0 + (double)p[0];
+}
+
+__global__ void k_comp_finalize(const int64_t* ncomp_p, int64_t cap, const int32_t* c_root, const int64_t* seg_entry,
+                                SegLayout L, const double* mu, const double* sigma, int branch,
+                                const int32_t* npix, const unsigned long long* key, const unsigned long long* w,
+                                const int32_t* box, int64_t* out_base, fitrig_candidate* out, int64_t out_cap) {
+  int64_t n = ncomp_p[0];
+  if (n > cap) n = cap;
+  const int64_t b0 = out_base[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = b0 + i;
+    if (o >= out_cap) continue;
+    int64_t set;
+    int y, x;
+    slot_pos(seg_entry, L, c_root[i], set, y, x);
+    fitrig_candidate C;
+    C.branch = branch;
+    C.triple = (branch == FITRIG_IMAGE) ? (int32_t)set : -1;
+    C.label = (int64_t)y * L.Wo + x;
+    C.n_pix = npix[i];
+    const unsigned long long k = key[i];
+    const uint32_t lin = 0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull);
+    C.peak_y = (int32_t)(lin / (uint32_t)L.Wo);
+    C.peak_x = (int32_t)(lin % (uint32_t)L.Wo);
+    const float pq = ord_val((uint32_t)(k >> 32));
+    C.peak_q = pq;
+    C.peak_z = (float)(((double)pq - mu[set]) / sigma[set]);
+    C.pad0 = 0;
+    const double sw = u128_to_d(w + i * 6 + 0);
+    C.cy = u128_to_d(w + i * 6 + 2) / sw;
+    C.cx = u128_to_d(w + i * 6 + 4) / sw;
+    C.y0 = box[i * 4 + 0];
+    C.x0 = box[i * 4 + 1];
+    C.y1 = box[i * 4 + 2];
+    C.x1 = box[i * 4 + 3];
+    out[o] = C;
+  }
+}
+
+__global__ void k_advance_base(int64_t* counters) {
+  // counters: [1] components of this run, [3] output base
+  if (threadIdx.x == 0 && blockIdx.x == 0) counters[3] += counters[1];
+}
+
+// ---------------------------------------------------------------------------
+// Image-frequency branch: per tile, DFT over s of the detrended tile series,
+// one-sided magnitudes k = 1..floor(n'/2), h = max or harmonic sum.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t ntiles, int harm, double* eta,
+                                             float* eta_f) {
+  extern __shared__ double tw[];  // [2][np]: cos, sin of 2 pi m / np
+  for (int m = threadIdx.x; m < np; m += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)np, &sn, &cs);
+    tw[m] = cs;
+    tw[np + m] = sn;
+  }
+  __syncthreads();
+  const int K = np / 2;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+    double mean = 0.0;
+    for (int s = 0; s < np; ++s) mean += cube[(int64_t)s * ntiles + t];
+    mean /= (double)np;
+    double best = 0.0;
+    for (int k = 1; k <= K; ++k) {
+      double val = 0.0;
+      const int jmax = harm == 0 ? 1 : harm;
+      for (int j = 1; j <= jmax && j * k <= K; ++j) {
+        const int kk = j * k;
+        double re = 0.0, im = 0.0;
+        int ph = 0;
+        for (int s = 0; s < np; ++s) {
+          const double v = cube[(int64_t)s * ntiles + t] - mean;
+          re = fma(v, tw[ph], re);
+          im = fma(-v, tw[np + ph], im);
+          ph += kk;
+          if (ph >= np) ph -= np;
+        }
+        val += sqrt(re * re + im * im);
+      }
+      if (k == 1 || val > best) best = val;
+    }
+    if (K < 1) best = 0.0;
+    eta[t] = best;
+    if (eta_f) eta_f[t] = (float)best;
+  }
+}
+
+}  // namespace fitrig

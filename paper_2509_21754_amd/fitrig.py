@@ -1,0 +1,250 @@
+"""Python binding of the FITrig C ABI (``include/fitrig.h``).
+
+Argument marshalling only: every step of the path runs in the HIP library
+``libfitrig.so``. The functions named like the C entry points are thin
+wrappers; :class:`Context` adds the torch-tensor convenience layer (device
+memory and streams come from PyTorch, nothing else does).
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+ABI_VERSION = 1
+
+OK, E_INVAL, E_NOMEM, E_HIP, E_TRUNC, E_BUSY, E_NOTREADY = 0, -1, -2, -3, -4, -5, -6
+F32, F16, BF16 = 0, 1, 2
+SLIDING, TILES = 0, 1
+IMAGE, FREQ = 1, 2
+MEAN_STD, MEDIAN_MAD = 0, 1
+MAP_QTILDE, MAP_TLISI = 0, 1
+FLAG_SIGMA_ZERO, FLAG_TRUNC = 1, 2
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfitrig.so")
+
+
+class fitrig_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("window", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
+        ("branches", ctypes.c_int32),
+        ("sigma_est", ctypes.c_int32),
+        ("harm", ctypes.c_int32),
+        ("r_signed", ctypes.c_int32),
+        ("map_kind", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("C", ctypes.c_double),
+        ("max_pixels", ctypes.c_int64),
+        ("max_snap", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("max_segments", ctypes.c_int64),
+    ]
+
+
+class fitrig_candidate(ctypes.Structure):
+    _fields_ = [
+        ("branch", ctypes.c_int32),
+        ("triple", ctypes.c_int32),
+        ("label", ctypes.c_int64),
+        ("n_pix", ctypes.c_int32),
+        ("peak_y", ctypes.c_int32),
+        ("peak_x", ctypes.c_int32),
+        ("peak_z", ctypes.c_float),
+        ("peak_q", ctypes.c_float),
+        ("pad0", ctypes.c_int32),
+        ("cy", ctypes.c_double),
+        ("cx", ctypes.c_double),
+        ("y0", ctypes.c_int32),
+        ("x0", ctypes.c_int32),
+        ("y1", ctypes.c_int32),
+        ("x1", ctypes.c_int32),
+    ]
+
+
+class fitrig_stats(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_double),
+        ("n_triples", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+        ("mu", ctypes.POINTER(ctypes.c_double)),
+        ("sigma", ctypes.POINTER(ctypes.c_double)),
+        ("flags", ctypes.POINTER(ctypes.c_uint32)),
+        ("eta_mu", ctypes.c_double),
+        ("eta_sigma", ctypes.c_double),
+        ("n_image_cand", ctypes.c_int64),
+        ("n_freq_cand", ctypes.c_int64),
+    ]
+
+
+EXPORTS = (
+    "fitrig_config_default",
+    "fitrig_create",
+    "fitrig_detect",
+    "fitrig_destroy",
+    "fitrig_status_string",
+    "fitrig_last_hip_error",
+    "fitrig_abi_version",
+)
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """dlopen the HIP library; raises when it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"FITrig HIP library not built: {path} (run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.fitrig_config_default.argtypes = [ctypes.POINTER(fitrig_config)]
+    L.fitrig_config_default.restype = None
+    L.fitrig_create.argtypes = [ctypes.POINTER(fitrig_config), ctypes.POINTER(vp)]
+    L.fitrig_create.restype = i32
+    L.fitrig_detect.argtypes = [vp, vp, i32, i32, i32, i32, dbl, ctypes.POINTER(fitrig_candidate), i64,
+                                ctypes.POINTER(i64), vp, vp, ctypes.POINTER(fitrig_stats), vp]
+    L.fitrig_detect.restype = i32
+    L.fitrig_destroy.argtypes = [vp]
+    L.fitrig_destroy.restype = i32
+    L.fitrig_status_string.argtypes = [i32]
+    L.fitrig_status_string.restype = ctypes.c_char_p
+    L.fitrig_last_hip_error.argtypes = [vp]
+    L.fitrig_last_hip_error.restype = i32
+    L.fitrig_abi_version.argtypes = []
+    L.fitrig_abi_version.restype = i32
+    _lib = L
+    return L
+
+
+# ---- thin wrappers with the C names -----------------------------------------
+
+def fitrig_config_default(**overrides) -> fitrig_config:
+    cfg = fitrig_config()
+    load().fitrig_config_default(ctypes.byref(cfg))
+    for k, v in overrides.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+def fitrig_create(cfg: fitrig_config) -> tuple[int, Optional[int]]:
+    h = ctypes.c_void_p()
+    rc = load().fitrig_create(ctypes.byref(cfg), ctypes.byref(h))
+    return rc, (h.value if rc == OK else None)
+
+
+def fitrig_detect(ctx, stack_ptr, dtype, n_snap, H, W, sigma, cand, cand_cap, n_cand, index_map, eta_map,
+                  stats, hip_stream) -> int:
+    return load().fitrig_detect(ctx, stack_ptr, dtype, n_snap, H, W, sigma, cand, cand_cap, n_cand, index_map,
+                                eta_map, stats, hip_stream)
+
+
+def fitrig_destroy(ctx) -> int:
+    return load().fitrig_destroy(ctx)
+
+
+def fitrig_status_string(code: int) -> str:
+    return load().fitrig_status_string(code).decode()
+
+
+def fitrig_last_hip_error(ctx) -> int:
+    return load().fitrig_last_hip_error(ctx)
+
+
+def fitrig_abi_version() -> int:
+    return load().fitrig_abi_version()
+
+
+# ---- torch convenience layer --------------------------------------------------
+
+class FitrigError(RuntimeError):
+    def __init__(self, code: int, where: str, hip: int = 0):
+        super().__init__(f"{where}: {fitrig_status_string(code)} ({code}), hip error {hip}")
+        self.code = code
+
+
+def _dtype_code(t) -> int:
+    import torch
+
+    return {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}[t.dtype]
+
+
+def _cand_dict(c: fitrig_candidate) -> dict:
+    return dict(branch=c.branch, triple=c.triple, label=c.label, n_pix=c.n_pix, peak_y=c.peak_y,
+                peak_x=c.peak_x, peak_z=c.peak_z, peak_q=c.peak_q, cy=c.cy, cx=c.cx, y0=c.y0,
+                x0=c.x0, y1=c.y1, x1=c.x1)
+
+
+class Context:
+    """Owns a fitrig_ctx; ``detect`` takes device tensors."""
+
+    def __init__(self, **cfg):
+        self.cfg = fitrig_config_default(**cfg)
+        rc, h = fitrig_create(self.cfg)
+        if rc != OK:
+            raise FitrigError(rc, "fitrig_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fitrig_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def detect(self, stack, sigma: float, *, cand_cap: int = 1 << 16, index_map=None, eta_map=None,
+               stream=None, raise_on_trunc: bool = False):
+        """Run the path on ``stack`` ([n][H][W] device tensor, f32/f16/bf16).
+
+        Returns (candidates (list of dicts), stats (dict), status)."""
+        import torch
+
+        if not stack.is_cuda or not stack.is_contiguous() or stack.dim() != 3:
+            raise ValueError("stack must be a contiguous 3-D device tensor")
+        n, H, W = stack.shape
+        np_ = max(n - 2, 0)
+        cand = (fitrig_candidate * max(cand_cap, 1))()
+        ncand = ctypes.c_int64()
+        mu = (ctypes.c_double * max(np_, 1))()
+        sg = (ctypes.c_double * max(np_, 1))()
+        fl = (ctypes.c_uint32 * max(np_, 1))()
+        st = fitrig_stats()
+        st.mu = ctypes.cast(mu, ctypes.POINTER(ctypes.c_double))
+        st.sigma = ctypes.cast(sg, ctypes.POINTER(ctypes.c_double))
+        st.flags = ctypes.cast(fl, ctypes.POINTER(ctypes.c_uint32))
+        for m in (index_map, eta_map):
+            if m is not None and (not m.is_cuda or m.dtype != torch.float32 or not m.is_contiguous()):
+                raise ValueError("maps must be contiguous float32 device tensors")
+        if stream is None:
+            stream = torch.cuda.current_stream(stack.device)
+        rc = fitrig_detect(self.handle, ctypes.c_void_p(stack.data_ptr()), _dtype_code(stack), n, H, W,
+                           float(sigma), cand, cand_cap, ctypes.byref(ncand),
+                           ctypes.c_void_p(index_map.data_ptr()) if index_map is not None else None,
+                           ctypes.c_void_p(eta_map.data_ptr()) if eta_map is not None else None,
+                           ctypes.byref(st), ctypes.c_void_p(stream.cuda_stream))
+        if rc not in (OK, E_TRUNC) or (rc == E_TRUNC and raise_on_trunc):
+            raise FitrigError(rc, "fitrig_detect", fitrig_last_hip_error(self.handle))
+        k = min(ncand.value, cand_cap)
+        cands = [_cand_dict(cand[i]) for i in range(k)]
+        stats = dict(M=st.M, n_triples=st.n_triples, mu=list(mu[:np_]), sigma=list(sg[:np_]),
+                     flags=list(fl[:np_]), eta_mu=st.eta_mu, eta_sigma=st.eta_sigma,
+                     n_image_cand=st.n_image_cand, n_freq_cand=st.n_freq_cand, n_cand=ncand.value)
+        return cands, stats, rc

@@ -1,0 +1,91 @@
+"""CPU checks of the C-ABI library: it loads, exports every function the
+header declares, its structs have the header's layout, and argument
+validation rejects bad input before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2509_21754_amd import fitrig as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fitrig.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fitrig_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    lib = F.load()
+    names = header_functions()
+    assert "fitrig_detect" in names and "fitrig_create" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", F.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out), n
+    assert set(F.EXPORTS) == set(names)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "probe.c"
+    exe = tmp_path / "probe"
+    fields = {
+        "fitrig_config": [f for f, _ in F.fitrig_config._fields_],
+        "fitrig_candidate": [f for f, _ in F.fitrig_candidate._fields_],
+        "fitrig_stats": [f for f, _ in F.fitrig_stats._fields_],
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fitrig.h"', "int main(void){"]
+    for s, fs in fields.items():
+        lines.append(f'printf("{s} size %zu\\n", sizeof({s}));')
+        for f in fs:
+            lines.append(f'printf("{s} {f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for s, cls in (("fitrig_config", F.fitrig_config), ("fitrig_candidate", F.fitrig_candidate),
+                   ("fitrig_stats", F.fitrig_stats)):
+        assert got[(s, "size")] == ctypes.sizeof(cls), s
+        for f, _ in cls._fields_:
+            assert got[(s, f)] == getattr(cls, f).offset, (s, f)
+
+
+def test_status_strings_and_version():
+    assert F.fitrig_abi_version() == F.ABI_VERSION
+    assert F.fitrig_status_string(F.OK) == "ok"
+    for code in (F.E_INVAL, F.E_NOMEM, F.E_HIP, F.E_TRUNC, F.E_BUSY, F.E_NOTREADY):
+        assert F.fitrig_status_string(code) not in ("ok", "unknown status")
+    assert F.fitrig_status_string(-99) == "unknown status"
+
+
+def test_defaults():
+    c = F.fitrig_config_default()
+    assert (c.abi_version, c.mode, c.window, c.tile, c.branches, c.sigma_est, c.harm, c.r_signed,
+            c.map_kind, c.C) == (1, F.SLIDING, 7, 32, F.IMAGE | F.FREQ, F.MEAN_STD, 0, 0, F.MAP_QTILDE, 1e-6)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(abi_version=2), dict(mode=2), dict(window=4), dict(window=0), dict(window=19), dict(tile=0),
+    dict(branches=0), dict(branches=4), dict(sigma_est=2), dict(harm=1), dict(harm=-1), dict(r_signed=2),
+    dict(map_kind=3), dict(C=0.0), dict(C=-1.0), dict(C=float("nan")), dict(max_pixels=-1),
+])
+def test_create_rejects_bad_config(bad):
+    rc, h = F.fitrig_create(F.fitrig_config_default(**bad))
+    assert rc == F.E_INVAL and h is None
+
+
+def test_detect_rejects_null_context():
+    n = ctypes.c_int64(5)
+    rc = F.fitrig_detect(None, ctypes.c_void_p(1), F.F32, 4, 8, 8, 6.0, None, 0, ctypes.byref(n), None, None,
+                         None, None)
+    assert rc == F.E_INVAL
+    assert F.fitrig_destroy(None) == F.E_INVAL

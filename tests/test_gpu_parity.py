@@ -1,0 +1,230 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle
+on the same seeded inputs, at sizes that span several workgroup tiles and
+ragged tails, plus edge cases and determinism."""
+import numpy as np
+import pytest
+
+from oracle import ref
+from parity import (check_candidates, check_eta, check_maps, check_stats, structured_stack)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DT = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+
+
+def _ctx(**cfg):
+    from paper_2509_21754_amd import Context
+
+    return Context(**cfg)
+
+
+def run_gpu(X, tau, dtype="f32", with_maps=True, cand_cap=1 << 16, **cfg):
+    """X: float32/float64 numpy stack -> (cands, stats, qmap, eta, stack used)."""
+    t = torch.from_numpy(np.ascontiguousarray(X)).to(DT[dtype]).cuda()
+    n, H, W = t.shape
+    mode = cfg.get("mode", 0)
+    tile = cfg.get("tile", 32)
+    if mode == 0:
+        qshape = (n - 2, H, W)
+    else:
+        qshape = (n - 2, -(-H // tile), -(-W // tile))
+    qmap = torch.full(qshape, float("nan"), device="cuda") if with_maps else None
+    eta = torch.full((-(-H // tile), -(-W // tile)), float("nan"), device="cuda") if with_maps else None
+    with _ctx(**cfg) as ctx:
+        cands, stats, rc = ctx.detect(t, tau, index_map=qmap, eta_map=eta, cand_cap=cand_cap)
+    torch.cuda.synchronize()
+    used = t.float().cpu().numpy()
+    return cands, stats, (qmap.cpu().numpy() if with_maps else None), (eta.cpu().numpy() if with_maps else None), used, rc
+
+
+SMALL = [
+    # (H, W, n, window, dtype, seed)
+    (37, 530, 5, 7, "f32", 1),
+    (70, 249, 6, 9, "f32", 2),
+    (16, 16, 3, 1, "f32", 3),
+    (5, 7, 4, 3, "f32", 4),
+    (33, 300, 7, 5, "f16", 5),
+    (48, 260, 8, 17, "bf16", 6),
+    (90, 760, 4, 11, "f32", 7),
+    (1, 600, 4, 7, "f32", 8),
+    (600, 1, 4, 7, "f32", 9),
+    (1, 1, 3, 1, "f32", 10),
+    (129, 497, 6, 15, "f32", 11),
+    (64, 512, 5, 3, "f32", 12),
+]
+
+
+@pytest.mark.parametrize("H,W,n,w,dt,seed", SMALL)
+def test_sliding_parity_small(H, W, n, w, dt, seed):
+    X = structured_stack(seed, n, H, W)
+    tau = 3.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, dt, window=w, branches=1)
+    assert rc == 0
+    out = ref.detect(used, tau=tau, window=w, branches=ref.IMAGE)
+    check_maps(q, out["q"])
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"], out["flags"])
+    assert [int(f) for f in stats["flags"]] == out["flags"]
+    check_candidates(cands, out, tau)
+    assert stats["M"] == pytest.approx(ref.normaliser(used), rel=0, abs=0)
+
+
+@pytest.mark.parametrize("zeros", [False, True])
+def test_both_branches_parity(zeros):
+    X = structured_stack(21, 14, 150, 700, zeros=zeros)
+    for k in range(2, 14, 4):
+        X[k, 60:67, 300:307] += 30.0
+    tau = 4.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, window=7)
+    assert rc == 0
+    out = ref.detect(used, tau=tau, window=7)
+    check_maps(q, out["q"])
+    check_eta(eta, out["eta"])
+    assert stats["eta_mu"] == pytest.approx(out["eta_mu"], rel=1e-6)
+    assert stats["eta_sigma"] == pytest.approx(out["eta_sigma"], rel=1e-6)
+    n = check_candidates(cands, out, tau)
+    assert n > 0
+    assert any(c["branch"] == ref.FREQ for c in cands)
+
+
+def test_workload_c0():
+    import synth
+
+    spec = synth.WORKLOADS["c0"]
+    X = synth.make_stack(spec).numpy()
+    cands, stats, q, eta, used, rc = run_gpu(X, 6.0, window=7)
+    out = ref.detect(used, tau=6.0, window=7)
+    check_maps(q, out["q"])
+    check_eta(eta, out["eta"])
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"])
+    check_candidates(cands, out, 6.0)
+
+
+@pytest.mark.parametrize("tau", [5.0, 6.0, 7.0])
+def test_workload_c1_crop(tau):
+    import synth
+
+    spec = synth.spec("c1", H=384, W=800, n=64)
+    X = synth.make_stack(spec).numpy()
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, window=7)
+    out = ref.detect(used, tau=tau, window=7)
+    check_maps(q, out["q"])
+    check_eta(eta, out["eta"])
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"])
+    check_candidates(cands, out, tau)
+
+
+@pytest.mark.parametrize("tile,H,W,n", [(32, 100, 300, 8), (5, 37, 53, 6), (1, 9, 11, 4), (64, 70, 300, 6),
+                                        (7, 64, 512, 5)])
+def test_tile_mode_parity(tile, H, W, n):
+    X = structured_stack(30 + tile, n, H, W)
+    tau = 2.5
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, mode=1, tile=tile)
+    out = ref.detect(used, tau=tau, mode=ref.TILES, tile=tile)
+    check_maps(q, out["q"])
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"], out["flags"])
+    check_candidates(cands, out, tau)
+    if out["eta"] is not None:
+        check_eta(eta, out["eta"])
+
+
+def test_median_mad_parity():
+    X = structured_stack(41, 9, 80, 520)
+    tau = 5.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, window=5, sigma_est=1)
+    out = ref.detect(used, tau=tau, window=5, sigma_est=ref.MEDIAN_MAD)
+    check_maps(q, out["q"])
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"])
+    check_candidates(cands, out, tau)
+
+
+def test_median_mad_tiles_and_freq():
+    X = structured_stack(42, 12, 96, 320)
+    tau = 3.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, mode=1, tile=8, sigma_est=1)
+    out = ref.detect(used, tau=tau, mode=ref.TILES, tile=8, sigma_est=ref.MEDIAN_MAD)
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"])
+    assert stats["eta_mu"] == pytest.approx(out["eta_mu"], rel=1e-6)
+    assert stats["eta_sigma"] == pytest.approx(out["eta_sigma"], rel=1e-6)
+    check_candidates(cands, out, tau)
+
+
+@pytest.mark.parametrize("harm", [0, 3])
+def test_freq_branch_only(harm):
+    X = structured_stack(51, 34, 64, 300)
+    for k in range(1, 34, 5):
+        X[k, 20:27, 100:107] += 9.0
+    tau = 3.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, branches=2, harm=harm, tile=16)
+    out = ref.detect(used, tau=tau, branches=ref.FREQ, harm=harm, tile=16)
+    check_eta(eta, out["eta"])
+    check_candidates(cands, out, tau)
+    assert all(c["branch"] == ref.FREQ and c["triple"] == -1 for c in cands)
+
+
+def test_r_signed_reading():
+    X = structured_stack(61, 6, 40, 280)
+    X -= 1.0
+    tau = 3.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, window=5, r_signed=1, branches=1)
+    out = ref.detect(used, tau=tau, window=5, r_signed=True, branches=ref.IMAGE)
+    check_maps(q, out["q"])
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"])
+    check_candidates(cands, out, tau)
+
+
+def test_tlisi_map_kind():
+    X = structured_stack(71, 5, 30, 270)
+    t = torch.from_numpy(X).cuda()
+    qmap = torch.empty((3, 30, 270), device="cuda")
+    with _ctx(window=3, map_kind=1, branches=1) as ctx:
+        cands, stats, rc = ctx.detect(t, 4.0, index_map=qmap)
+    q = ref.index_maps(X, window=3)
+    M = ref.normaliser(X)
+    np.testing.assert_allclose(qmap.cpu().numpy(), 1 - q / M**2, rtol=0, atol=2e-7)
+
+
+def test_determinism_bitwise():
+    X = structured_stack(81, 10, 120, 600)
+    r1 = run_gpu(X, 3.0, window=9)
+    r2 = run_gpu(X, 3.0, window=9)
+    assert r1[0] == r2[0]
+    assert np.array_equal(r1[2], r2[2]) and np.array_equal(r1[3], r2[3], equal_nan=True)
+    assert r1[1]["mu"] == r2[1]["mu"] and r1[1]["sigma"] == r2[1]["sigma"]
+
+
+def test_identical_frames_give_nothing():
+    f = np.random.default_rng(3).normal(size=(50, 300)).astype(np.float32) * 5 + 100
+    X = np.stack([f] * 7)
+    cands, stats, q, eta, used, rc = run_gpu(X, 3.0, window=5)
+    assert cands == [] and rc == 0
+    assert np.all(q == 0.0)
+    assert all(fl & 1 for fl in stats["flags"])
+
+
+def test_power_of_two_scaling_bitwise():
+    X = structured_stack(91, 6, 64, 300).astype(np.float32)
+    a = np.float32(4.0)
+    r1 = run_gpu(X, 3.0, window=7, branches=1, C=1e-6)
+    r2 = run_gpu(X * a, 3.0, window=7, branches=1, C=4e-6)
+    assert np.array_equal(r2[2], r1[2] * np.float32(16.0))
+    k1 = [(c["triple"], c["label"], c["n_pix"], c["peak_y"], c["peak_x"]) for c in r1[0]]
+    k2 = [(c["triple"], c["label"], c["n_pix"], c["peak_y"], c["peak_x"]) for c in r2[0]]
+    assert k1 == k2
+
+
+def test_candidate_capacity_truncation():
+    X = structured_stack(101, 8, 100, 500)
+    full = run_gpu(X, 2.0, window=5, branches=1)
+    assert len(full[0]) > 5
+    part = run_gpu(X, 2.0, window=5, branches=1, cand_cap=3)
+    assert part[5] == -4
+    assert part[1]["n_cand"] == len(full[0])
+    assert part[0] == full[0][:3]
+
+
+def test_internal_capacity_flag():
+    X = structured_stack(102, 8, 100, 500)
+    cands, stats, q, eta, used, rc = run_gpu(X, 1.0, window=5, branches=1, max_segments=4)
+    assert rc == -4
+    assert all(f & 2 for f in stats["flags"])
