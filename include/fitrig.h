@@ -78,7 +78,7 @@ typedef struct {
   double C;             /* the constant of Eqs. (2), (5); > 0 (default 1e-6) */
   int64_t max_pixels;   /* capacity hint H*W used to size scratch at create (0 = grow on demand) */
   int32_t max_snap;     /* capacity hint n_snap (0 = grow on demand) */
-  int32_t reserved;
+  int32_t profile;      /* 1: time each phase of fitrig_detect with HIP events (see fitrig_phase_times) */
   int64_t max_segments; /* selection capacity in 64-cell row segments (0 = automatic) */
 } fitrig_config;
 
@@ -159,6 +159,20 @@ const char* fitrig_status_string(fitrig_status s);
 
 /* The last HIP error code seen by the context (0 = none). */
 int32_t fitrig_last_hip_error(const fitrig_ctx* ctx);
+
+/*
+ * Phase durations of the last fitrig_detect on ctx, in milliseconds, measured
+ * with HIP events recorded on the call's stream (config profile = 1):
+ *   [0] pass over the stack (streaming index kernel or tile kernel)
+ *   [1] per-triple spread
+ *   [2] image-branch selection and components
+ *   [3] frequency branch
+ *   [4] result copies to the host
+ * Writes min(cap, FITRIG_N_PHASES) values; returns the number written, or
+ * 0 when profiling is off or no call has completed, -1 on a null pointer.
+ */
+#define FITRIG_N_PHASES 5
+int32_t fitrig_phase_times(const fitrig_ctx* ctx, double* ms, int32_t cap);
 
 /* Library ABI version (FITRIG_ABI_VERSION of the build). */
 int32_t fitrig_abi_version(void);

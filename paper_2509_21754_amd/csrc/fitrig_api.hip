@@ -49,12 +49,15 @@ struct fitrig_ctx {
   fitrig_config cfg;
   hipStream_t stream = nullptr;
   int32_t last_hip = 0;
-  DevBuf stat_part, seg_max, seg_max2, tile_part, wg_max, tile_wgmax, cube, cube_f, eta_d, eta_f, mu, sigma, flags, eta_st, M, qscratch;
-  DevBuf hist, rs_state, rs_med, rs_dev, chunk_cnt, counters;
+  DevBuf stat_part, seg_max, seg_max2, tile_part, cube, cube_f, eta_d, eta_f, mu, sigma, flags, eta_st, M, qscratch;
+  DevBuf hist, rs_state, rs_med, rs_dev, chunk_cnt, counters, mom_tmp, max_key;
   DevBuf seg_entry, seg_mask, cell_q, parent, comp_of, c_root, c_npix, c_key, c_w, c_box, c_out;
   int64_t seg_cap = 0, comp_cap = 0;
   void* h_stage = nullptr;
   size_t h_stage_cap = 0;
+  hipEvent_t ev[FITRIG_N_PHASES + 1] = {};
+  double phase_ms[FITRIG_N_PHASES] = {};
+  int32_t have_times = 0;
 };
 
 namespace {
@@ -99,11 +102,11 @@ fitrig_status ensure_host(fitrig_ctx* ctx, size_t bytes) {
   return FITRIG_OK;
 }
 
-template <typename T>
+template <typename T, bool RS>
 void launch_stream(int H, dim3 grid, hipStream_t st, const StreamArgs& A) {
   switch (H) {
 #define CASE(h) \
-  case h: hipLaunchKernelGGL((k_stream<T, h>), grid, dim3(kLanes), 0, st, A); break;
+  case h: hipLaunchKernelGGL((k_stream<T, h, RS>), grid, dim3(kLanes), 0, st, A); break;
     CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: break;
@@ -121,15 +124,15 @@ struct RecomputeArgs {
   int r_signed;
 };
 
-template <typename T>
+template <typename T, bool RS>
 void launch_recompute(int halo, dim3 grid, hipStream_t st, const RecomputeArgs& R, const SegLayout& L,
                       const int64_t* seg_entry, const int64_t* nsel, int64_t cap, const double* mu,
                       const double* sigma, double tau, uint64_t* mask, float* cq) {
   switch (halo) {
 #define CASE(h)                                                                                          \
   case h:                                                                                                \
-    hipLaunchKernelGGL((k_recompute<T, h>), grid, dim3(64), 0, st, R.base, R.c0, R.c1, R.ncarry, R.plane, \
-                       R.H, R.W, R.Cf, R.r_signed, L, seg_entry, nsel, cap, mu, sigma, tau, mask, cq);  \
+    hipLaunchKernelGGL((k_recompute<T, h, RS>), grid, dim3(64), 0, st, R.base, R.c0, R.c1, R.ncarry, R.plane, \
+                       R.H, R.W, R.Cf, L, seg_entry, nsel, cap, mu, sigma, tau, mask, cq);               \
     break;
     CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -165,7 +168,7 @@ __global__ void k_run_done(int64_t* c, int64_t seg_cap, int64_t comp_cap, int br
   c[CNT_OUTBASE] += nc;
 }
 template <typename T>
-__global__ void k_stack_max(const T* p, int64_t n, float* wg_max) {
+__global__ void k_stack_max(const T* p, int64_t n, uint32_t* max_key) {
   __shared__ float sh[256];
   float m = -INFINITY;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -176,7 +179,7 @@ __global__ void k_stack_max(const T* p, int64_t n, float* wg_max) {
     if (threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) wg_max[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) atomicMax(max_key, ord_key(sh[0]));
 }
 
 struct Call {
@@ -188,6 +191,19 @@ struct Call {
   float* eta_map;
   hipStream_t st;
 };
+
+// Mean / population std per set, two fixed-order stages.
+fitrig_status moments(fitrig_ctx* ctx, hipStream_t st, const double* src, int nsets, int64_t nparts, int raw,
+                      int64_t count, double* mu, double* sigma, uint32_t* flags) {
+  const int G = (int)std::min<int64_t>(64, std::max<int64_t>(1, nparts / 4096));
+  fitrig_status rc;
+  if ((rc = ensure(ctx, ctx->mom_tmp, (size_t)nsets * G * 16)) != FITRIG_OK) return rc;
+  hipLaunchKernelGGL(k_moments_part, dim3(G, nsets), dim3(256), 0, st, src, nparts, raw, (double*)ctx->mom_tmp.p);
+  hipLaunchKernelGGL(k_moments, dim3(nsets), dim3(256), 0, st, (const double*)ctx->mom_tmp.p, (int64_t)G, 0, count,
+                     mu, sigma, flags);
+  LAUNCH_CHECK(ctx);
+  return FITRIG_OK;
+}
 
 // Spread by exact median / MAD of a float array [nsets][per_set].
 fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, int nsets, int64_t per_set,
@@ -266,20 +282,15 @@ fitrig_status select_run(fitrig_ctx* ctx, const Call& c, const SegLayout& L, flo
   } else {
     RecomputeArgs R{c.stack, nullptr, nullptr, 0, (int64_t)c.H * c.W, c.H, c.W, (float)ctx->cfg.C,
                     ctx->cfg.r_signed};
+#define RC(T, RS) \
+  launch_recompute<T, RS>(halo, dim3(gsel), st, R, L, seg_entry, cnt + CNT_NSEL, cap, mu, sigma, c.tau, mask, cq)
+    const bool rs = ctx->cfg.r_signed != 0;
     switch (c.dtype) {
-      case FITRIG_F32:
-        launch_recompute<float>(halo, dim3(gsel), st, R, L, seg_entry, cnt + CNT_NSEL, cap, mu, sigma, c.tau, mask,
-                                cq);
-        break;
-      case FITRIG_F16:
-        launch_recompute<__half>(halo, dim3(gsel), st, R, L, seg_entry, cnt + CNT_NSEL, cap, mu, sigma, c.tau, mask,
-                                 cq);
-        break;
-      default:
-        launch_recompute<bf16_t>(halo, dim3(gsel), st, R, L, seg_entry, cnt + CNT_NSEL, cap, mu, sigma, c.tau, mask,
-                                 cq);
-        break;
+      case FITRIG_F32: rs ? RC(float, true) : RC(float, false); break;
+      case FITRIG_F16: rs ? RC(__half, true) : RC(__half, false); break;
+      default: rs ? RC(bf16_t, true) : RC(bf16_t, false); break;
     }
+#undef RC
   }
   LAUNCH_CHECK(ctx);
   const int gcell = grid_for(cap * 64, 256, 4096);
@@ -352,8 +363,11 @@ fitrig_status run_tile_kernel(fitrig_ctx* ctx, const Call& c, int tile, int Ty, 
   A.r_signed = ctx->cfg.r_signed;
   A.Cf = (float)ctx->cfg.C;
   A.tile_part = (double*)ctx->tile_part.p;
-  A.wg_max = (float*)ctx->tile_wgmax.p;
-  hipLaunchKernelGGL((k_tile<T>), dim3(nchunk, Ty, c.n - 2), dim3(kLanes), 0, c.st, A);
+  A.max_key = (uint32_t*)ctx->max_key.p;
+  if (A.r_signed)
+    hipLaunchKernelGGL((k_tile<T, true>), dim3(nchunk, Ty, c.n - 2), dim3(kLanes), 0, c.st, A);
+  else
+    hipLaunchKernelGGL((k_tile<T, false>), dim3(nchunk, Ty, c.n - 2), dim3(kLanes), 0, c.st, A);
   LAUNCH_CHECK(ctx);
   return FITRIG_OK;
 }
@@ -378,8 +392,17 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   if ((rc = ensure(ctx, ctx->flags, (size_t)np * 4)) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->eta_st, 32)) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->M, 8)) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->max_key, 64)) != FITRIG_OK) return rc;
   int64_t* cnt = (int64_t*)ctx->counters.p;
   hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, cnt, (int64_t)CNT_N, (int64_t)0);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)ctx->max_key.p, (int64_t)1, 0u);
+  const bool prof = cfg.profile != 0;
+  ctx->have_times = 0;
+  auto mark = [&](int i) -> fitrig_status {
+    if (prof) HIP_TRY(ctx, hipEventRecord(ctx->ev[i], st));
+    return FITRIG_OK;
+  };
+  if ((rc = mark(0)) != FITRIG_OK) return rc;
   double* mu = (double*)ctx->mu.p;
   double* sigma = (double*)ctx->sigma.p;
   uint32_t* flags = (uint32_t*)ctx->flags.p;
@@ -389,8 +412,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
 
   // ---- pass over the stack -------------------------------------------------
   bool have_cube = false;
-  int64_t nwg_max = 0;
-  const float* max_src = nullptr;
+  bool have_max = false;
   const int out_w = out_width(halo);
   const int ncol = (c.W + out_w - 1) / out_w;
   const int nbands = (c.H + kBand - 1) / kBand;
@@ -402,9 +424,8 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     const int64_t nwg = (int64_t)ncol * nbands;
     if (nwg > INT32_MAX) return FITRIG_E_INVAL;
     const bool byprod = freq && tile == 32;
-    if ((rc = ensure(ctx, ctx->stat_part, (size_t)np * nwg * 16)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->stat_part, (size_t)np * nwg * 16 * 16)) != FITRIG_OK) return rc;
     if ((rc = ensure(ctx, ctx->seg_max, (size_t)np * c.H * nseg_row * 4)) != FITRIG_OK) return rc;
-    if ((rc = ensure(ctx, ctx->wg_max, (size_t)nwg * 4)) != FITRIG_OK) return rc;
     if (byprod && (rc = ensure(ctx, ctx->tile_part, (size_t)np * nbands * ncol * kPieces * 3 * 8)) != FITRIG_OK)
       return rc;
     qmap = c.index_map;
@@ -429,15 +450,19 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     A.stat_part = (double*)ctx->stat_part.p;
     A.seg_max = (float*)ctx->seg_max.p;
     A.tile_part = byprod ? (double*)ctx->tile_part.p : nullptr;
-    A.wg_max = (float*)ctx->wg_max.p;
+    A.max_key = (uint32_t*)ctx->max_key.p;
+    const bool rs = cfg.r_signed != 0;
     switch (c.dtype) {
-      case FITRIG_F32: launch_stream<float>(halo, dim3((unsigned)nwg), st, A); break;
-      case FITRIG_F16: launch_stream<__half>(halo, dim3((unsigned)nwg), st, A); break;
-      default: launch_stream<bf16_t>(halo, dim3((unsigned)nwg), st, A); break;
+      case FITRIG_F32: rs ? launch_stream<float, true>(halo, dim3((unsigned)nwg), st, A)
+                          : launch_stream<float, false>(halo, dim3((unsigned)nwg), st, A); break;
+      case FITRIG_F16: rs ? launch_stream<__half, true>(halo, dim3((unsigned)nwg), st, A)
+                          : launch_stream<__half, false>(halo, dim3((unsigned)nwg), st, A); break;
+      default: rs ? launch_stream<bf16_t, true>(halo, dim3((unsigned)nwg), st, A)
+                  : launch_stream<bf16_t, false>(halo, dim3((unsigned)nwg), st, A); break;
     }
     LAUNCH_CHECK(ctx);
-    nwg_max = nwg;
-    max_src = (const float*)ctx->wg_max.p;
+    have_max = true;
+    if ((rc = mark(1)) != FITRIG_OK) return rc;
     if (byprod) {
       if ((rc = ensure(ctx, ctx->cube, (size_t)np * Ty * Tx * 8)) != FITRIG_OK) return rc;
       if ((rc = ensure(ctx, ctx->cube_f, (size_t)np * Ty * Tx * 4)) != FITRIG_OK) return rc;
@@ -449,9 +474,9 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     }
     // per-triple spread
     if (!robust) {
-      hipLaunchKernelGGL(k_moments, dim3(np), dim3(256), 0, st, (const double*)ctx->stat_part.p, nwg, 0, plane, mu,
-                         sigma, flags);
-      LAUNCH_CHECK(ctx);
+      if ((rc = moments(ctx, st, (const double*)ctx->stat_part.p, np, nwg * 16, 0, plane, mu, sigma, flags)) !=
+          FITRIG_OK)
+        return rc;
     } else {
       if ((rc = robust_spread(ctx, st, qmap, np, plane, mu, sigma, flags)) != FITRIG_OK) return rc;
     }
@@ -462,7 +487,6 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     const int pieces = (kLanes + tile - 1) / tile + 1;
     if ((rc = ensure(ctx, ctx->tile_part, (size_t)np * Ty * nchunk * pieces * 3 * 8)) != FITRIG_OK) return rc;
     const int64_t nwg = (int64_t)np * Ty * nchunk;
-    if ((rc = ensure(ctx, ctx->tile_wgmax, (size_t)nwg * 4)) != FITRIG_OK) return rc;
     if ((rc = ensure(ctx, ctx->cube, (size_t)np * Ty * Tx * 8)) != FITRIG_OK) return rc;
     if ((rc = ensure(ctx, ctx->cube_f, (size_t)np * Ty * Tx * 4)) != FITRIG_OK) return rc;
     switch (c.dtype) {
@@ -470,9 +494,9 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
       case FITRIG_F16: rc = run_tile_kernel<__half>(ctx, c, tile, Ty, nchunk, pieces); break;
       default: rc = run_tile_kernel<bf16_t>(ctx, c, tile, Ty, nchunk, pieces); break;
     }
-    if (nwg_max == 0) {
-      max_src = (const float*)ctx->tile_wgmax.p;
-      nwg_max = nwg;
+    if (!have_max) {
+      have_max = true;
+      if ((rc = mark(1)) != FITRIG_OK) return rc;
     }
     if (rc != FITRIG_OK) return rc;
     hipLaunchKernelGGL(k_tile_merge, dim3(grid_for((int64_t)np * Ty * Tx)), dim3(256), 0, st,
@@ -481,30 +505,30 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     LAUNCH_CHECK(ctx);
     have_cube = true;
   }
-  if (nwg_max == 0) {
+  if (!have_max) {
     // no pass produced the maximum (e.g. frequency branch only, n' < 4)
     const int g = 1024;
-    if ((rc = ensure(ctx, ctx->wg_max, g * 4)) != FITRIG_OK) return rc;
+    uint32_t* mk = (uint32_t*)ctx->max_key.p;
     switch (c.dtype) {
       case FITRIG_F32:
         hipLaunchKernelGGL(k_stack_max<float>, dim3(g), dim3(256), 0, st, (const float*)c.stack, (int64_t)c.n * plane,
-                           (float*)ctx->wg_max.p);
+                           mk);
         break;
       case FITRIG_F16:
         hipLaunchKernelGGL(k_stack_max<__half>, dim3(g), dim3(256), 0, st, (const __half*)c.stack,
-                           (int64_t)c.n * plane, (float*)ctx->wg_max.p);
+                           (int64_t)c.n * plane, mk);
         break;
       default:
         hipLaunchKernelGGL(k_stack_max<bf16_t>, dim3(g), dim3(256), 0, st, (const bf16_t*)c.stack,
-                           (int64_t)c.n * plane, (float*)ctx->wg_max.p);
+                           (int64_t)c.n * plane, mk);
         break;
     }
-    nwg_max = g;
-    max_src = (const float*)ctx->wg_max.p;
+    if ((rc = mark(1)) != FITRIG_OK) return rc;
   }
-  hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(256), 0, st, max_src, nwg_max, cfg.C,
+  hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(64), 0, st, (const uint32_t*)ctx->max_key.p, cfg.C,
                      (double*)ctx->M.p);
   LAUNCH_CHECK(ctx);
+  if ((rc = mark(2)) != FITRIG_OK) return rc;
 
   // ---- image-branch selection ---------------------------------------------
   if (img) {
@@ -517,9 +541,8 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     } else {
       const int64_t ncell = (int64_t)Ty * Tx;
       if (!robust) {
-        hipLaunchKernelGGL(k_moments, dim3(np), dim3(256), 0, st, (const double*)ctx->cube.p, ncell, 1, ncell, mu,
-                           sigma, flags);
-        LAUNCH_CHECK(ctx);
+        if ((rc = moments(ctx, st, (const double*)ctx->cube.p, np, ncell, 1, ncell, mu, sigma, flags)) != FITRIG_OK)
+          return rc;
       } else {
         if ((rc = robust_spread(ctx, st, (const float*)ctx->cube_f.p, np, ncell, mu, sigma, flags)) != FITRIG_OK)
           return rc;
@@ -537,6 +560,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     }
   }
 
+  if ((rc = mark(3)) != FITRIG_OK) return rc;
   // ---- frequency branch ----------------------------------------------------
   if (freq) {
     const int64_t ntiles = (int64_t)Ty * Tx;
@@ -547,9 +571,9 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
                        (float*)ctx->eta_f.p);
     LAUNCH_CHECK(ctx);
     if (!robust) {
-      hipLaunchKernelGGL(k_moments, dim3(1), dim3(256), 0, st, (const double*)ctx->eta_d.p, ntiles, 1, ntiles, eta_mu,
-                         eta_sig, eta_flag);
-      LAUNCH_CHECK(ctx);
+      if ((rc = moments(ctx, st, (const double*)ctx->eta_d.p, 1, ntiles, 1, ntiles, eta_mu, eta_sig, eta_flag)) !=
+          FITRIG_OK)
+        return rc;
     } else {
       if ((rc = robust_spread(ctx, st, (const float*)ctx->eta_f.p, 1, ntiles, eta_mu, eta_sig, eta_flag)) != FITRIG_OK)
         return rc;
@@ -574,6 +598,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     LAUNCH_CHECK(ctx);
   }
 
+  if ((rc = mark(4)) != FITRIG_OK) return rc;
   // ---- results to the host --------------------------------------------------
   const size_t small = CNT_N * 8 + 8 + 32 + (size_t)np * (8 + 8 + 4);
   if ((rc = ensure_host(ctx, small)) != FITRIG_OK) return rc;
@@ -596,7 +621,16 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     HIP_TRY(ctx, hipMemcpyAsync(h_sig, sigma, (size_t)np * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipMemcpyAsync(h_fl, flags, (size_t)np * 4, hipMemcpyDeviceToHost, st));
   }
+  if ((rc = mark(5)) != FITRIG_OK) return rc;
   HIP_TRY(ctx, hipStreamSynchronize(st));
+  if (prof) {
+    for (int i = 0; i < FITRIG_N_PHASES; ++i) {
+      float ms = 0.0f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+      ctx->phase_ms[i] = ms;
+    }
+    ctx->have_times = 1;
+  }
   const int64_t total = h_cnt[CNT_OUTBASE];
   const bool trunc_internal = h_cnt[CNT_TRUNC] != 0;
   const int64_t ncopy = std::min<int64_t>(total, cand_cap);
@@ -636,6 +670,7 @@ fitrig_status validate_cfg(const fitrig_config* c) {
   if (c->map_kind != FITRIG_MAP_QTILDE && c->map_kind != FITRIG_MAP_TLISI) return FITRIG_E_INVAL;
   if (!(c->C > 0.0) || !isfinite(c->C)) return FITRIG_E_INVAL;
   if (c->max_pixels < 0 || c->max_snap < 0 || c->max_segments < 0) return FITRIG_E_INVAL;
+  if (c->profile != 0 && c->profile != 1) return FITRIG_E_INVAL;
   return FITRIG_OK;
 }
 
@@ -660,6 +695,14 @@ void fitrig_config_default(fitrig_config* cfg) {
 }
 
 int32_t fitrig_abi_version(void) { return FITRIG_ABI_VERSION; }
+
+int32_t fitrig_phase_times(const fitrig_ctx* ctx, double* ms, int32_t cap) {
+  if (!ctx || !ms) return -1;
+  if (!ctx->have_times) return 0;
+  const int32_t n = cap < FITRIG_N_PHASES ? cap : FITRIG_N_PHASES;
+  for (int32_t i = 0; i < n; ++i) ms[i] = ctx->phase_ms[i];
+  return n < 0 ? 0 : n;
+}
 
 const char* fitrig_status_string(fitrig_status s) {
   switch (s) {
@@ -688,8 +731,9 @@ fitrig_status fitrig_create(const fitrig_config* cfg, fitrig_ctx** out) {
   ctx->cfg = *cfg;
   hipError_t e = hipSetDevice(cfg->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+  for (int i = 0; e == hipSuccess && i <= FITRIG_N_PHASES; ++i) e = hipEventCreate(&ctx->ev[i]);
   if (e != hipSuccess) {
-    delete ctx;
+    fitrig_destroy(ctx);
     return FITRIG_E_HIP;
   }
   // Scratch sized from the capacity hints, so warm calls allocate nothing.
@@ -702,9 +746,8 @@ fitrig_status fitrig_create(const fitrig_config* cfg, fitrig_ctx** out) {
     const int64_t nbands = (Wd + kBand - 1) / kBand + 1;
     const int64_t nwg = ncol * nbands;
     const int64_t nseg = np * (cfg->max_pixels / out_w + Wd) * kSegsPerGroup;
-    if ((rc = ensure(ctx, ctx->stat_part, (size_t)(np * nwg * 16))) != FITRIG_OK ||
+    if ((rc = ensure(ctx, ctx->stat_part, (size_t)(np * nwg * 16 * 16))) != FITRIG_OK ||
         (rc = ensure(ctx, ctx->seg_max, (size_t)(nseg * 4))) != FITRIG_OK ||
-        (rc = ensure(ctx, ctx->wg_max, (size_t)(nwg * 4))) != FITRIG_OK ||
         (rc = ensure_selection(ctx, nseg)) != FITRIG_OK) {
       fitrig_destroy(ctx);
       return rc;
@@ -718,7 +761,7 @@ fitrig_status fitrig_destroy(fitrig_ctx* ctx) {
   if (!ctx) return FITRIG_E_INVAL;
   (void)hipSetDevice(ctx->cfg.device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&ctx->seg_max2, &ctx->tile_wgmax, &ctx->stat_part, &ctx->seg_max,  &ctx->tile_part, &ctx->wg_max,   &ctx->cube,    &ctx->cube_f,
+  DevBuf* bufs[] = {&ctx->mom_tmp, &ctx->max_key, &ctx->seg_max2, &ctx->stat_part, &ctx->seg_max,  &ctx->tile_part, &ctx->cube,    &ctx->cube_f,
                     &ctx->eta_d,     &ctx->eta_f,    &ctx->mu,        &ctx->sigma,    &ctx->flags,   &ctx->eta_st,
                     &ctx->M,         &ctx->qscratch, &ctx->hist,      &ctx->rs_state, &ctx->rs_med,  &ctx->rs_dev,
                     &ctx->chunk_cnt, &ctx->counters, &ctx->seg_entry, &ctx->seg_mask, &ctx->cell_q,  &ctx->parent,
@@ -728,6 +771,8 @@ fitrig_status fitrig_destroy(fitrig_ctx* ctx) {
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  for (int i = 0; i <= FITRIG_N_PHASES; ++i)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   delete ctx;
   return FITRIG_OK;
 }

@@ -15,7 +15,9 @@ constexpr int kMaxHalo = 8;          // window <= 17
 constexpr int kPieces = 9;           // 32-wide tile pieces a column group can touch
 constexpr int kHistBins = 2048;      // radix-select digit bins (11 bits)
 
-inline int out_width(int halo) { return halo <= 4 ? kLanes - 8 : kLanes - 16; }
+// Output columns of a column group: 15 full 16-column chunks (the 256 lanes
+// also cover the halo of up to 8 columns on each side).
+inline int out_width(int /*halo*/) { return kLanes - 16; }
 
 // Streaming index kernel arguments (one launch covers every triple).
 struct StreamArgs {
@@ -33,7 +35,7 @@ struct StreamArgs {
   double* stat_part;     // [n-2][nwg][2]  (sum q, sum q^2)
   float* seg_max;        // [n-2][H][ncol*4]
   double* tile_part;     // nullable [n-2][nbands][ncol][kPieces][3]
-  float* wg_max;         // [nwg]
+  uint32_t* max_key;     // order-preserving key of the stack maximum (atomic max)
 };
 
 // Generic tile-mode kernel arguments (re-reads the three frames of a triple).
@@ -51,7 +53,7 @@ struct TileArgs {
   int32_t r_signed;
   float Cf;
   double* tile_part;     // [n-2][Ty][nchunk][pieces][3]
-  float* wg_max;         // [grid]
+  uint32_t* max_key;     // order-preserving key of the stack maximum (atomic max)
 };
 
 // Layout of the 64-cell row segments a selection works on.

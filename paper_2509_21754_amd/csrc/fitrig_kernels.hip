@@ -58,6 +58,15 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
+// Order-preserving map of a float to uint32 (and back).
+__device__ __forceinline__ uint32_t ord_key(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord_val(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
 constexpr int fdiv8(int a) { return a >= 0 ? a / 8 : -((-a + 7) / 8); }
 
 // Window reduction over a register array.
@@ -141,14 +150,48 @@ __device__ __forceinline__ float group8_max(float v) {
   return fmaxf(v, t);
 }
 
+// Sum over the 64 lanes of a wave with DPP (quad swaps, half-row and row
+// mirrors, row broadcasts); the total ends in lane 63. Fixed order.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = __double_as_longlong(v);
+  int lo, hi;
+  if constexpr (ROWMASK == 0xF) {
+    lo = __builtin_amdgcn_mov_dpp((int)(u & 0xFFFFFFFFu), CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xFFFFFFFFu), CTRL, ROWMASK, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROWMASK, 0xF, false);
+  }
+  return __longlong_as_double(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+// Sum over each row of 16 lanes (every lane of the row ends with it).
+__device__ __forceinline__ double row_sum_f64(double v) {
+  v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+  return v;
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 // Pointwise terms of one pixel: Delta from the two frame differences, r from
-// the reference pixel (Eqs. (3)-(5)).
-__device__ __forceinline__ void pix_terms(float d_new, float d_old, float ref, float Cf, int r_signed,
-                                          float& dl, float& rl) {
+// the reference pixel (Eqs. (3)-(5)). RS selects the literal signed reading
+// of Eq. (4); otherwise the ratio uses |x_hat| and is clamped to [0, 1].
+template <bool RS>
+__device__ __forceinline__ void pix_terms(float d_new, float d_old, float ref, float Cf, float& dl, float& rl) {
   dl = fabsf(fabsf(d_new) - fabsf(d_old));
-  float den = (ref == 0.0f) ? Cf : ref;
-  if (!r_signed) den = fabsf(den);
-  rl = fminf(dl * __builtin_amdgcn_rcpf(den), 1.0f);
+  const float den = (ref == 0.0f) ? Cf : ref;
+  // dl >= 0, so for |x_hat| the product is already >= 0 and min(., 1) is the clamp
+  rl = fminf(dl * __builtin_amdgcn_rcpf(RS ? den : fabsf(den)), 1.0f);
 }
 
 // 1 / n^2 for a window of n in-image cells (n = rows * cols).
@@ -159,186 +202,362 @@ __device__ __forceinline__ float inv_count2(int y, int x, int H, int Hh, int Wh)
   return 1.0f / (float)(nn * nn);
 }
 
+// Window maximum by max3 tripling: t3[j] = max(a[j..j+2]), then each window
+// of 2H+1 values is the max3 of at most three t3 terms (plus singles). The
+// inputs are non-negative finite floats (Delta and its window maxima), whose
+// bit patterns order like unsigned integers, so the maxima run on the bits
+// (exact, no NaN canonicalisation) and agree with every other evaluation.
+__device__ __forceinline__ uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) {
+  // one v_max3_u32 (common-subexpression elimination would otherwise split
+  // overlapping triples back into two-operand maxima)
+  uint32_t r;
+  asm("v_max3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+template <int H, int NOUT>
+struct WinMax {
+  static constexpr int L = 2 * H + 1;
+  static constexpr int NIN = NOUT + 2 * H;
+  __device__ static __forceinline__ void run(const float* af, float* o) {
+    if constexpr (L == 1) {
+#pragma unroll
+      for (int c = 0; c < NOUT; ++c) o[c] = af[c];
+    } else {
+      uint32_t a[NIN];
+#pragma unroll
+      for (int j = 0; j < NIN; ++j) a[j] = __float_as_uint(af[j]);
+      uint32_t t3[NIN > 2 ? NIN - 2 : 1];
+#pragma unroll
+      for (int j = 0; j + 2 < NIN; ++j) t3[j] = umax3(a[j], a[j + 1], a[j + 2]);
+#pragma unroll
+      for (int c = 0; c < NOUT; ++c) {
+        // terms: t3 at c, c+3, ... while they fit, then singles
+        uint32_t acc[8];
+        int nt = 0, p = c;
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+          if (p + 2 <= c + L - 1) {
+            acc[nt++] = t3[p];
+            p += 3;
+          }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (p <= c + L - 1) acc[nt++] = a[p++];
+        uint32_t m = acc[0];
+        int i = 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (i + 1 < nt) {
+            m = umax3(m, acc[i], acc[i + 1]);
+            i += 2;
+          } else if (i < nt) {
+            m = max(m, acc[i]);
+            i += 1;
+          }
+        }
+        o[c] = __uint_as_float(m);
+      }
+    }
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_ld<__half>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+}
+template <>
+__device__ __forceinline__ float buf_ld<bf16_t>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
+}
+
+// Buffer descriptor word 3 for gfx9 raw buffers; a lane offset at or beyond
+// the record count reads 0, which masks columns outside the image.
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr int kRecords = 0x40000000;
+constexpr int kOffMasked = 0x40000000;
+
 // ---------------------------------------------------------------------------
 // Streaming index kernel (sliding window). One workgroup owns 16 output rows
 // x out_w output columns and walks every frame once, keeping the previous
 // frame and the previous difference of its (16 + 2H) x 256 input pixels in
-// registers. Per triple it writes FP64 moment partials, the maximum q of
-// every 64-cell row segment, optional q map rows, and (tile == 32) the
+// registers; the next frame is loaded while the current one is reduced.
+// Per triple it writes FP64 moment partials (one per wave), the maximum q
+// of every 64-cell row segment, optional q map rows, and (tile == 32) the
 // per-column sums of the 32-row tiles for the frequency branch.
 // ---------------------------------------------------------------------------
-template <typename T, int H>
-__global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
-  constexpr int NR = kBand + 2 * H;
-  constexpr int NH = 8 + 2 * H;
-  constexpr int LDW = kLanes + 4;
-  __shared__ float sV[3][kBand][LDW];
-  __shared__ float sCol[3][kLanes];
-  __shared__ double sRed[2][kLanes / 64];
-  __shared__ float sMax[kLanes / 64];
+template <typename T, int H, bool RS>
+struct Stream {
+  static constexpr int NR = kBand + 2 * H;
+  static constexpr int NT = 16;            // outputs per horizontal task
+  static constexpr int NH = NT + 2 * H;
+  // LDS row layout: column c at c + c/16 (one pad word per 16 columns) and a
+  // row stride of 16 mod 64 words, so the 16-column horizontal tasks of a
+  // wave read 64 distinct banks.
+  static constexpr int LDW = kLanes + 16;
+  __device__ static __forceinline__ int lcol(int c) { return c + (c >> 4); }
 
-  const int lane = threadIdx.x;
-  const int wave = lane >> 6;
-  const int nwg = gridDim.x;
-  const int bid = xcd_remap(blockIdx.x, nwg);
-  const int band = bid / A.ncol;
-  const int grp = bid - band * A.ncol;
-  const int y0 = band * kBand;
-  const int x0 = grp * A.out_w;
-  const int xin = x0 - H + lane;
-  const bool colv = (lane < A.out_w + 2 * H) && xin >= 0 && xin < A.W;
-  const int nseg_row = A.ncol * kSegsPerGroup;
-  const bool interior =
-      (y0 - H >= 0) && (y0 + kBand - 1 + H < A.H) && (x0 - H >= 0) && (x0 + A.out_w - 1 + H < A.W);
-  constexpr int WN = (2 * H + 1) * (2 * H + 1);
-  const float inv_full = 1.0f / (float)(WN * WN);
+  // per-column tile sums of the group's columns, with 32 zero words on each
+  // side so a 32-column tile piece is always 32 in-range reads
+  static constexpr int CPAD = 32;
+  struct Shared {
+    float V[3][kBand][LDW];
+    float col[3][kLanes + 2 * CPAD];
+    int mx[kLanes / 64];
+  };
 
-  float xp[NR], dp[NR];
-#pragma unroll
-  for (int i = 0; i < NR; ++i) {
-    xp[i] = 0.0f;
-    dp[i] = 0.0f;
-  }
-  float mx = -INFINITY;
+  const StreamArgs& A;
+  Shared& sh;
+  int lane, wave, bid, band, grp, y0, x0, nseg_row, voff;
+  int64_t wg_off;
+  bool all_rows, interior;
+  float inv_full;
+  int mxi;
 
-  for (int k = 0; k < A.n; ++k) {
+  __device__ Stream(const StreamArgs& a, Shared& s) : A(a), sh(s) {}
+
+  template <bool ALLROWS>
+  __device__ __forceinline__ void load(int k, float* dst) {
     const T* fr = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, k);
-    float xn[NR];
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(fr + wg_off), (short)0, kRecords, kRsrcWord3);
+    int pitch = A.W * (int)sizeof(T);
+    // keep the row offsets in one running scalar instead of a hoisted table
+    asm volatile("" : "+s"(pitch));
+    int so = 0;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       const int y = y0 - H + i;
-      float v = 0.0f;
-      if (colv && y >= 0 && y < A.H) v = to_f<T>(fr[(int64_t)y * A.W + xin]);
-      xn[i] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < NR; i += 2) mx = (i + 1 < NR) ? fmaxf(mx, fmaxf(xn[i], xn[i + 1])) : fmaxf(mx, xn[i]);
-    float d[NR];
-#pragma unroll
-    for (int i = 0; i < NR; ++i) d[i] = xn[i] - xp[i];
-
-    if (k >= 2) {
-      const int s = k - 2;
-      float dl[NR], rl[NR];
-#pragma unroll
-      for (int i = 0; i < NR; ++i) pix_terms(d[i], dp[i], xp[i], A.Cf, A.r_signed, dl[i], rl[i]);
-      {
-        float vs[kBand], vm[kBand], vr[kBand], ts[kBand / 8], tm[kBand / 8], tr[kBand / 8];
-        Win<H, kBand, false>::run(dl, vs, ts);
-        Win<H, kBand, true>::run(dl, vm, tm);
-        Win<H, kBand, false>::run(rl, vr, tr);
-#pragma unroll
-        for (int c = 0; c < kBand; ++c) {
-          sV[0][c][lane] = vs[c];
-          sV[1][c][lane] = vm[c];
-          sV[2][c][lane] = vr[c];
-        }
-        if (A.tile_part) {
-          const int ox = lane - H;
-          if (ox >= 0 && ox < A.out_w) {
-            sCol[0][ox] = colv ? ts[0] + ts[1] : 0.0f;
-            sCol[1][ox] = colv ? fmaxf(tm[0], tm[1]) : 0.0f;
-            sCol[2][ox] = colv ? tr[0] + tr[1] : 0.0f;
-          }
-        }
-      }
-      __syncthreads();
-
-      double ssum = 0.0, ssq = 0.0;
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int task = lane + kLanes * t;
-        const int r = task >> 5, ch = task & 31;
-        const int y = y0 + r;
-        const int xc = x0 + 8 * ch;
-        const bool chv = (8 * ch < A.out_w) && (xc < A.W) && (y < A.H);
-        const int cb = chv ? 8 * ch : 0;
-        float hs[NH], hm[NH], hr[NH];
-#pragma unroll
-        for (int i = 0; i < NH; ++i) {
-          hs[i] = sV[0][r][cb + i];
-          hm[i] = sV[1][r][cb + i];
-          hr[i] = sV[2][r][cb + i];
-        }
-        float os[8], om[8], orr[8];
-        Win<H, 8, false>::run(hs, os, nullptr);
-        Win<H, 8, true>::run(hm, om, nullptr);
-        Win<H, 8, false>::run(hr, orr, nullptr);
-        float qv[8];
-        float gmax = -INFINITY;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int x = xc + c;
-          const bool v = chv && x < A.W;
-          float inv = inv_full;
-          if (!interior) inv = inv_count2(y, x, H, A.H, A.W);
-          const float q = ((os[c] * om[c]) * orr[c]) * inv;
-          qv[c] = q;
-          if (v) {
-            const double qd = (double)q;
-            ssum += qd;
-            ssq = fma(qd, qd, ssq);
-            gmax = fmaxf(gmax, q);
-          }
-        }
-        gmax = group8_max(gmax);
-        if (chv && (ch & 7) == 0)
-          A.seg_max[((int64_t)s * A.H + y) * nseg_row + grp * kSegsPerGroup + (ch >> 3)] = gmax;
-        if (A.qmap && chv) {
-          float* dst = A.qmap + ((int64_t)s * A.H + y) * A.W + xc;
-#pragma unroll
-          for (int c = 0; c < 8; ++c)
-            if (xc + c < A.W) dst[c] = qv[c];
-        }
-      }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        ssum += __shfl_xor(ssum, off);
-        ssq += __shfl_xor(ssq, off);
-      }
-      if ((lane & 63) == 0) {
-        sRed[0][wave] = ssum;
-        sRed[1][wave] = ssq;
-      }
-      __syncthreads();
-      if (lane == 0) {
-        double a0 = sRed[0][0], a1 = sRed[1][0];
-#pragma unroll
-        for (int w = 1; w < kLanes / 64; ++w) {
-          a0 += sRed[0][w];
-          a1 += sRed[1][w];
-        }
-        A.stat_part[((int64_t)s * nwg + bid) * 2 + 0] = a0;
-        A.stat_part[((int64_t)s * nwg + bid) * 2 + 1] = a1;
-      }
-      if (A.tile_part && lane < kPieces * 3) {
-        const int p = lane / 3, qd = lane - 3 * (lane / 3);
-        const int tx = x0 / 32 + p;
-        const int ca = max(tx * 32, x0) - x0;
-        const int cbnd = min(min(tx * 32 + 32, x0 + A.out_w), A.W) - x0;
-        double acc = 0.0;
-        for (int c = ca; c < cbnd; ++c) {
-          const double v = (double)sCol[qd][c];
-          acc = (qd == 1) ? fmax(acc, v) : acc + v;
-        }
-        A.tile_part[((((int64_t)s * A.nbands + band) * A.ncol + grp) * kPieces + p) * 3 + qd] = acc;
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      dp[i] = d[i];
-      xp[i] = xn[i];
+      if (ALLROWS || (y >= 0 && y < A.H))
+        dst[i] = buf_ld<T>(r, voff, so);
+      else
+        dst[i] = 0.0f;
+      so += pitch;
     }
   }
+
+  // One frame: P holds frame k-1 (becomes the load target of frame k+1), C
+  // holds frame k; DI holds the difference of frames k-1, k-2 and DO receives
+  // the difference of frames k, k-1 (the two swap between calls).
+  template <bool ALLROWS>
+  __device__ __forceinline__ void step(int k, float* P, const float* C, const float* DI, float* DO) {
+    // running maximum on the signed-int view of the bits: it orders every
+    // positive float correctly and maps non-positive values below them, which
+    // is all max(., C) with C > 0 needs
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-  if ((lane & 63) == 0) sMax[wave] = mx;
+    for (int i = 0; i + 1 < NR; i += 2) mxi = max(mxi, max(__float_as_int(C[i]), __float_as_int(C[i + 1])));
+    if constexpr (NR % 2) mxi = max(mxi, __float_as_int(C[NR - 1]));
+    float dl[NR], rl[NR];
+    if (k >= 2) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        DO[i] = C[i] - P[i];
+        pix_terms<RS>(DO[i], DI[i], P[i], A.Cf, dl[i], rl[i]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) DO[i] = C[i] - P[i];
+    }
+    if (k + 1 < A.n) load<ALLROWS>(k + 1, P);
+    if (k < 2) return;
+    const int s = k - 2;
+    {
+      float vs[kBand], vm[kBand], vr[kBand], ts[kBand / 8], tr[kBand / 8];
+      Win<H, kBand, false>::run(dl, vs, ts);
+      WinMax<H, kBand>::run(dl, vm);
+      Win<H, kBand, false>::run(rl, vr, tr);
+#pragma unroll
+      for (int c = 0; c < kBand; ++c) {
+        sh.V[0][c][lcol(lane)] = vs[c];
+        sh.V[1][c][lcol(lane)] = vm[c];
+        sh.V[2][c][lcol(lane)] = vr[c];
+      }
+      if (A.tile_part) {
+        const int ox = lane - H;
+        if (ox >= 0 && ox < A.out_w) {
+          uint32_t mb = __float_as_uint(dl[H]);
+#pragma unroll
+          for (int i = 1; i < kBand; ++i) mb = max(mb, __float_as_uint(dl[H + i]));
+          const float m = __uint_as_float(mb);
+          sh.col[0][CPAD + ox] = ts[0] + ts[1];
+          sh.col[1][CPAD + ox] = m;
+          sh.col[2][CPAD + ox] = tr[0] + tr[1];
+        }
+      }
+    }
+    __syncthreads();
+    // horizontal: lane -> (row r, 16-column chunk ch)
+    const int r = lane >> 4, ch = lane & 15;
+    const int y = y0 + r;
+    const int xc = x0 + NT * ch;
+    const bool chv = (NT * ch < A.out_w) && (xc < A.W) && (y < A.H);
+    // chunk base in the padded layout; column 16 ch + i sits at 17 ch + i + i/16.
+    // Reads past column 255 (last chunk) land in padding or the next row and
+    // only feed outputs outside the group.
+    const int cb = chv ? 17 * ch : 0;
+    float os[NT], om[NT], orr[NT];
+    {
+      float h[NH];
+#pragma unroll
+      for (int i = 0; i < NH; ++i) h[i] = sh.V[0][r][cb + i + (i >> 4)];
+      Win<H, NT, false>::run(h, os, nullptr);
+#pragma unroll
+      for (int i = 0; i < NH; ++i) h[i] = sh.V[1][r][cb + i + (i >> 4)];
+      WinMax<H, NT>::run(h, om);
+#pragma unroll
+      for (int i = 0; i < NH; ++i) h[i] = sh.V[2][r][cb + i + (i >> 4)];
+      Win<H, NT, false>::run(h, orr, nullptr);
+    }
+    float qv[NT];
+    // FP64 moments: q^2 of a float is exact in double, so a constant map
+    // gives exactly zero variance
+    double s1 = 0.0, s2 = 0.0;
+    float gmax = -INFINITY;
+    if (interior) {
+      // every chunk but the 16th is fully inside the image: no per-cell masks,
+      // the idle chunk is dropped once per lane. The constant 1/n^2 is applied
+      // after the reductions: q = p * inv with p = (S max) R, and rounding
+      // p * inv is monotone, so max q = (max p) * inv exactly.
+      float pv[NT];
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        const float pq = (os[c] * om[c]) * orr[c];
+        pv[c] = pq;
+        const double pd = (double)pq;
+        s1 += pd;
+        s2 = fma(pd, pd, s2);
+        gmax = fmaxf(gmax, pq);
+      }
+      const double id = (double)inv_full;
+      s1 *= id;
+      s2 *= id * id;
+      gmax *= inv_full;
+      if (A.qmap) {
+#pragma unroll
+        for (int c = 0; c < NT; ++c) qv[c] = pv[c] * inv_full;
+      }
+      if (!chv) {
+        s1 = 0.0;
+        s2 = 0.0;
+        gmax = -INFINITY;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        const int x = xc + c;
+        const bool v = chv && x < A.W;
+        const float q = ((os[c] * om[c]) * orr[c]) * inv_count2(y, x, H, A.H, A.W);
+        qv[c] = q;
+        const double qm = v ? (double)q : 0.0;
+        s1 += qm;
+        s2 = fma(qm, qm, s2);
+        gmax = v ? fmaxf(gmax, q) : gmax;
+      }
+    }
+    // 64-cell segments = 4 consecutive chunks = one lane quad
+    gmax = fmaxf(gmax, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(gmax), 0xB1, 0xF, 0xF, false)));
+    gmax = fmaxf(gmax, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(gmax), 0x4E, 0xF, 0xF, false)));
+    if ((ch & 3) == 0 && y < A.H && xc < A.W && NT * ch < A.out_w)
+      A.seg_max[((int64_t)s * A.H + y) * nseg_row + grp * kSegsPerGroup + (ch >> 2)] = gmax;
+    if (A.qmap && chv) {
+      float* dst = A.qmap + ((int64_t)s * A.H + y) * A.W + xc;
+#pragma unroll
+      for (int c = 0; c < NT; ++c)
+        if (xc + c < A.W) dst[c] = qv[c];
+    }
+    const double a1 = row_sum_f64(s1);
+    const double a2 = row_sum_f64(s2);
+    if ((lane & 15) == 15) {
+      double* sp = A.stat_part + (((int64_t)s * gridDim.x + bid) * 16 + (lane >> 4)) * 2;
+      sp[0] = a1;
+      sp[1] = a2;
+    }
+    if (A.tile_part) {
+      // job = (quantity qd, piece p) on 8 lanes; lane sub sums columns
+      // 4 sub .. 4 sub + 3 of the 32 columns of tile x0/32 + p (zeros outside
+      // the group or the image), then the 8 lanes combine by DPP (fixed order)
+      const int job = lane >> 3, sub = lane & 7;
+      const int qd = job / kPieces, p = job - kPieces * (job / kPieces);
+      const int qs = qd < 3 ? qd : 0;
+      const int c0 = (x0 / 32 + p) * 32 - x0 + 4 * sub;  // >= -31
+      const float* cv = &sh.col[qs][CPAD + c0];
+      const float v0 = cv[0], v1 = cv[1], v2 = cv[2], v3 = cv[3];
+      float sm = (v0 + v1) + (v2 + v3);
+      uint32_t mb = umax3(__float_as_uint(v0), __float_as_uint(v1), max(__float_as_uint(v2), __float_as_uint(v3)));
+      sm += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sm), 0xB1, 0xF, 0xF, false));
+      mb = max(mb, (uint32_t)__builtin_amdgcn_mov_dpp((int)mb, 0xB1, 0xF, 0xF, false));
+      sm += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sm), 0x4E, 0xF, 0xF, false));
+      mb = max(mb, (uint32_t)__builtin_amdgcn_mov_dpp((int)mb, 0x4E, 0xF, 0xF, false));
+      sm += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sm), 0x141, 0xF, 0xF, false));
+      mb = max(mb, (uint32_t)__builtin_amdgcn_mov_dpp((int)mb, 0x141, 0xF, 0xF, false));
+      if (sub == 0 && qd < 3)
+        A.tile_part[((((int64_t)s * A.nbands + band) * A.ncol + grp) * kPieces + p) * 3 + qd] =
+            (double)(qd == 1 ? __uint_as_float(mb) : sm);
+    }
+    __syncthreads();
+  }
+};
+
+template <typename T, int H, bool RS>
+__global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
+  using S = Stream<T, H, RS>;
+  __shared__ typename S::Shared sh;
+  S st(A, sh);
+  st.lane = threadIdx.x;
+  st.wave = st.lane >> 6;
+  st.bid = xcd_remap(blockIdx.x, gridDim.x);
+  st.band = st.bid / A.ncol;
+  st.grp = st.bid - st.band * A.ncol;
+  st.y0 = st.band * kBand;
+  st.x0 = st.grp * A.out_w;
+  const int xin = st.x0 - H + st.lane;
+  const bool colv = (st.lane < A.out_w + 2 * H) && xin >= 0 && xin < A.W;
+  st.voff = colv ? st.lane * (int)sizeof(T) : kOffMasked;
+  st.wg_off = (int64_t)(st.y0 - H) * A.W + (st.x0 - H);
+  st.all_rows = (st.y0 - H >= 0) && (st.y0 + kBand + H <= A.H);
+  st.interior = st.all_rows && (st.x0 - H >= 0) && (st.x0 + A.out_w - 1 + H < A.W);
+  st.nseg_row = A.ncol * kSegsPerGroup;
+  constexpr int WN = (2 * H + 1) * (2 * H + 1);
+  st.inv_full = 1.0f / (float)(WN * WN);
+  st.mxi = INT32_MIN;
+  for (int i = st.lane; i < 3 * kBand * S::LDW; i += kLanes) (&sh.V[0][0][0])[i] = 0.0f;
+  for (int i = st.lane; i < 3 * (kLanes + 2 * S::CPAD); i += kLanes) (&sh.col[0][0])[i] = 0.0f;
   __syncthreads();
-  if (lane == 0) {
-    float m = sMax[0];
-    for (int w = 1; w < kLanes / 64; ++w) m = fmaxf(m, sMax[w]);
-    A.wg_max[bid] = m;
+  float fa[S::NR], fb[S::NR], da[S::NR], db[S::NR];
+#pragma unroll
+  for (int i = 0; i < S::NR; ++i) {
+    fa[i] = 0.0f;
+    da[i] = 0.0f;
+  }
+  if (st.all_rows) {
+    st.template load<true>(0, fb);
+    for (int k = 0; k < A.n; k += 2) {
+      st.template step<true>(k, fa, fb, da, db);
+      if (k + 1 < A.n) st.template step<true>(k + 1, fb, fa, db, da);
+    }
+  } else {
+    st.template load<false>(0, fb);
+    for (int k = 0; k < A.n; k += 2) {
+      st.template step<false>(k, fa, fb, da, db);
+      if (k + 1 < A.n) st.template step<false>(k + 1, fb, fa, db, da);
+    }
+  }
+  int mx = st.mxi;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mx = max(mx, __shfl_xor(mx, off));
+  if ((st.lane & 63) == 0) sh.mx[st.wave] = mx;
+  __syncthreads();
+  if (st.lane == 0) {
+    int m = sh.mx[0];
+    for (int w = 1; w < kLanes / 64; ++w) m = max(m, sh.mx[w]);
+    // m is the largest value when any is positive, else some value <= 0
+    atomicMax(A.max_key, ord_key(__int_as_float(m)));
   }
 }
 
@@ -348,7 +567,7 @@ __global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
 // tile row and accumulates sum Delta, max Delta and sum r in FP64; per tile
 // piece of the chunk the columns are summed in order.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool RS>
 __global__ __launch_bounds__(kLanes) void k_tile(TileArgs A) {
   __shared__ double sCol[3][kLanes];
   __shared__ float sMax[kLanes / 64];
@@ -369,7 +588,7 @@ __global__ __launch_bounds__(kLanes) void k_tile(TileArgs A) {
       const float a = to_f<T>(f0[o]), b = to_f<T>(f1[o]), c = to_f<T>(f2[o]);
       mx = fmaxf(mx, fmaxf(a, fmaxf(b, c)));
       float dl, rl;
-      pix_terms(c - b, b - a, b, A.Cf, A.r_signed, dl, rl);
+      pix_terms<RS>(c - b, b - a, b, A.Cf, dl, rl);
       sd += (double)dl;
       md = fmax(md, (double)dl);
       sr += (double)rl;
@@ -395,7 +614,7 @@ __global__ __launch_bounds__(kLanes) void k_tile(TileArgs A) {
   if (lane == 0) {
     float m = sMax[0];
     for (int w = 1; w < kLanes / 64; ++w) m = fmaxf(m, sMax[w]);
-    A.wg_max[((int64_t)s * gridDim.y + ty) * A.nchunk + chunk] = m;
+    atomicMax(A.max_key, ord_key(m));
   }
 }
 
@@ -446,6 +665,33 @@ __device__ double wg_sum(double v, double* sh) {
   return r;
 }
 
+// First stage of the per-set moments: workgroup g of set s reduces the
+// contiguous slice g of the set's entries (raw values, or (sum, sum sq)
+// pairs) into out[s][g][2], in a fixed order.
+__global__ __launch_bounds__(256) void k_moments_part(const double* src, int64_t nparts, int raw, double* out) {
+  __shared__ double sh[256];
+  const int s = blockIdx.y, g = blockIdx.x, G = gridDim.x;
+  const int64_t per = (nparts + G - 1) / G;
+  const int64_t a = (int64_t)g * per, b = min(a + per, nparts);
+  double x = 0.0, y = 0.0;
+  for (int64_t i = a + threadIdx.x; i < b; i += 256) {
+    if (raw) {
+      const double v = src[(int64_t)s * nparts + i];
+      x += v;
+      y = fma(v, v, y);
+    } else {
+      x += src[((int64_t)s * nparts + i) * 2 + 0];
+      y += src[((int64_t)s * nparts + i) * 2 + 1];
+    }
+  }
+  x = wg_sum(x, sh);
+  y = wg_sum(y, sh);
+  if (threadIdx.x == 0) {
+    out[((int64_t)s * G + g) * 2 + 0] = x;
+    out[((int64_t)s * G + g) * 2 + 1] = y;
+  }
+}
+
 // Per set: mean and population std from moment partials [set][nparts][2]
 // (raw = 0) or from raw values [set][nparts] (raw = 1).
 __global__ __launch_bounds__(256) void k_moments(const double* src, int64_t nparts, int raw, int64_t count,
@@ -476,17 +722,9 @@ __global__ __launch_bounds__(256) void k_moments(const double* src, int64_t npar
   }
 }
 
-__global__ __launch_bounds__(256) void k_max_finalize(const float* wg_max, int64_t n, double C, double* M) {
-  __shared__ float sh[256];
-  float m = -INFINITY;
-  for (int64_t i = threadIdx.x; i < n; i += 256) m = fmaxf(m, wg_max[i]);
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) M[0] = fmax((double)sh[0], C);
+// M = max(max over the stack, C) from the order-preserving key of the maximum.
+__global__ void k_max_finalize(const uint32_t* max_key, double C, double* M) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) M[0] = fmax((double)ord_val(max_key[0]), C);
 }
 
 __global__ void k_to_tlisi(float* map, int64_t n, const double* M) {
@@ -511,13 +749,6 @@ struct RsState {
   int64_t rank;
 };
 
-__device__ __forceinline__ uint32_t ord_key(float v) {
-  const uint32_t u = __float_as_uint(v);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float ord_val(uint32_t k) {
-  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
-}
 
 __global__ __launch_bounds__(256) void k_rs_hist(const float* vals, int64_t per_set, int mode, const double* med,
                                                  const RsState* st, int shift, int nbits, uint32_t* hist) {
@@ -755,9 +986,9 @@ __global__ __launch_bounds__(256) void k_compact_write(F f, E emit, int64_t ne_s
 
 // Exact q of the cells of each selected segment, recomputed with the same
 // arithmetic as k_stream; mask of z > tau.
-template <typename T, int H>
+template <typename T, int H, bool RS>
 __global__ __launch_bounds__(64) void k_recompute(const void* base, const void* c0, const void* c1, int ncarry,
-                                                  int64_t plane, int Hh, int Wh, float Cf, int r_signed,
+                                                  int64_t plane, int Hh, int Wh, float Cf,
                                                   SegLayout L, const int64_t* seg_entry, const int64_t* nsel_p,
                                                   int64_t cap, const double* mu, const double* sigma, double tau,
                                                   uint64_t* seg_mask, float* cell_q) {
@@ -792,12 +1023,12 @@ __global__ __launch_bounds__(64) void k_recompute(const void* base, const void* 
           b = to_f<T>(f1[o]);
           c = to_f<T>(f2[o]);
         }
-        pix_terms(c - b, b - a, b, Cf, r_signed, dl[j], rl[j]);
+        pix_terms<RS>(c - b, b - a, b, Cf, dl[j], rl[j]);
       }
       float o8[8];
       Win<H, 8, false>::run(dl, o8, nullptr);
       sv[0][cc] = o8[y - by];
-      Win<H, 8, true>::run(dl, o8, nullptr);
+      WinMax<H, 8>::run(dl, o8);
       sv[1][cc] = o8[y - by];
       Win<H, 8, false>::run(rl, o8, nullptr);
       sv[2][cc] = o8[y - by];
@@ -817,7 +1048,7 @@ __global__ __launch_bounds__(64) void k_recompute(const void* base, const void* 
         hr[j] = sv[2][ci];
       }
       Win<H, 8, false>::run(hs, os, nullptr);
-      Win<H, 8, true>::run(hm, om, nullptr);
+      WinMax<H, 8>::run(hm, om);
       Win<H, 8, false>::run(hr, orr, nullptr);
       const int c = x - bx;
       // same association as k_stream: ((sum * max) * sum_r) * 1/n^2

@@ -42,7 +42,7 @@ class fitrig_config(ctypes.Structure):
         ("C", ctypes.c_double),
         ("max_pixels", ctypes.c_int64),
         ("max_snap", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
         ("max_segments", ctypes.c_int64),
     ]
 
@@ -90,7 +90,10 @@ EXPORTS = (
     "fitrig_status_string",
     "fitrig_last_hip_error",
     "fitrig_abi_version",
+    "fitrig_phase_times",
 )
+N_PHASES = 5
+PHASES = ("index_pass", "spread", "image_select", "freq_branch", "host_copy")
 
 _lib: Optional[ctypes.CDLL] = None
 
@@ -119,6 +122,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fitrig_last_hip_error.restype = i32
     L.fitrig_abi_version.argtypes = []
     L.fitrig_abi_version.restype = i32
+    L.fitrig_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
+    L.fitrig_phase_times.restype = i32
     _lib = L
     return L
 
@@ -163,6 +168,12 @@ def fitrig_abi_version() -> int:
     return load().fitrig_abi_version()
 
 
+def fitrig_phase_times(ctx) -> list:
+    buf = (ctypes.c_double * N_PHASES)()
+    n = load().fitrig_phase_times(ctx, buf, N_PHASES)
+    return list(buf[:max(n, 0)])
+
+
 # ---- torch convenience layer --------------------------------------------------
 
 class FitrigError(RuntimeError):
@@ -177,10 +188,16 @@ def _dtype_code(t) -> int:
     return {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}[t.dtype]
 
 
-def _cand_dict(c: fitrig_candidate) -> dict:
-    return dict(branch=c.branch, triple=c.triple, label=c.label, n_pix=c.n_pix, peak_y=c.peak_y,
-                peak_x=c.peak_x, peak_z=c.peak_z, peak_q=c.peak_q, cy=c.cy, cx=c.cx, y0=c.y0,
-                x0=c.x0, y1=c.y1, x1=c.x1)
+_CAND_KEYS = ("branch", "triple", "label", "n_pix", "peak_y", "peak_x", "peak_z", "peak_q", "cy", "cx",
+              "y0", "x0", "y1", "x1")
+
+
+def _rec_dict(r) -> dict:
+    d = {k: r[k].item() for k in _CAND_KEYS}
+    # float fields come from float32 storage
+    d["peak_z"] = float(r["peak_z"])
+    d["peak_q"] = float(r["peak_q"])
+    return d
 
 
 class Context:
@@ -192,6 +209,10 @@ class Context:
         if rc != OK:
             raise FitrigError(rc, "fitrig_create")
         self.handle = h
+
+    def phase_times(self) -> dict:
+        """Per-phase milliseconds of the last detect (config profile=1)."""
+        return dict(zip(PHASES, fitrig_phase_times(self.handle)))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -210,41 +231,52 @@ class Context:
     def __exit__(self, *a):
         self.close()
 
+    def _buffers(self, cand_cap: int, np_: int):
+        b = getattr(self, "_buf", None)
+        if b is None or b["cap"] < cand_cap or b["np"] < np_:
+            cap, npb = max(cand_cap, 1), max(np_, 1)
+            b = {"cap": cap, "np": npb, "cand": (fitrig_candidate * cap)(),
+                 "mu": (ctypes.c_double * npb)(), "sg": (ctypes.c_double * npb)(),
+                 "fl": (ctypes.c_uint32 * npb)(), "n": ctypes.c_int64(), "st": fitrig_stats()}
+            b["st"].mu = ctypes.cast(b["mu"], ctypes.POINTER(ctypes.c_double))
+            b["st"].sigma = ctypes.cast(b["sg"], ctypes.POINTER(ctypes.c_double))
+            b["st"].flags = ctypes.cast(b["fl"], ctypes.POINTER(ctypes.c_uint32))
+            self._buf = b
+        return b
+
     def detect(self, stack, sigma: float, *, cand_cap: int = 1 << 16, index_map=None, eta_map=None,
-               stream=None, raise_on_trunc: bool = False):
+               stream=None, raise_on_trunc: bool = False, as_dicts: bool = True):
         """Run the path on ``stack`` ([n][H][W] device tensor, f32/f16/bf16).
 
-        Returns (candidates (list of dicts), stats (dict), status)."""
+        Returns (candidates, stats (dict), status). Candidates are a list of
+        dicts, or with ``as_dicts=False`` a numpy structured array (a copy of
+        the records the library wrote)."""
+        import numpy as np
         import torch
 
         if not stack.is_cuda or not stack.is_contiguous() or stack.dim() != 3:
             raise ValueError("stack must be a contiguous 3-D device tensor")
         n, H, W = stack.shape
         np_ = max(n - 2, 0)
-        cand = (fitrig_candidate * max(cand_cap, 1))()
-        ncand = ctypes.c_int64()
-        mu = (ctypes.c_double * max(np_, 1))()
-        sg = (ctypes.c_double * max(np_, 1))()
-        fl = (ctypes.c_uint32 * max(np_, 1))()
-        st = fitrig_stats()
-        st.mu = ctypes.cast(mu, ctypes.POINTER(ctypes.c_double))
-        st.sigma = ctypes.cast(sg, ctypes.POINTER(ctypes.c_double))
-        st.flags = ctypes.cast(fl, ctypes.POINTER(ctypes.c_uint32))
+        b = self._buffers(cand_cap, np_)
         for m in (index_map, eta_map):
             if m is not None and (not m.is_cuda or m.dtype != torch.float32 or not m.is_contiguous()):
                 raise ValueError("maps must be contiguous float32 device tensors")
         if stream is None:
             stream = torch.cuda.current_stream(stack.device)
         rc = fitrig_detect(self.handle, ctypes.c_void_p(stack.data_ptr()), _dtype_code(stack), n, H, W,
-                           float(sigma), cand, cand_cap, ctypes.byref(ncand),
+                           float(sigma), b["cand"], cand_cap, ctypes.byref(b["n"]),
                            ctypes.c_void_p(index_map.data_ptr()) if index_map is not None else None,
                            ctypes.c_void_p(eta_map.data_ptr()) if eta_map is not None else None,
-                           ctypes.byref(st), ctypes.c_void_p(stream.cuda_stream))
+                           ctypes.byref(b["st"]), ctypes.c_void_p(stream.cuda_stream))
         if rc not in (OK, E_TRUNC) or (rc == E_TRUNC and raise_on_trunc):
             raise FitrigError(rc, "fitrig_detect", fitrig_last_hip_error(self.handle))
-        k = min(ncand.value, cand_cap)
-        cands = [_cand_dict(cand[i]) for i in range(k)]
-        stats = dict(M=st.M, n_triples=st.n_triples, mu=list(mu[:np_]), sigma=list(sg[:np_]),
-                     flags=list(fl[:np_]), eta_mu=st.eta_mu, eta_sigma=st.eta_sigma,
-                     n_image_cand=st.n_image_cand, n_freq_cand=st.n_freq_cand, n_cand=ncand.value)
+        ncand = b["n"].value
+        k = min(ncand, cand_cap)
+        arr = np.ctypeslib.as_array(b["cand"])[:k].copy()
+        cands = [_rec_dict(r) for r in arr] if as_dicts else arr
+        st = b["st"]
+        stats = dict(M=st.M, n_triples=st.n_triples, mu=list(b["mu"][:np_]), sigma=list(b["sg"][:np_]),
+                     flags=list(b["fl"][:np_]), eta_mu=st.eta_mu, eta_sigma=st.eta_sigma,
+                     n_image_cand=st.n_image_cand, n_freq_cand=st.n_freq_cand, n_cand=ncand)
         return cands, stats, rc
