@@ -75,6 +75,136 @@ def cpu_baseline(spec_name: str) -> dict:
                       f"full detect incl. frequency branch, {dt:.2f} s"}
 
 
+def pulsar_recall(cands, spec) -> dict:
+    """Share of (pulsar, trigger triple) pairs with an image-branch candidate
+    whose box (grown by 2 px) holds the pulsar: a pulse in frame p triggers
+    triples p-2 and p."""
+    import numpy as np
+
+    import synth
+
+    sky = synth.sky_model(spec)
+    img = cands[cands["branch"] == 1]
+    by_t = {}
+    for t in np.unique(img["triple"]):
+        sel = img[img["triple"] == t]
+        by_t[int(t)] = (sel["y0"] - 2, sel["x0"] - 2, sel["y1"] + 2, sel["x1"] + 2)
+    hit = tot = 0
+    for i in range(len(sky.pulsar_amp)):
+        y, x = int(sky.pulsar_yx[i, 0]), int(sky.pulsar_yx[i, 1])
+        for p in np.nonzero(sky.pulsar_w[i] > 0)[0]:
+            for t in (int(p) - 2, int(p)):
+                if 0 <= t <= spec.n - 3:
+                    tot += 1
+                    b = by_t.get(t)
+                    if b is not None and bool(np.any((b[0] <= y) & (y <= b[2]) & (b[1] <= x) & (x <= b[3]))):
+                        hit += 1
+    return {"pulsar_triggers": tot, "detected": hit, "recall": round(hit / tot, 4) if tot else None}
+
+
+def time_detect(ctx, stack, tau, steps, warmup, stream):
+    for _ in range(warmup):
+        ctx.detect(stack, tau, stream=stream, as_dicts=False)
+    import torch
+
+    torch.cuda.synchronize()
+    step_ms, phases = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        cands, stats, rc = ctx.detect(stack, tau, stream=stream, as_dicts=False)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        phases.append(ctx.phase_times())
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, step_ms, phases, cands, stats
+
+
+def pctl(v, p):
+    srt = sorted(v)
+    return srt[min(len(srt) - 1, int(round(p * (len(srt) - 1))))]
+
+
+def serving_replay(n_req: int, slots: int, rate_hz: float, budget_gib: float, dev) -> dict:
+    """The serving workload: Poisson arrivals of snapshot stacks of 16 fields
+    (size class 2048^2 / 4096^2 / 8192^2 and storage dtype fixed per field,
+    16 / 32 / 128 snapshots per request) replayed in real time through the
+    server, then the same requests submitted at once (capacity)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2509_21754_amd import Server
+
+    reqs = synth.serving_requests(n_req, rate_hz=rate_hz)
+    n_pool = max(r["n"] for r in reqs)
+    pools = {}
+    for i, size in enumerate(sorted({r["size"] for r in reqs})):
+        sp = synth.scaled(synth.WORKLOADS["c1"], size, size, n=n_pool, seed=1004 * 10 + i)
+        base = synth.make_stack(sp, device=dev)
+        for dt in sorted({r["dtype"] for r in reqs if r["size"] == size}):
+            pools[(size, dt)] = base if dt == "f32" else base.to(torch.float16)
+        if ("f32" not in {r["dtype"] for r in reqs if r["size"] == size}):
+            del base
+    torch.cuda.synchronize()
+    print(f"[bench] serving pools ready: {sorted(pools)}", file=sys.stderr, flush=True)
+    max_px = max(r["size"] for r in reqs) ** 2
+
+    def run(realtime: bool):
+        cursor = {}
+        with Server(n_slots=slots, max_fields=32, mem_budget=int(budget_gib * (1 << 30)), window=7,
+                    max_pixels=max_px, max_snap=n_pool + 2) as srv:
+            # warm every slot and size class outside the timed part (fields 100+)
+            for j, key in enumerate(sorted(pools)):
+                tk = srv.submit(100 + j, pools[key][:3], 6.0)
+                srv.poll(tk)
+                srv.release(tk)
+            tickets = []
+            t0 = time.perf_counter()
+            for r in reqs:
+                if realtime:
+                    dt = t0 + r["t"] - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                pool = pools[(r["size"], r["dtype"])]
+                c = cursor.get(r["field"], 0)
+                if c + r["n"] > n_pool:
+                    c = 0
+                cursor[r["field"]] = c + r["n"]
+                tickets.append((srv.submit(r["field"], pool[c:c + r["n"]], 6.0), r))
+            res = []
+            for tk, r in tickets:
+                o = srv.poll(tk, as_dicts=False)
+                res.append((o, r))
+                srv.release(tk)
+            wall = time.perf_counter() - t0
+        return res, wall
+
+    out = {"requests": n_req, "rate_hz": rate_hz, "slots": slots, "mem_budget_gib": budget_gib,
+           "fields": 16, "window": 7, "tau": 6.0}
+    for mode in ("realtime", "saturated"):
+        res, wall = run(mode == "realtime")
+        bad = [o["status"] for o, _ in res if o["status"] not in (0, -4)]
+        lat = [(o["t_done_ns"] - o["t_submit_ns"]) / 1e6 for o, _ in res]
+        wait = [(o["t_start_ns"] - o["t_submit_ns"]) / 1e6 for o, _ in res]
+        first = min(o["t_submit_ns"] for o, _ in res)
+        last = max(o["t_done_ns"] for o, _ in res)
+        px = sum(r["n"] * r["size"] ** 2 for _, r in res)
+        d = {"mpix_s": round(px / ((last - first) / 1e9) / 1e6, 1), "wall_s": round(wall, 3),
+             "p50_ms": round(pctl(lat, 0.5), 3), "p99_ms": round(pctl(lat, 0.99), 3),
+             "queue_wait_p50_ms": round(pctl(wait, 0.5), 3), "errors": len(bad)}
+        for dt in ("f16", "f32"):
+            l2 = [x for x, (_, r) in zip(lat, res) if r["dtype"] == dt]
+            pxd = [r["n"] * r["size"] ** 2 for _, r in res if r["dtype"] == dt]
+            if l2:
+                d[dt] = {"requests": len(l2), "p50_ms": round(pctl(l2, 0.5), 3), "p99_ms": round(pctl(l2, 0.99), 3),
+                         "mean_mpix": round(float(np.mean(pxd)) / 1e6, 1)}
+        out[mode] = d
+        print(f"[bench] serving {mode}: {d}", file=sys.stderr, flush=True)
+    del pools
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +212,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp16-form", action="store_true", help="skip the FP16-storage run of the same stack")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving replay")
+    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-budget-gib", type=float, default=48.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -111,25 +246,9 @@ def main() -> int:
     n, H, W = spec.n, spec.H, spec.W
     ctx = Context(window=spec.window, profile=1, max_pixels=H * W, max_snap=n)
     stream = torch.cuda.current_stream(dev)
-    for _ in range(args.warmup):
-        ctx.detect(stack, tau, stream=stream, as_dicts=False)
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done, timing {args.steps} steps", file=sys.stderr, flush=True)
-    step_ms, kern_ms, phases = [], [], []
-    ncand = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        cands, stats, rc = ctx.detect(stack, tau, stream=stream, as_dicts=False)
-        step_ms.append((time.perf_counter() - ts) * 1e3)
-        pt = ctx.phase_times()
-        phases.append(pt)
-        kern_ms.append(pt["index_pass"])
-        ncand = stats["n_cand"]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    print(f"[bench] timing {args.steps} steps after {args.warmup} warmup", file=sys.stderr, flush=True)
+    ms_per_step, step_ms, phases, cands, stats = time_detect(ctx, stack, tau, args.steps, args.warmup, stream)
+    kern_ms = [p["index_pass"] for p in phases]
     px = n * H * W
     value = px / (ms_per_step / 1e3) / 1e6
     kmean = statistics.mean(kern_ms)
@@ -140,8 +259,6 @@ def main() -> int:
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_stream (streaming index pass)", "kernel_ms": round(kmean, 4),
             "alg_bytes_per_launch": alg_bytes}
-    srt = sorted(step_ms)
-    p99 = srt[min(len(srt) - 1, int(round(0.99 * (len(srt) - 1))))]
     phase_mean = {k: round(statistics.mean(p[k] for p in phases), 4) for k in phases[0]}
     out = {
         "metric": "detected snapshot Mpix/s",
@@ -160,14 +277,39 @@ def main() -> int:
                    "window": spec.window, "tau": tau, "branches": "image+freq", "sigma_est": "mean_std"},
         "hbm_peak_frac_whole_step": round(px * BYTES_IN[spec.dtype] / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "p50_ms": round(statistics.median(step_ms), 4),
-        "p99_ms": round(p99, 4),
+        "p99_ms": round(pctl(step_ms, 0.99), 4),
         "phase_ms": phase_mean,
-        "n_candidates": ncand,
+        "n_candidates": stats["n_cand"],
         "roofline": roof,
     }
+    if spec.dtype == "f32" and not args.no_fp16_form:
+        # the precision form on the same stack: FP16 storage (round to nearest
+        # even), FP32 arithmetic; detection accuracy on the injected pulsars
+        acc32 = pulsar_recall(cands, spec)
+        s16 = stack.to(torch.float16)
+        torch.cuda.synchronize()
+        print("[bench] timing the FP16-storage form", file=sys.stderr, flush=True)
+        ms16, st16, ph16, c16, stats16 = time_detect(ctx, s16, tau, args.steps, args.warmup, stream)
+        k16 = statistics.mean(p["index_pass"] for p in ph16)
+        a16 = px * 2 / (k16 / 1e3) / 1e9
+        keys32 = set(zip(cands["branch"].tolist(), cands["triple"].tolist(), cands["label"].tolist()))
+        keys16 = set(zip(c16["branch"].tolist(), c16["triple"].tolist(), c16["label"].tolist()))
+        out["fp16_form"] = {
+            "value": round(px / (ms16 / 1e3) / 1e6, 1), "unit": "Mpix/s", "ms_per_step": round(ms16, 4),
+            "p50_ms": round(statistics.median(st16), 4), "p99_ms": round(pctl(st16, 0.99), 4),
+            "roofline": {"bound": "hbm", "achieved": round(a16, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(a16 / HBM_PEAK_GBS, 4), "kernel_ms": round(k16, 4)},
+            "n_candidates": stats16["n_cand"], "pulsar_recall_fp32": acc32,
+            "pulsar_recall_fp16": pulsar_recall(c16, spec),
+            "candidates_shared_with_fp32": len(keys32 & keys16),
+        }
+        del s16
     ctx.close()
     del stack
     torch.cuda.empty_cache()
+    if not args.no_serving:
+        print("[bench] serving replay", file=sys.stderr, flush=True)
+        out["serving"] = serving_replay(args.serving_requests, args.serving_slots, 40.0, args.serving_budget_gib, dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)

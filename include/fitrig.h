@@ -177,6 +177,72 @@ int32_t fitrig_phase_times(const fitrig_ctx* ctx, double* ms, int32_t cap);
 /* Library ABI version (FITRIG_ABI_VERSION of the build). */
 int32_t fitrig_abi_version(void);
 
+/* ---- serving form ----------------------------------------------------------
+ * A real-time trigger loop: requests are snapshot stacks of a field (a
+ * fixed sky position and image size). The server keeps each field's last two
+ * snapshots and its running maximum M resident on the device (the paper
+ * estimates M from past snapshots in real time, Sec. 2.2.4), so a request's
+ * first two triples reach back into the previous request and triples are
+ * numbered per field. Requests are admitted while a slot and the memory
+ * budget allow; admitted requests of different fields run concurrently on
+ * separate streams, requests of one field run in submission order. Each
+ * result is identical to running the same frames alone.
+ */
+typedef struct fitrig_server fitrig_server;
+
+typedef struct {
+  fitrig_config base;   /* index / selection settings of every request; its
+                           capacity hints size each slot's scratch up front */
+  int32_t n_slots;      /* requests on the device at once (default 4) */
+  int32_t max_fields;   /* fields with resident state (default 64) */
+  int64_t mem_budget;   /* device bytes for slot scratch plus field state; 0 = no limit */
+  int64_t cand_cap;     /* candidates kept per result (default 65536) */
+} fitrig_server_config;
+
+typedef struct {
+  int64_t ticket;
+  int64_t field_id;
+  fitrig_status status;     /* status of the run (as fitrig_detect) */
+  int32_t n_triples;        /* triples analysed, including those reaching into the previous request */
+  int64_t first_triple;     /* field-wide index of the first of them */
+  int64_t n_cand;           /* total candidates (records beyond cand_cap are not kept) */
+  const fitrig_candidate* cand; /* min(n_cand, cand_cap) records, owned by the server until released */
+  double M;                 /* running max(max over every frame of the field so far, C) */
+  int64_t t_submit_ns, t_start_ns, t_done_ns; /* steady-clock stamps: submit, launch, results on the host */
+} fitrig_result;
+
+/* Fills cfg with the defaults above. */
+void fitrig_server_config_default(fitrig_server_config* cfg);
+
+/* Creates the server: one context and stream per slot, worker threads.
+ * Errors: E_INVAL (null, bad base config, n_slots < 1, max_fields < 1,
+ * cand_cap < 0, mem_budget < 0), E_NOMEM, E_HIP. */
+fitrig_status fitrig_server_create(const fitrig_server_config* cfg, fitrig_server** out);
+
+/* Submits a stack (device, [n_snap][H][W], must stay valid and unchanged
+ * until the request is done). A field keeps its size and dtype; a request of
+ * another size or dtype resets the field's state. blocking = 1 waits for
+ * admission; blocking = 0 returns E_BUSY when the request does not fit now.
+ * *ticket identifies the request.
+ * Errors: E_INVAL (null, n_snap < 1, a field's first request with n_snap < 3,
+ * sizes as fitrig_detect, sigma not finite or <= 0, too many fields),
+ * E_BUSY (non-blocking and not admitted; also when the request alone exceeds
+ * mem_budget). */
+fitrig_status fitrig_submit(fitrig_server* srv, int64_t field_id, const void* stack, fitrig_dtype dtype,
+                            int32_t n_snap, int32_t H, int32_t W, double sigma, int32_t blocking,
+                            int64_t* ticket);
+
+/* Result of a ticket. wait = 1 blocks until it is done; wait = 0 returns
+ * E_NOTREADY while it runs. Errors: E_INVAL (unknown or released ticket). */
+fitrig_status fitrig_poll(fitrig_server* srv, int64_t ticket, int32_t wait, fitrig_result* out);
+
+/* Frees a finished ticket's result memory. Errors: E_INVAL (unknown ticket),
+ * E_NOTREADY (still running). */
+fitrig_status fitrig_release(fitrig_server* srv, int64_t ticket);
+
+/* Waits for every request, then frees the server. Errors: E_INVAL (null). */
+fitrig_status fitrig_server_destroy(fitrig_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,6 +3,6 @@
 The Python side only marshals arguments; see ``fitrig.py``.
 """
 from .fitrig import (  # noqa: F401
-    Context, FitrigError, fitrig_abi_version, fitrig_config_default, fitrig_create, fitrig_destroy,
+    Context, FitrigError, Server, fitrig_abi_version, fitrig_config_default, fitrig_create, fitrig_destroy,
     fitrig_detect, fitrig_last_hip_error, fitrig_phase_times, fitrig_status_string, load,
 )

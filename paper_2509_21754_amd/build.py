@@ -28,10 +28,11 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
-    src = os.path.join(CSRC, "fitrig_api.hip")
+    # fitrig_api.hip includes the kernels; fitrig_server.hip is the serving loop
+    srcs = [os.path.join(CSRC, "fitrig_api.hip"), os.path.join(CSRC, "fitrig_server.hip")]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           src, "-o", tmp]
+           *srcs, "-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -183,9 +183,12 @@ __global__ void k_stack_max(const T* p, int64_t n, uint32_t* max_key) {
 }
 
 struct Call {
-  const void* stack;
+  const void* stack;      // the new frames
+  const void* carry0;     // frames carried in front of them (serving), nullable
+  const void* carry1;
+  int ncarry;
   fitrig_dtype dtype;
-  int n, H, W;
+  int n, H, W;            // n = ncarry + new frames
   double tau;
   float* index_map;
   float* eta_map;
@@ -280,7 +283,7 @@ fitrig_status select_run(fitrig_ctx* ctx, const Call& c, const SegLayout& L, flo
     hipLaunchKernelGGL(k_fill_direct, dim3(gsel), dim3(64), 0, st, direct_vals, L, (const int64_t*)seg_entry,
                        (const int64_t*)(cnt + CNT_NSEL), cap, mu, sigma, c.tau, mask, cq);
   } else {
-    RecomputeArgs R{c.stack, nullptr, nullptr, 0, (int64_t)c.H * c.W, c.H, c.W, (float)ctx->cfg.C,
+    RecomputeArgs R{c.stack, c.carry0, c.carry1, c.ncarry, (int64_t)c.H * c.W, c.H, c.W, (float)ctx->cfg.C,
                     ctx->cfg.r_signed};
 #define RC(T, RS) \
   launch_recompute<T, RS>(halo, dim3(gsel), st, R, L, seg_entry, cnt + CNT_NSEL, cap, mu, sigma, c.tau, mask, cq)
@@ -351,8 +354,9 @@ template <typename T>
 fitrig_status run_tile_kernel(fitrig_ctx* ctx, const Call& c, int tile, int Ty, int nchunk, int pieces) {
   TileArgs A;
   A.base = c.stack;
-  A.carry0 = A.carry1 = nullptr;
-  A.ncarry = 0;
+  A.carry0 = c.carry0;
+  A.carry1 = c.carry1;
+  A.ncarry = c.ncarry;
   A.n = c.n;
   A.plane = (int64_t)c.H * c.W;
   A.H = c.H;
@@ -435,8 +439,9 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     }
     StreamArgs A;
     A.base = c.stack;
-    A.carry0 = A.carry1 = nullptr;
-    A.ncarry = 0;
+    A.carry0 = c.carry0;
+    A.carry1 = c.carry1;
+    A.ncarry = c.ncarry;
     A.n = c.n;
     A.plane = plane;
     A.H = c.H;
@@ -511,16 +516,16 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     uint32_t* mk = (uint32_t*)ctx->max_key.p;
     switch (c.dtype) {
       case FITRIG_F32:
-        hipLaunchKernelGGL(k_stack_max<float>, dim3(g), dim3(256), 0, st, (const float*)c.stack, (int64_t)c.n * plane,
+        hipLaunchKernelGGL(k_stack_max<float>, dim3(g), dim3(256), 0, st, (const float*)c.stack, (int64_t)(c.n - c.ncarry) * plane,
                            mk);
         break;
       case FITRIG_F16:
         hipLaunchKernelGGL(k_stack_max<__half>, dim3(g), dim3(256), 0, st, (const __half*)c.stack,
-                           (int64_t)c.n * plane, mk);
+                           (int64_t)(c.n - c.ncarry) * plane, mk);
         break;
       default:
         hipLaunchKernelGGL(k_stack_max<bf16_t>, dim3(g), dim3(256), 0, st, (const bf16_t*)c.stack,
-                           (int64_t)c.n * plane, mk);
+                           (int64_t)(c.n - c.ncarry) * plane, mk);
         break;
     }
     if ((rc = mark(1)) != FITRIG_OK) return rc;
@@ -790,6 +795,8 @@ fitrig_status fitrig_detect(fitrig_ctx* ctx, const void* stack, fitrig_dtype dty
   if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FITRIG_E_HIP;
   Call c;
   c.stack = stack;
+  c.carry0 = c.carry1 = nullptr;
+  c.ncarry = 0;
   c.dtype = dtype;
   c.n = n_snap;
   c.H = H;
@@ -802,3 +809,56 @@ fitrig_status fitrig_detect(fitrig_ctx* ctx, const void* stack, fitrig_dtype dty
 }
 
 }  // extern "C"
+
+namespace fitrig {
+
+// Detect over [carried frames][new frames] (serving). The carried frames
+// have the dtype and size of the stack.
+fitrig_status detect_frames(fitrig_ctx* ctx, const void* carry0, const void* carry1, int ncarry, const void* stack,
+                            fitrig_dtype dtype, int32_t n_new, int32_t H, int32_t W, double sigma,
+                            fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand, fitrig_stats* stats,
+                            void* hip_stream) {
+  if (!ctx || !stack || !n_cand || ncarry < 0 || ncarry > 2) return FITRIG_E_INVAL;
+  if ((ncarry >= 1 && !carry0) || (ncarry == 2 && !carry1)) return FITRIG_E_INVAL;
+  if (dtype != FITRIG_F32 && dtype != FITRIG_F16 && dtype != FITRIG_BF16) return FITRIG_E_INVAL;
+  if (n_new < 1 || ncarry + n_new < 3 || H < 1 || W < 1) return FITRIG_E_INVAL;
+  if ((uint64_t)H * (uint64_t)W >= (1ull << 32)) return FITRIG_E_INVAL;
+  if (!(sigma > 0.0) || !isfinite(sigma)) return FITRIG_E_INVAL;
+  if (cand_cap < 0 || (cand_cap > 0 && !cand)) return FITRIG_E_INVAL;
+  *n_cand = 0;
+  if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FITRIG_E_HIP;
+  Call c;
+  c.stack = stack;
+  c.carry0 = carry0;
+  c.carry1 = carry1;
+  c.ncarry = ncarry;
+  c.dtype = dtype;
+  c.n = ncarry + n_new;
+  c.H = H;
+  c.W = W;
+  c.tau = sigma;
+  c.index_map = nullptr;
+  c.eta_map = nullptr;
+  c.st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+  return detect_impl(ctx, c, cand, cand_cap, n_cand, stats);
+}
+
+hipStream_t ctx_stream(fitrig_ctx* ctx) { return ctx->stream; }
+int32_t& ctx_last_hip(fitrig_ctx* ctx) { return ctx->last_hip; }
+
+// Device bytes a context needs for one call of this size (admission).
+int64_t scratch_estimate(const fitrig_config& cfg, int n, int H, int W) {
+  const int64_t np = n - 2, plane = (int64_t)H * W;
+  const int out_w = out_width(cfg.window / 2);
+  const int64_t ncol = (W + out_w - 1) / out_w, nbands = (H + kBand - 1) / kBand;
+  const int64_t nwg = ncol * nbands;
+  const int64_t nseg = np * H * ncol * kSegsPerGroup;
+  const int64_t segcap = cfg.max_segments > 0 ? cfg.max_segments : std::max<int64_t>(65536, std::min<int64_t>(nseg / 64, 1 << 22));
+  const int64_t Ty = (H + cfg.tile - 1) / cfg.tile, Tx = (W + cfg.tile - 1) / cfg.tile;
+  int64_t b = np * nwg * 256 + nseg * 4 + np * nbands * ncol * kPieces * 24 + np * Ty * Tx * 12;
+  b += segcap * (8 + 8 + 64 * 12) + 2 * segcap * (4 + 4 + 8 + 48 + 16 + 2 * (int64_t)sizeof(fitrig_candidate));
+  if (cfg.sigma_est == FITRIG_MEDIAN_MAD) b += np * plane * 4;
+  return b;
+}
+
+}  // namespace fitrig

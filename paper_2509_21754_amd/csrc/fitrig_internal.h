@@ -101,3 +101,16 @@ struct SelBuffers {
 };
 
 }  // namespace fitrig
+
+#include "fitrig.h"
+
+namespace fitrig {
+// Host-side entry points shared between translation units of the library.
+fitrig_status detect_frames(fitrig_ctx* ctx, const void* carry0, const void* carry1, int ncarry, const void* stack,
+                            fitrig_dtype dtype, int32_t n_new, int32_t H, int32_t W, double sigma,
+                            fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand, fitrig_stats* stats,
+                            void* hip_stream);
+hipStream_t ctx_stream(fitrig_ctx* ctx);
+int32_t& ctx_last_hip(fitrig_ctx* ctx);
+int64_t scratch_estimate(const fitrig_config& cfg, int n, int H, int W);
+}  // namespace fitrig

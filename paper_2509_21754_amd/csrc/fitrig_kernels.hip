@@ -187,11 +187,25 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 // the reference pixel (Eqs. (3)-(5)). RS selects the literal signed reading
 // of Eq. (4); otherwise the ratio uses |x_hat| and is clamped to [0, 1].
 template <bool RS>
-__device__ __forceinline__ void pix_terms(float d_new, float d_old, float ref, float Cf, float& dl, float& rl) {
-  dl = fabsf(fabsf(d_new) - fabsf(d_old));
+__device__ __forceinline__ void pix_ratio(float dl, float ref, float Cf, float& rl) {
   const float den = (ref == 0.0f) ? Cf : ref;
   // dl >= 0, so for |x_hat| the product is already >= 0 and min(., 1) is the clamp
   rl = fminf(dl * __builtin_amdgcn_rcpf(RS ? den : fabsf(den)), 1.0f);
+}
+
+template <bool RS>
+__device__ __forceinline__ void pix_terms(float d_new, float d_old, float ref, float Cf, float& dl, float& rl) {
+  dl = fabsf(fabsf(d_new) - fabsf(d_old));
+  pix_ratio<RS>(dl, ref, Cf, rl);
+}
+
+// Same terms, Delta returned signed: Delta = |dd| (the absolute value is
+// applied where it is consumed, as a source modifier).
+template <bool RS>
+__device__ __forceinline__ void pix_terms_signed(float d_new, float d_old, float ref, float Cf, float& dd,
+                                                 float& rl) {
+  dd = fabsf(d_new) - fabsf(d_old);
+  pix_ratio<RS>(fabsf(dd), ref, Cf, rl);
 }
 
 // 1 / n^2 for a window of n in-image cells (n = rows * cols).
@@ -257,6 +271,53 @@ struct WinMax {
           }
         }
         o[c] = __uint_as_float(m);
+      }
+    }
+  }
+};
+
+// Window maximum of |a| for register values produced by arithmetic (so no
+// NaN canonicalisation is needed); the absolute value folds into the max3
+// source modifiers. Same tripling as WinMax; max is exact in any order.
+template <int H, int NOUT>
+struct WinMaxAbs {
+  static constexpr int L = 2 * H + 1;
+  static constexpr int NIN = NOUT + 2 * H;
+  __device__ static __forceinline__ float m3(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
+  __device__ static __forceinline__ void run(const float* a, float* o) {
+    if constexpr (L == 1) {
+#pragma unroll
+      for (int c = 0; c < NOUT; ++c) o[c] = fabsf(a[c]);
+    } else {
+      float t3[NIN > 2 ? NIN - 2 : 1];
+#pragma unroll
+      for (int j = 0; j + 2 < NIN; ++j) t3[j] = m3(fabsf(a[j]), fabsf(a[j + 1]), fabsf(a[j + 2]));
+#pragma unroll
+      for (int c = 0; c < NOUT; ++c) {
+        float acc[8];
+        int nt = 0, p = c;
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+          if (p + 2 <= c + L - 1) {
+            acc[nt++] = t3[p];
+            p += 3;
+          }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (p <= c + L - 1) acc[nt++] = fabsf(a[p++]);
+        float m = acc[0];
+        int i = 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (i + 1 < nt) {
+            m = m3(m, acc[i], acc[i + 1]);
+            i += 2;
+          } else if (i < nt) {
+            m = fmaxf(m, acc[i]);
+            i += 1;
+          }
+        }
+        o[c] = m;
       }
     }
   }
@@ -358,19 +419,24 @@ struct Stream {
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
         DO[i] = C[i] - P[i];
-        pix_terms<RS>(DO[i], DI[i], P[i], A.Cf, dl[i], rl[i]);
+        pix_terms_signed<RS>(DO[i], DI[i], P[i], A.Cf, dl[i], rl[i]);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < NR; ++i) DO[i] = C[i] - P[i];
     }
-    if (k + 1 < A.n) load<ALLROWS>(k + 1, P);
+    // the next frame's loads go straight into P (after the last frame the
+    // same frame is re-read from cache: an unconditional load avoids copies)
+    load<ALLROWS>(k + 1 < A.n ? k + 1 : k, P);
     if (k < 2) return;
     const int s = k - 2;
     {
       float vs[kBand], vm[kBand], vr[kBand], ts[kBand / 8], tr[kBand / 8];
-      Win<H, kBand, false>::run(dl, vs, ts);
-      WinMax<H, kBand>::run(dl, vm);
+      float al[NR];
+#pragma unroll
+      for (int i = 0; i < NR; ++i) al[i] = fabsf(dl[i]);
+      Win<H, kBand, false>::run(al, vs, ts);
+      WinMaxAbs<H, kBand>::run(dl, vm);
       Win<H, kBand, false>::run(rl, vr, tr);
 #pragma unroll
       for (int c = 0; c < kBand; ++c) {
@@ -381,10 +447,9 @@ struct Stream {
       if (A.tile_part) {
         const int ox = lane - H;
         if (ox >= 0 && ox < A.out_w) {
-          uint32_t mb = __float_as_uint(dl[H]);
+          float m = fabsf(dl[H]);
 #pragma unroll
-          for (int i = 1; i < kBand; ++i) mb = max(mb, __float_as_uint(dl[H + i]));
-          const float m = __uint_as_float(mb);
+          for (int i = 1; i < kBand; ++i) m = fmaxf(m, fabsf(dl[H + i]));
           sh.col[0][CPAD + ox] = ts[0] + ts[1];
           sh.col[1][CPAD + ox] = m;
           sh.col[2][CPAD + ox] = tr[0] + tr[1];

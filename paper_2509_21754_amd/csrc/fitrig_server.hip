@@ -1,0 +1,331 @@
+// FITrig serving form: a trigger loop over fields (sky position + image size).
+//
+// Per field the server keeps the last two snapshots (device) and the running
+// maximum M, so every request continues the field's sequence of triples and
+// its M estimate from past snapshots (the paper's real-time rule for M,
+// Sec. 2.2.4). Requests are admitted while the memory budget allows
+// (estimated slot scratch of the running and queued requests plus the
+// resident field state); admitted requests wait for one of n_slots worker
+// slots, each with its own context and HIP stream, so requests of different
+// fields run concurrently on the device. A field's requests run in
+// submission order. Results are bitwise those of running the same frames
+// alone (the kernels are deterministic and each slot owns its scratch).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "fitrig.h"
+#include "fitrig_internal.h"
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+size_t dtype_bytes(fitrig_dtype d) { return d == FITRIG_F32 ? 4 : 2; }
+
+struct Req {
+  int64_t ticket = 0, field = 0;
+  const void* stack = nullptr;
+  fitrig_dtype dtype = FITRIG_F32;
+  int n = 0, H = 0, W = 0;
+  double tau = 0.0;
+  int64_t mem = 0;  // admission charge while queued or running
+  int64_t t_submit = 0, t_start = 0, t_done = 0;
+  bool done = false;
+  fitrig_status status = FITRIG_OK;
+  std::vector<fitrig_candidate> cand;
+  int64_t n_cand = 0;
+  int n_triples = 0;
+  int64_t first_triple = 0;
+  double M = 0.0;
+};
+
+struct Field {
+  int H = 0, W = 0;
+  fitrig_dtype dtype = FITRIG_F32;
+  char* carry = nullptr;     // two frames on the device
+  size_t frame_bytes = 0;
+  int ncarry = 0;            // frames held (0..2) once every submitted request has run
+  int64_t frames_seen = 0;   // frames of finished requests
+  int64_t frames_submitted = 0;
+  double M = -INFINITY;
+  bool busy = false;         // a request of this field is ready or running
+  std::deque<int64_t> pending;
+};
+
+}  // namespace
+
+struct fitrig_server {
+  fitrig_server_config cfg;
+  std::mutex mu;
+  std::condition_variable cv_ready, cv_done;
+  std::deque<int64_t> ready;
+  std::unordered_map<int64_t, Req*> reqs;
+  std::unordered_map<int64_t, Field> fields;
+  std::vector<std::thread> workers;
+  std::vector<fitrig_ctx*> ctxs;
+  int64_t next_ticket = 1;
+  int64_t mem_charged = 0;  // queued + running requests
+  int64_t mem_fields = 0;   // resident field state
+  int outstanding = 0;      // admitted, not finished
+  bool stop = false;
+};
+
+namespace {
+
+void worker_main(fitrig_server* S, int slot) {
+  fitrig_ctx* ctx = S->ctxs[slot];
+  std::vector<fitrig_candidate> buf((size_t)std::max<int64_t>(S->cfg.cand_cap, 1));
+  for (;;) {
+    Req* r = nullptr;
+    const void *c0 = nullptr, *c1 = nullptr;
+    int nc = 0;
+    int64_t first = 0;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_ready.wait(lk, [&] { return S->stop || !S->ready.empty(); });
+      if (S->ready.empty()) return;
+      const int64_t t = S->ready.front();
+      S->ready.pop_front();
+      r = S->reqs[t];
+      Field& f = S->fields[r->field];
+      nc = f.ncarry;
+      if (nc >= 1) c0 = f.carry + (2 - nc) * f.frame_bytes;
+      if (nc == 2) c1 = f.carry + f.frame_bytes;
+      first = f.frames_seen - nc;
+    }
+    r->t_start = now_ns();
+    fitrig_stats st;
+    memset(&st, 0, sizeof(st));
+    int64_t ncand = 0;
+    fitrig_status rc = fitrig::detect_frames(ctx, c0, c1, nc, r->stack, r->dtype, r->n, r->H, r->W, r->tau,
+                                             buf.data(), S->cfg.cand_cap, &ncand, &st, nullptr);
+    // the field keeps the last two frames of [carried | new]
+    Field* fp;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      fp = &S->fields[r->field];
+    }
+    const size_t fb = fp->frame_bytes;
+    hipStream_t hs = fitrig::ctx_stream(ctx);
+    hipError_t he = hipSuccess;
+    if (r->n >= 2) {
+      he = hipMemcpyAsync(fp->carry, (const char*)r->stack + (size_t)(r->n - 2) * fb, 2 * fb,
+                          hipMemcpyDeviceToDevice, hs);
+    } else {  // one new frame: [previous newest, new]
+      if (nc >= 1)
+        he = hipMemcpyAsync(fp->carry, fp->carry + fb, fb, hipMemcpyDeviceToDevice, hs);
+      if (he == hipSuccess)
+        he = hipMemcpyAsync(fp->carry + fb, r->stack, fb, hipMemcpyDeviceToDevice, hs);
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(hs);
+    if (he != hipSuccess && (rc == FITRIG_OK || rc == FITRIG_E_TRUNC)) {
+      fitrig::ctx_last_hip(ctx) = (int32_t)he;
+      rc = FITRIG_E_HIP;
+    }
+    const int64_t kept = std::min<int64_t>(ncand, S->cfg.cand_cap);
+    r->cand.assign(buf.begin(), buf.begin() + kept);
+    for (fitrig_candidate& c : r->cand)  // field-wide triple numbers
+      if (c.branch == FITRIG_IMAGE) c.triple = (int32_t)(c.triple + first);
+    r->t_done = now_ns();
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      Field& f = S->fields[r->field];
+      r->status = rc;
+      r->n_cand = ncand;
+      r->n_triples = nc + r->n - 2 > 0 ? nc + r->n - 2 : 0;
+      r->first_triple = first;
+      f.M = fmax(f.M, st.M);
+      r->M = f.M;
+      f.frames_seen += r->n;
+      f.ncarry = (int)std::min<int64_t>(2, nc + r->n);
+      S->mem_charged -= r->mem;
+      S->outstanding -= 1;
+      r->done = true;
+      f.busy = false;
+      if (!f.pending.empty()) {
+        S->ready.push_back(f.pending.front());
+        f.pending.pop_front();
+        f.busy = true;
+        S->cv_ready.notify_one();
+      }
+    }
+    S->cv_done.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void fitrig_server_config_default(fitrig_server_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  fitrig_config_default(&cfg->base);
+  cfg->n_slots = 4;
+  cfg->max_fields = 64;
+  cfg->mem_budget = 0;
+  cfg->cand_cap = 65536;
+}
+
+fitrig_status fitrig_server_create(const fitrig_server_config* cfg, fitrig_server** out) {
+  if (!cfg || !out) return FITRIG_E_INVAL;
+  *out = nullptr;
+  if (cfg->n_slots < 1 || cfg->n_slots > 64 || cfg->max_fields < 1 || cfg->cand_cap < 0 || cfg->mem_budget < 0)
+    return FITRIG_E_INVAL;
+  fitrig_server* S = new (std::nothrow) fitrig_server();
+  if (!S) return FITRIG_E_NOMEM;
+  S->cfg = *cfg;
+  S->cfg.base.profile = 0;
+  for (int i = 0; i < cfg->n_slots; ++i) {
+    fitrig_ctx* c = nullptr;
+    const fitrig_status rc = fitrig_create(&S->cfg.base, &c);
+    if (rc != FITRIG_OK) {
+      for (fitrig_ctx* x : S->ctxs) fitrig_destroy(x);
+      delete S;
+      return rc;
+    }
+    S->ctxs.push_back(c);
+  }
+  for (int i = 0; i < cfg->n_slots; ++i) S->workers.emplace_back(worker_main, S, i);
+  *out = S;
+  return FITRIG_OK;
+}
+
+fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stack, fitrig_dtype dtype, int32_t n_snap,
+                            int32_t H, int32_t W, double sigma, int32_t blocking, int64_t* ticket) {
+  if (!S || !stack || !ticket) return FITRIG_E_INVAL;
+  if (dtype != FITRIG_F32 && dtype != FITRIG_F16 && dtype != FITRIG_BF16) return FITRIG_E_INVAL;
+  if (n_snap < 1 || H < 1 || W < 1 || (uint64_t)H * (uint64_t)W >= (1ull << 32)) return FITRIG_E_INVAL;
+  if (!(sigma > 0.0) || !isfinite(sigma)) return FITRIG_E_INVAL;
+  const int64_t t_submit = now_ns();
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->fields.find(field_id);
+  const bool fresh = it == S->fields.end();
+  if (fresh && (int64_t)S->fields.size() >= S->cfg.max_fields) return FITRIG_E_INVAL;
+  Field* f = fresh ? nullptr : &it->second;
+  const bool resize = f && (f->H != H || f->W != W || f->dtype != dtype);
+  if (resize && (f->busy || !f->pending.empty())) return FITRIG_E_INVAL;
+  const int64_t carried = (f && !resize) ? std::min<int64_t>(2, f->frames_submitted) : 0;
+  if (carried + n_snap < 3) return FITRIG_E_INVAL;
+  const size_t fb = (size_t)H * W * dtype_bytes(dtype);
+  const int64_t field_mem = (fresh || resize) ? (int64_t)(2 * fb) : 0;
+  const int64_t mem = fitrig::scratch_estimate(S->cfg.base, (int)(carried + n_snap), H, W);
+  const int64_t budget = S->cfg.mem_budget;
+  auto fits = [&] { return budget == 0 || S->mem_charged + S->mem_fields + field_mem + mem <= budget; };
+  if (budget > 0 && field_mem + mem + S->mem_fields > budget) return FITRIG_E_BUSY;
+  if (!fits()) {
+    if (!blocking) return FITRIG_E_BUSY;
+    S->cv_done.wait(lk, fits);
+  }
+  // (re)create the field state
+  if (fresh || resize) {
+    Field& nf = S->fields[field_id];
+    if (nf.carry) {
+      (void)hipFree(nf.carry);
+      S->mem_fields -= (int64_t)(2 * nf.frame_bytes);
+    }
+    nf = Field();
+    nf.H = H;
+    nf.W = W;
+    nf.dtype = dtype;
+    nf.frame_bytes = fb;
+    if (hipSetDevice(S->cfg.base.device) != hipSuccess || hipMalloc((void**)&nf.carry, 2 * fb) != hipSuccess) {
+      S->fields.erase(field_id);
+      return FITRIG_E_NOMEM;
+    }
+    S->mem_fields += (int64_t)(2 * fb);
+    f = &nf;
+  }
+  Req* r = new (std::nothrow) Req();
+  if (!r) return FITRIG_E_NOMEM;
+  r->ticket = S->next_ticket++;
+  r->field = field_id;
+  r->stack = stack;
+  r->dtype = dtype;
+  r->n = n_snap;
+  r->H = H;
+  r->W = W;
+  r->tau = sigma;
+  r->mem = mem;
+  r->t_submit = t_submit;
+  S->reqs[r->ticket] = r;
+  S->mem_charged += mem;
+  S->outstanding += 1;
+  f->frames_submitted += n_snap;
+  if (!f->busy) {
+    f->busy = true;
+    S->ready.push_back(r->ticket);
+    S->cv_ready.notify_one();
+  } else {
+    f->pending.push_back(r->ticket);
+  }
+  *ticket = r->ticket;
+  return FITRIG_OK;
+}
+
+fitrig_status fitrig_poll(fitrig_server* S, int64_t ticket, int32_t wait, fitrig_result* out) {
+  if (!S || !out) return FITRIG_E_INVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return FITRIG_E_INVAL;
+  Req* r = it->second;
+  if (!r->done) {
+    if (!wait) return FITRIG_E_NOTREADY;
+    S->cv_done.wait(lk, [&] { return r->done; });
+  }
+  out->ticket = r->ticket;
+  out->field_id = r->field;
+  out->status = r->status;
+  out->n_triples = r->n_triples;
+  out->first_triple = r->first_triple;
+  out->n_cand = r->n_cand;
+  out->cand = r->cand.empty() ? nullptr : r->cand.data();
+  out->M = r->M;
+  out->t_submit_ns = r->t_submit;
+  out->t_start_ns = r->t_start;
+  out->t_done_ns = r->t_done;
+  return FITRIG_OK;
+}
+
+fitrig_status fitrig_release(fitrig_server* S, int64_t ticket) {
+  if (!S) return FITRIG_E_INVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return FITRIG_E_INVAL;
+  if (!it->second->done) return FITRIG_E_NOTREADY;
+  delete it->second;
+  S->reqs.erase(it);
+  return FITRIG_OK;
+}
+
+fitrig_status fitrig_server_destroy(fitrig_server* S) {
+  if (!S) return FITRIG_E_INVAL;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->outstanding == 0; });
+    S->stop = true;
+  }
+  S->cv_ready.notify_all();
+  for (std::thread& t : S->workers) t.join();
+  for (fitrig_ctx* c : S->ctxs) fitrig_destroy(c);
+  for (auto& kv : S->fields)
+    if (kv.second.carry) (void)hipFree(kv.second.carry);
+  for (auto& kv : S->reqs) delete kv.second;
+  delete S;
+  return FITRIG_OK;
+}
+
+}  // extern "C"

@@ -82,6 +82,32 @@ class fitrig_stats(ctypes.Structure):
     ]
 
 
+class fitrig_server_config(ctypes.Structure):
+    _fields_ = [
+        ("base", fitrig_config),
+        ("n_slots", ctypes.c_int32),
+        ("max_fields", ctypes.c_int32),
+        ("mem_budget", ctypes.c_int64),
+        ("cand_cap", ctypes.c_int64),
+    ]
+
+
+class fitrig_result(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_int64),
+        ("field_id", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("n_triples", ctypes.c_int32),
+        ("first_triple", ctypes.c_int64),
+        ("n_cand", ctypes.c_int64),
+        ("cand", ctypes.POINTER(fitrig_candidate)),
+        ("M", ctypes.c_double),
+        ("t_submit_ns", ctypes.c_int64),
+        ("t_start_ns", ctypes.c_int64),
+        ("t_done_ns", ctypes.c_int64),
+    ]
+
+
 EXPORTS = (
     "fitrig_config_default",
     "fitrig_create",
@@ -91,6 +117,12 @@ EXPORTS = (
     "fitrig_last_hip_error",
     "fitrig_abi_version",
     "fitrig_phase_times",
+    "fitrig_server_config_default",
+    "fitrig_server_create",
+    "fitrig_submit",
+    "fitrig_poll",
+    "fitrig_release",
+    "fitrig_server_destroy",
 )
 N_PHASES = 5
 PHASES = ("index_pass", "spread", "image_select", "freq_branch", "host_copy")
@@ -124,6 +156,18 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fitrig_abi_version.restype = i32
     L.fitrig_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
     L.fitrig_phase_times.restype = i32
+    L.fitrig_server_config_default.argtypes = [ctypes.POINTER(fitrig_server_config)]
+    L.fitrig_server_config_default.restype = None
+    L.fitrig_server_create.argtypes = [ctypes.POINTER(fitrig_server_config), ctypes.POINTER(vp)]
+    L.fitrig_server_create.restype = i32
+    L.fitrig_submit.argtypes = [vp, i64, vp, i32, i32, i32, i32, dbl, i32, ctypes.POINTER(i64)]
+    L.fitrig_submit.restype = i32
+    L.fitrig_poll.argtypes = [vp, i64, i32, ctypes.POINTER(fitrig_result)]
+    L.fitrig_poll.restype = i32
+    L.fitrig_release.argtypes = [vp, i64]
+    L.fitrig_release.restype = i32
+    L.fitrig_server_destroy.argtypes = [vp]
+    L.fitrig_server_destroy.restype = i32
     _lib = L
     return L
 
@@ -172,6 +216,41 @@ def fitrig_phase_times(ctx) -> list:
     buf = (ctypes.c_double * N_PHASES)()
     n = load().fitrig_phase_times(ctx, buf, N_PHASES)
     return list(buf[:max(n, 0)])
+
+
+def fitrig_server_config_default(**overrides) -> fitrig_server_config:
+    cfg = fitrig_server_config()
+    load().fitrig_server_config_default(ctypes.byref(cfg))
+    for k, v in overrides.items():
+        if hasattr(cfg, k):
+            setattr(cfg, k, v)
+        elif hasattr(cfg.base, k):
+            setattr(cfg.base, k, v)
+        else:
+            raise KeyError(k)
+    return cfg
+
+
+def fitrig_server_create(cfg: fitrig_server_config) -> tuple[int, Optional[int]]:
+    h = ctypes.c_void_p()
+    rc = load().fitrig_server_create(ctypes.byref(cfg), ctypes.byref(h))
+    return rc, (h.value if rc == OK else None)
+
+
+def fitrig_submit(srv, field_id, stack_ptr, dtype, n_snap, H, W, sigma, blocking, ticket) -> int:
+    return load().fitrig_submit(srv, field_id, stack_ptr, dtype, n_snap, H, W, sigma, blocking, ticket)
+
+
+def fitrig_poll(srv, ticket, wait, out) -> int:
+    return load().fitrig_poll(srv, ticket, wait, out)
+
+
+def fitrig_release(srv, ticket) -> int:
+    return load().fitrig_release(srv, ticket)
+
+
+def fitrig_server_destroy(srv) -> int:
+    return load().fitrig_server_destroy(srv)
 
 
 # ---- torch convenience layer --------------------------------------------------
@@ -280,3 +359,77 @@ class Context:
                      flags=list(b["fl"][:np_]), eta_mu=st.eta_mu, eta_sigma=st.eta_sigma,
                      n_image_cand=st.n_image_cand, n_freq_cand=st.n_freq_cand, n_cand=ncand)
         return cands, stats, rc
+
+
+class Server:
+    """Owns a fitrig_server; stacks are device tensors that must stay alive
+    (and unchanged) until their ticket is done."""
+
+    def __init__(self, n_slots: int = 4, max_fields: int = 64, mem_budget: int = 0, cand_cap: int = 1 << 16,
+                 **base):
+        self.cfg = fitrig_server_config_default(n_slots=n_slots, max_fields=max_fields, mem_budget=mem_budget,
+                                                cand_cap=cand_cap, **base)
+        rc, h = fitrig_server_create(self.cfg)
+        if rc != OK:
+            raise FitrigError(rc, "fitrig_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, field_id: int, stack, sigma: float, blocking: bool = True):
+        """Ticket, or None when a non-blocking submit is not admitted."""
+        if not stack.is_cuda or not stack.is_contiguous() or stack.dim() != 3:
+            raise ValueError("stack must be a contiguous 3-D device tensor")
+        n, H, W = stack.shape
+        t = ctypes.c_int64()
+        rc = fitrig_submit(self.handle, int(field_id), ctypes.c_void_p(stack.data_ptr()), _dtype_code(stack), n, H,
+                           W, float(sigma), 1 if blocking else 0, ctypes.byref(t))
+        if rc == E_BUSY and not blocking:
+            return None
+        if rc != OK:
+            raise FitrigError(rc, "fitrig_submit")
+        self._keep[t.value] = stack
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True, as_dicts: bool = True):
+        """Result dict (candidates, timing), or None if not ready (wait=False)."""
+        import numpy as np
+
+        r = fitrig_result()
+        rc = fitrig_poll(self.handle, ticket, 1 if wait else 0, ctypes.byref(r))
+        if rc == E_NOTREADY:
+            return None
+        if rc != OK:
+            raise FitrigError(rc, "fitrig_poll")
+        k = min(r.n_cand, self.cfg.cand_cap)
+        if k and r.cand:
+            arr = np.ctypeslib.as_array(ctypes.cast(r.cand, ctypes.POINTER(fitrig_candidate * k)).contents).copy()
+        else:
+            arr = np.ctypeslib.as_array((fitrig_candidate * 1)())[:0].copy()
+        return dict(ticket=r.ticket, field_id=r.field_id, status=r.status, n_triples=r.n_triples,
+                    first_triple=r.first_triple, n_cand=r.n_cand, M=r.M,
+                    cands=[_rec_dict(x) for x in arr] if as_dicts else arr,
+                    t_submit_ns=r.t_submit_ns, t_start_ns=r.t_start_ns, t_done_ns=r.t_done_ns)
+
+    def release(self, ticket: int):
+        rc = fitrig_release(self.handle, ticket)
+        if rc != OK:
+            raise FitrigError(rc, "fitrig_release")
+        self._keep.pop(ticket, None)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fitrig_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

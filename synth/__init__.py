@@ -249,14 +249,15 @@ def spec(name: str, **over) -> StackSpec:
 def serving_requests(count: int, rate_hz: float = 40.0, seed: int = 1004,
                      sizes=(2048, 4096, 8192), lengths=(16, 32, 128), n_fields: int = 16):
     """Poisson arrivals for the serving workload: each request names a field
-    (fixed size class per field), a snapshot count and a storage dtype
-    (fp16 / fp32, 50 / 50)."""
+    (a fixed size class and storage dtype per field, fp16 / fp32 50 / 50) and a
+    snapshot count."""
     rng = np.random.default_rng(seed)
     field_size = rng.choice(sizes, n_fields)
+    field_dtype = np.where(rng.random(n_fields) < 0.5, "f16", "f32")
     t = np.cumsum(rng.exponential(1.0 / rate_hz, count))
     reqs = []
     for i in range(count):
         f = int(rng.integers(0, n_fields))
         reqs.append(dict(t=float(t[i]), field=f, size=int(field_size[f]),
-                         n=int(rng.choice(lengths)), dtype=("f16" if rng.random() < 0.5 else "f32")))
+                         n=int(rng.choice(lengths)), dtype=str(field_dtype[f])))
     return reqs

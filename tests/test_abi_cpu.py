@@ -35,11 +35,10 @@ def test_library_exports_every_declared_function():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "probe.c"
     exe = tmp_path / "probe"
-    fields = {
-        "fitrig_config": [f for f, _ in F.fitrig_config._fields_],
-        "fitrig_candidate": [f for f, _ in F.fitrig_candidate._fields_],
-        "fitrig_stats": [f for f, _ in F.fitrig_stats._fields_],
-    }
+    classes = {"fitrig_config": F.fitrig_config, "fitrig_candidate": F.fitrig_candidate,
+               "fitrig_stats": F.fitrig_stats, "fitrig_server_config": F.fitrig_server_config,
+               "fitrig_result": F.fitrig_result}
+    fields = {k: [f for f, _ in c._fields_] for k, c in classes.items()}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fitrig.h"', "int main(void){"]
     for s, fs in fields.items():
         lines.append(f'printf("{s} size %zu\\n", sizeof({s}));')
@@ -52,8 +51,7 @@ def test_struct_layout_matches_header(tmp_path):
     for line in subprocess.check_output([str(exe)], text=True).splitlines():
         a, b, c = line.split()
         got[(a, b)] = int(c)
-    for s, cls in (("fitrig_config", F.fitrig_config), ("fitrig_candidate", F.fitrig_candidate),
-                   ("fitrig_stats", F.fitrig_stats)):
+    for s, cls in classes.items():
         assert got[(s, "size")] == ctypes.sizeof(cls), s
         for f, _ in cls._fields_:
             assert got[(s, f)] == getattr(cls, f).offset, (s, f)
@@ -89,3 +87,16 @@ def test_detect_rejects_null_context():
                          None, None)
     assert rc == F.E_INVAL
     assert F.fitrig_destroy(None) == F.E_INVAL
+
+
+def test_server_rejects_bad_config_on_cpu():
+    for bad in (dict(n_slots=0), dict(max_fields=0), dict(cand_cap=-1), dict(mem_budget=-5), dict(window=2)):
+        rc, h = F.fitrig_server_create(F.fitrig_server_config_default(**bad))
+        assert rc == F.E_INVAL and h is None
+    t = ctypes.c_int64()
+    assert F.fitrig_submit(None, 0, ctypes.c_void_p(1), F.F32, 3, 4, 4, 6.0, 1, ctypes.byref(t)) == F.E_INVAL
+    assert F.fitrig_poll(None, 1, 0, ctypes.byref(F.fitrig_result())) == F.E_INVAL
+    assert F.fitrig_release(None, 1) == F.E_INVAL
+    assert F.fitrig_server_destroy(None) == F.E_INVAL
+    c = F.fitrig_server_config_default()
+    assert (c.n_slots, c.max_fields, c.mem_budget, c.cand_cap, c.base.window) == (4, 64, 0, 65536, 7)

@@ -1,0 +1,113 @@
+"""GPU tests of the serving form through the C ABI: every result of a mix of
+fields served concurrently equals the same frames (the field's two carried
+snapshots followed by the request's) run alone through fitrig_detect, and
+matches the FP64 oracle; requests of a field run in order; admission by
+memory."""
+import numpy as np
+import pytest
+
+from oracle import ref
+from parity import check_candidates, structured_stack
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DT = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+
+
+def _alone(frames_t, tau, **cfg):
+    from paper_2509_21754_amd import Context
+
+    with Context(**cfg) as ctx:
+        cands, stats, rc = ctx.detect(frames_t, tau, as_dicts=False)
+    return cands, stats, rc
+
+
+def _plan(seed):
+    """Fields (H, W, dtype) and an interleaved list of (field, n_new)."""
+    rng = np.random.default_rng(seed)
+    fields = {0: (70, 300, "f32"), 1: (33, 530, "f16"), 2: (64, 256, "f32"), 3: (5, 7, "bf16"),
+              4: (128, 260, "f32")}
+    reqs = []
+    left = {f: 4 for f in fields}
+    first = {f: True for f in fields}
+    while any(left.values()):
+        f = int(rng.choice([k for k, v in left.items() if v]))
+        n = int(rng.integers(3, 7)) if first[f] else int(rng.integers(1, 6))
+        first[f] = False
+        left[f] -= 1
+        reqs.append((f, n))
+    return fields, reqs
+
+
+@pytest.mark.parametrize("branches", [1, 3])
+def test_server_mix_equals_alone(branches):
+    from paper_2509_21754_amd import Server
+
+    tau = 4.0
+    cfg = dict(window=5, branches=branches, tile=16)
+    fields, reqs = _plan(7 + branches)
+    frames = {f: [] for f in fields}   # every frame submitted so far, host float copies
+    submitted = []
+    keep = []
+    with Server(n_slots=3, max_fields=8, **cfg) as srv:
+        for i, (f, n) in enumerate(reqs):
+            H, W, dt = fields[f]
+            X = structured_stack(100 * f + i, n, H, W)
+            t = torch.from_numpy(X).to(DT[dt]).cuda()
+            torch.cuda.synchronize()
+            keep.append(t)
+            prev = frames[f][-2:]
+            used = t.float().cpu().numpy()
+            frames[f].extend(list(used))
+            tk = srv.submit(f, t, tau)
+            submitted.append((tk, f, len(frames[f]) - n - len(prev), np.stack(prev + list(used)), dt))
+        results = [srv.poll(tk, as_dicts=False) for tk, *_ in submitted]
+        done = {tk: r for (tk, *_), r in zip(submitted, results)}
+        for (tk, f, first, used, dt), r in zip(submitted, results):
+            assert r["status"] in (0, -4), r["status"]
+            assert r["field_id"] == f
+            assert r["first_triple"] == first
+            assert r["n_triples"] == used.shape[0] - 2
+            frames_t = torch.from_numpy(used).to(DT[dt]).cuda()
+            alone, stats, rc = _alone(frames_t, tau, **cfg)
+            got = r["cands"].copy()
+            img = got["branch"] == ref.IMAGE
+            got["triple"][img] -= first
+            assert got.tobytes() == alone.tobytes(), (tk, f)
+            # the running M covers every frame of the field so far and C
+            seen = np.stack(frames[f][:first + used.shape[0]])
+            assert r["M"] == max(float(seen.max()), 1e-6)
+            out = ref.detect(used.astype(np.float64), tau=tau, window=5, branches=branches, tile=16)
+            from paper_2509_21754_amd.fitrig import _rec_dict
+            check_candidates([_rec_dict(x) for x in alone], out, tau)
+        # per-field submission order
+        for f in fields:
+            mine = [done[tk] for tk, ff, *_ in submitted if ff == f]
+            for a, b in zip(mine, mine[1:]):
+                assert b["t_start_ns"] >= a["t_done_ns"]
+                assert b["first_triple"] == a["first_triple"] + a["n_triples"]
+        for tk, *_ in submitted:
+            srv.release(tk)
+
+
+def test_server_admission_by_memory():
+    from paper_2509_21754_amd import FitrigError, Server
+
+    X = torch.from_numpy(structured_stack(5, 4, 40, 300)).cuda()
+    with Server(n_slots=2, mem_budget=1024, window=5) as srv:
+        assert srv.submit(0, X, 5.0, blocking=False) is None
+        with pytest.raises(FitrigError):
+            srv.submit(0, X, 5.0, blocking=True)     # alone larger than the budget
+    with Server(n_slots=2, window=5) as srv:
+        tk = srv.submit(0, X, 5.0)
+        r = srv.poll(tk)
+        assert r["status"] == 0
+        srv.release(tk)
+        with pytest.raises(FitrigError):
+            srv.poll(tk)
+        with pytest.raises(FitrigError):
+            srv.submit(1, X[:2].contiguous(), 5.0)    # a field's first request needs three frames
+        tk2 = srv.submit(0, X[:1].contiguous(), 5.0)  # later requests may bring a single frame
+        r2 = srv.poll(tk2)
+        assert r2["n_triples"] == 1 and r2["first_triple"] == 2
