@@ -124,6 +124,117 @@ def pctl(v, p):
     return srt[min(len(srt) - 1, int(round(p * (len(srt) - 1))))]
 
 
+CROP = 2048
+N_CROPS = 64
+
+
+def crop_origins(H: int, W: int) -> list:
+    """Seeded crop origins (seeds 0..63), multiples of 16 so that the block
+    structure of the window sums in a crop run lines up with the full image
+    and interior q values are the full image's bit for bit."""
+    import numpy as np
+
+    out = []
+    for i in range(N_CROPS):
+        rng = np.random.default_rng(i)
+        out.append((16 * int(rng.integers(0, (H - CROP) // 16 + 1)), 16 * int(rng.integers(0, (W - CROP) // 16 + 1))))
+    return out
+
+
+def _component_at(q2, mu, sg, tau, py, px):
+    """The oracle's 8-connected component of {z > tau} holding (py, px)."""
+    import numpy as np
+    from scipy import ndimage
+
+    from oracle import ref
+
+    comps, mask = ref.components(q2, mu, sg, tau, with_mask=True)
+    if not mask[py, px]:
+        return None
+    lab, _ = ndimage.label(mask, structure=np.ones((3, 3)))
+    first = int(np.flatnonzero(lab.ravel() == lab[py, px])[0])
+    return next(d for d in comps if d["label"] == first)
+
+
+def precision_report(spec, stack, raw, origins, stats, cands) -> dict:
+    """Error of the FP16-storage path against the FP64 oracle on seeded
+    crops, stated twice: algorithmic (oracle on the same decoded FP16 input)
+    and total (oracle on the values before rounding to FP16). q is compared on
+    crop-interior cells; candidates of the full-image run that lie inside a
+    crop's interior are compared with the oracle's components built with the
+    full-image mean and std."""
+    import numpy as np
+    import torch
+
+    from oracle import ref
+    from paper_2509_21754_amd import Context
+
+    h = spec.window // 2
+    tau = spec.taus[0]
+    n = spec.n
+    lo, hi = h, CROP - h
+    alg_rel, tot_rel = [], []
+    alg_bad = 0
+    cells = 0
+    cand_cmp = {"checked": 0, "identical_alg": 0, "near_threshold_skipped": 0, "found_in_total": 0}
+    img = cands[cands["branch"] == 1]
+    t0 = time.perf_counter()
+    with Context(window=spec.window) as ctx:
+        for i, (oy, ox) in enumerate(origins):
+            sub = stack[:, oy:oy + CROP, ox:ox + CROP].contiguous()
+            qg = torch.empty((n - 2, CROP, CROP), dtype=torch.float32, device=sub.device)
+            ctx.detect(sub, tau, index_map=qg, as_dicts=False)
+            qg = qg[:, lo:hi, lo:hi].cpu().numpy().astype(np.float64)
+            dec = sub.float().cpu().numpy()
+            pre = raw[i].cpu().numpy()
+            qd = ref.index_maps(dec, window=spec.window)[:, lo:hi, lo:hi]
+            qt = ref.index_maps(pre, window=spec.window)[:, lo:hi, lo:hi]
+            for s in range(n - 2):
+                atol = 1e-7 * float(qd[s].mean())
+                e_alg = np.abs(qg[s] - qd[s]) / (np.abs(qd[s]) + atol)
+                e_tot = np.abs(qg[s] - qt[s]) / (np.abs(qt[s]) + atol)
+                alg_bad += int(np.count_nonzero(np.abs(qg[s] - qd[s]) > 1e-5 * np.abs(qd[s]) + atol))
+                alg_rel.append(np.quantile(e_alg, [0.5, 0.99, 1.0]))
+                tot_rel.append(np.quantile(e_tot, [0.5, 0.99, 1.0]))
+                cells += qd[s].size
+            # candidates of the full-image run inside this crop's interior
+            inside = img[(img["y0"] >= oy + lo + 1) & (img["y1"] < oy + hi - 1) &
+                         (img["x0"] >= ox + lo + 1) & (img["x1"] < ox + hi - 1)]
+            for c in inside:
+                s = int(c["triple"])
+                mu, sg = stats["mu"][s], stats["sigma"][s]
+                # the candidate's box grown by one cell, in interior coordinates
+                y0, y1 = int(c["y0"]) - oy - lo - 1, int(c["y1"]) - oy - lo + 2
+                x0, x1 = int(c["x0"]) - ox - lo - 1, int(c["x1"]) - ox - lo + 2
+                if np.any(np.abs((qd[s][y0:y1, x0:x1] - mu) / sg - tau) <= 1e-4):
+                    cand_cmp["near_threshold_skipped"] += 1
+                    continue
+                cand_cmp["checked"] += 1
+                py, px = int(c["peak_y"]) - oy - lo - y0, int(c["peak_x"]) - ox - lo - x0
+                d = _component_at(qd[s][y0:y1, x0:x1], mu, sg, tau, py, px)
+                if d is not None and (d["n_pix"], d["y0"] + y0, d["x0"] + x0, d["y1"] + y0, d["x1"] + x0,
+                                      d["peak_y"], d["peak_x"]) == (
+                        int(c["n_pix"]), int(c["y0"]) - oy - lo, int(c["x0"]) - ox - lo, int(c["y1"]) - oy - lo,
+                        int(c["x1"]) - ox - lo, py, px):
+                    cand_cmp["identical_alg"] += 1
+                if _component_at(qt[s][y0:y1, x0:x1], mu, sg, tau, py, px) is not None:
+                    cand_cmp["found_in_total"] += 1
+            if (i + 1) % 8 == 0:
+                print(f"[bench] precision report: {i + 1}/{len(origins)} crops, {time.perf_counter() - t0:.0f} s",
+                      file=sys.stderr, flush=True)
+    A = np.array(alg_rel)
+    T = np.array(tot_rel)
+    return {
+        "crops": f"{len(origins)} seeded {CROP}x{CROP} crops (seeds 0..{len(origins) - 1}), interior cells",
+        "cells": cells,
+        "q_algorithmic_rel_err": {"median": float(np.median(A[:, 0])), "p99": float(np.max(A[:, 1])),
+                                  "max": float(np.max(A[:, 2])), "cells_outside_tolerance": alg_bad},
+        "q_total_rel_err": {"median": float(np.median(T[:, 0])), "p99": float(np.max(T[:, 1])),
+                            "max": float(np.max(T[:, 2]))},
+        "candidates": cand_cmp,
+    }
+
+
 def serving_replay(n_req: int, slots: int, rate_hz: float, budget_gib: float, dev) -> dict:
     """The serving workload: Poisson arrivals of snapshot stacks of 16 fields
     (size class 2048^2 / 4096^2 / 8192^2 and storage dtype fixed per field,
@@ -214,6 +325,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16-form", action="store_true", help="skip the FP16-storage run of the same stack")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving replay")
+    ap.add_argument("--no-precision-report", action="store_true",
+                    help="skip the crop error report of an FP16 / BF16 workload")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-budget-gib", type=float, default=48.0)
@@ -234,7 +347,16 @@ def main() -> int:
     torch.cuda.set_device(dev)
     print(f"[bench] generating {args.workload}: {spec.n}x{spec.H}x{spec.W} {spec.dtype}", file=sys.stderr,
           flush=True)
-    stack = synth.make_stack(spec, device=dev)
+    raw = origins = None
+    if spec.dtype != "f32" and not args.no_precision_report:
+        # keep crops of the values before rounding to the storage dtype
+        origins = crop_origins(spec.H, spec.W)
+        raw = torch.empty((len(origins), spec.n, CROP, CROP), dtype=torch.float32, device=dev)
+
+        def grab(k, frame):
+            for i, (oy, ox) in enumerate(origins):
+                raw[i, k].copy_(frame[oy:oy + CROP, ox:ox + CROP])
+    stack = synth.make_stack(spec, device=dev, on_frame=grab if raw is not None else None)
     torch.cuda.synchronize()
     if args.calibrate_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -304,6 +426,10 @@ def main() -> int:
             "candidates_shared_with_fp32": len(keys32 & keys16),
         }
         del s16
+    if raw is not None:
+        print("[bench] precision report on crops", file=sys.stderr, flush=True)
+        out["precision_report"] = precision_report(spec, stack, raw, origins, stats, cands)
+        del raw
     ctx.close()
     del stack
     torch.cuda.empty_cache()

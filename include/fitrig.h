@@ -135,7 +135,10 @@ fitrig_status fitrig_create(const fitrig_config* cfg, fitrig_ctx** out);
  *              [n_snap-2][ceil(H/tile)][ceil(W/tile)] (tiles)
  *   eta_map    device, nullable: [ceil(H/tile)][ceil(W/tile)] floats
  *   stats      host, nullable
- *   hip_stream hipStream_t to run on; NULL = the context's stream
+ *   hip_stream hipStream_t to run on; NULL = the context's stream, which
+ *              is a blocking stream: it starts after work queued earlier on
+ *              the legacy default stream (where the stack may have been
+ *              written) without further synchronisation by the caller
  * Candidates come in canonical order: image branch by (triple, label), then
  * the frequency branch by label. The call returns when every output is
  * written. Scratch grows (hipMalloc) when a stack exceeds the capacity

@@ -735,7 +735,9 @@ fitrig_status fitrig_create(const fitrig_config* cfg, fitrig_ctx** out) {
   if (!ctx) return FITRIG_E_NOMEM;
   ctx->cfg = *cfg;
   hipError_t e = hipSetDevice(cfg->device);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+  // blocking stream: ordered after the legacy default stream, where callers
+  // commonly produce the stack
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamDefault);
   for (int i = 0; e == hipSuccess && i <= FITRIG_N_PHASES; ++i) e = hipEventCreate(&ctx->ev[i]);
   if (e != hipSuccess) {
     fitrig_destroy(ctx);

@@ -198,8 +198,11 @@ def sky_model(spec: StackSpec) -> SkyModel:
 _TORCH_DT = {"f32": "float32", "f16": "float16", "bf16": "bfloat16"}
 
 
-def make_stack(spec: StackSpec, device="cpu", noise_sigma: float = 1.0):
-    """Materialise the stack [n][H][W] in the storage dtype on ``device``."""
+def make_stack(spec: StackSpec, device="cpu", noise_sigma: float = 1.0, on_frame=None):
+    """Materialise the stack [n][H][W] in the storage dtype on ``device``.
+
+    ``on_frame(k, frame)``, if given, sees each float32 frame before it is
+    rounded to the storage dtype (for crops of the unquantised values)."""
     import torch
 
     sky = sky_model(spec)
@@ -233,6 +236,8 @@ def make_stack(spec: StackSpec, device="cpu", noise_sigma: float = 1.0):
         for w, img in pimgs:
             if w[k] != 0.0:
                 frame.add_(img, alpha=float(w[k]))
+        if on_frame is not None:
+            on_frame(k, frame)
         out[k].copy_(frame)
     return out
 

@@ -228,3 +228,19 @@ def test_internal_capacity_flag():
     cands, stats, q, eta, used, rc = run_gpu(X, 1.0, window=5, branches=1, max_segments=4)
     assert rc == -4
     assert all(f & 2 for f in stats["flags"])
+
+
+@pytest.mark.parametrize("w,dt", [(9, "f16"), (7, "f32")])
+def test_crop_interior_bitwise(w, dt):
+    """q at the interior cells of a crop whose origin is a multiple of 16 is
+    the full image's bit for bit (the window sums follow absolute 8-aligned
+    blocks), which the crop error report relies on."""
+    X = structured_stack(91, 6, 300, 700)
+    _, _, q_full, _, _, _ = run_gpu(X, 5.0, dtype=dt, window=w)
+    h = w // 2
+    for oy, ox in ((16, 32), (48, 240), (0, 464)):
+        C = np.ascontiguousarray(X[:, oy:oy + 200, ox:ox + 208])
+        _, _, q_crop, _, _, _ = run_gpu(C, 5.0, dtype=dt, window=w)
+        a = q_crop[:, h:-h, h:-h]
+        b = q_full[:, oy + h:oy + 200 - h, ox + h:ox + 208 - h]
+        assert a.tobytes() == b.tobytes(), (oy, ox)

@@ -36,6 +36,7 @@ def c2_run():
     assert (spec.H, spec.W, spec.n, spec.window) == (H, W, N, WIN)
     print("[fullsize] generating the 16384^2 x 32 stack", flush=True)
     stack = synth.make_stack(spec, device="cuda")
+    torch.cuda.synchronize()
     qmap = torch.empty((N - 2, H, W), dtype=torch.float32, device="cuda")
     with Context(window=WIN, max_pixels=H * W, max_snap=N) as ctx:
         cands, stats, rc = ctx.detect(stack, TAU, index_map=qmap, as_dicts=False)

@@ -142,6 +142,29 @@ def test_sliding_windows_match_scipy(shape, w):
         np.testing.assert_allclose(q[s], (sd / cnt) * md * (sr / cnt), rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("shape,w", [((5, 13, 17), 3), ((4, 9, 20), 9)])
+def test_index_cells_match_scipy(shape, w):
+    """The per-cell sampler (used for sampled parity at full size, also on
+    crops) equals the same scipy box filters at every cell, edges included."""
+    rng = np.random.default_rng(7 * sum(shape) + w)
+    X = _rand_stack(rng, *shape, zeros=True)
+    n, H, W = shape
+    cells = np.array([(s, y, x) for s in range(n - 2) for y in range(H) for x in range(W)])
+    got = ref.index_cells(X, cells, window=w).reshape(n - 2, H, W)
+    for s in range(n - 2):
+        d, r = ref.pixel_terms(X, s)
+        cnt = ndimage.correlate(np.ones_like(d), np.ones((w, w)), mode="constant", cval=0.0)
+        sd = ndimage.correlate(d, np.ones((w, w)), mode="constant", cval=0.0)
+        sr = ndimage.correlate(r, np.ones((w, w)), mode="constant", cval=0.0)
+        md = ndimage.maximum_filter(d, size=w, mode="constant", cval=0.0)
+        np.testing.assert_allclose(got[s], (sd / cnt) * md * (sr / cnt), rtol=1e-12, atol=1e-15)
+    # a crop holding a cell's clipped window gives the same value
+    for s, y, x in cells[::37]:
+        ya, yb, xa, xb = max(0, y - w // 2), min(H, y + w // 2 + 1), max(0, x - w // 2), min(W, x + w // 2 + 1)
+        c = ref.index_cells(np.ascontiguousarray(X[s:s + 3, ya:yb, xa:xb]), [[0, y - ya, x - xa]], window=w)[0]
+        assert c == got[s, y, x]
+
+
 @pytest.mark.parametrize("shape,t", [((4, 12, 10), 4), ((3, 9, 13), 4), ((5, 7, 7), 1), ((3, 33, 70), 32)])
 def test_tile_mode_matches_block_reduction(shape, t):
     rng = np.random.default_rng(shape[1] * 7 + t)
