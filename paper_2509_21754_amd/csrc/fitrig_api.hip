@@ -449,6 +449,9 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     A.ncol = ncol;
     A.nbands = nbands;
     A.out_w = out_w;
+    // 4-byte pixels: blocks of 8 bands, so neighbouring bands share their
+    // halo rows in L2; 2-byte pixels run faster in row order
+    A.band_block = c.dtype == FITRIG_F32 ? 8 : 1;
     A.r_signed = cfg.r_signed;
     A.Cf = (float)cfg.C;
     A.qmap = qmap;

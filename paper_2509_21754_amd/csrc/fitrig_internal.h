@@ -29,6 +29,7 @@ struct StreamArgs {
   int64_t plane;         // H * W
   int32_t H, W;
   int32_t ncol, nbands, out_w;
+  int32_t band_block;    // workgroup order: blocks of this many bands (1 = row order)
   int32_t r_signed;
   float Cf;
   float* qmap;           // nullable [n-2][H][W]

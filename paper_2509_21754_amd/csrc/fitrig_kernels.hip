@@ -58,6 +58,20 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
+// Order of the streaming kernel's (band, group) tiles along one XCD's run of
+// workgroups: blocks of bb bands, group by group. With bb = 8 the workgroups
+// resident on an XCD at a time cover about 8 bands x 8 groups, so the halo
+// rows they share are fetched once into its L2; bb = 1 is row order.
+__device__ __forceinline__ void tile_of(int t, int nbands, int ncol, int bb_size, int& band, int& grp) {
+  const int per = bb_size * ncol;
+  const int bb = t / per;
+  const int rem = nbands - bb * bb_size;
+  const int hb = rem < bb_size ? rem : bb_size;
+  const int u = t - bb * per;
+  grp = u / hb;
+  band = bb * bb_size + (u - grp * hb);
+}
+
 // Order-preserving map of a float to uint32 (and back).
 __device__ __forceinline__ uint32_t ord_key(float v) {
   const uint32_t u = __float_as_uint(v);
@@ -412,8 +426,9 @@ struct Stream {
     // positive float correctly and maps non-positive values below them, which
     // is all max(., C) with C > 0 needs
 #pragma unroll
-    for (int i = 0; i + 1 < NR; i += 2) mxi = max(mxi, max(__float_as_int(C[i]), __float_as_int(C[i + 1])));
-    if constexpr (NR % 2) mxi = max(mxi, __float_as_int(C[NR - 1]));
+    // (own rows only: halo rows belong to the neighbouring bands; halo
+    // columns repeat pixels of the neighbouring groups, harmless for a max)
+    for (int i = H; i + 1 < H + kBand; i += 2) mxi = max(mxi, max(__float_as_int(C[i]), __float_as_int(C[i + 1])));
     float dl[NR], rl[NR];
     if (k >= 2) {
 #pragma unroll
@@ -576,9 +591,8 @@ __global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
   S st(A, sh);
   st.lane = threadIdx.x;
   st.wave = st.lane >> 6;
-  st.bid = xcd_remap(blockIdx.x, gridDim.x);
-  st.band = st.bid / A.ncol;
-  st.grp = st.bid - st.band * A.ncol;
+  tile_of(xcd_remap(blockIdx.x, gridDim.x), A.nbands, A.ncol, A.band_block, st.band, st.grp);
+  st.bid = st.band * A.ncol + st.grp;
   st.y0 = st.band * kBand;
   st.x0 = st.grp * A.out_w;
   const int xin = st.x0 - H + st.lane;
