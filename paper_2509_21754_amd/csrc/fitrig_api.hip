@@ -40,7 +40,8 @@ enum {
   CNT_TRUNC = 5,   // internal capacity exceeded
   CNT_IMG = 6,     // image-branch candidates
   CNT_FREQ = 7,    // frequency-branch candidates
-  CNT_N = 8
+  CNT_NBLK = 8,    // selection blocks flagged in the current run
+  CNT_N = 9
 };
 
 }  // namespace
@@ -52,6 +53,7 @@ struct fitrig_ctx {
   DevBuf stat_part, seg_max, seg_max2, tile_part, cube, cube_f, eta_d, eta_f, mu, sigma, flags, eta_st, M, qscratch;
   DevBuf hist, rs_state, rs_med, rs_dev, chunk_cnt, counters, mom_tmp, max_key;
   DevBuf seg_entry, seg_mask, cell_q, parent, comp_of, c_root, c_npix, c_key, c_w, c_box, c_out;
+  DevBuf bflag, blk_entry, blk_slot, band_start, band_end, rowslot;
   int64_t seg_cap = 0, comp_cap = 0;
   void* h_stage = nullptr;
   size_t h_stage_cap = 0;
@@ -160,9 +162,9 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
     p[i] = v;
 }
 // counters[CNT_TRUNC] |= overflow of this run; per-branch count; output base.
-__global__ void k_run_done(int64_t* c, int64_t seg_cap, int64_t comp_cap, int branch) {
+__global__ void k_run_done(int64_t* c, int64_t seg_cap, int64_t blk_cap, int64_t comp_cap, int branch) {
   if (threadIdx.x || blockIdx.x) return;
-  if (c[CNT_NSEL] > seg_cap || c[CNT_NCOMP] > comp_cap) c[CNT_TRUNC] |= 1;
+  if (c[CNT_NSEL] > seg_cap || c[CNT_NBLK] > blk_cap || c[CNT_NCOMP] > comp_cap) c[CNT_TRUNC] |= 1;
   const int64_t nc = c[CNT_NCOMP] < comp_cap ? c[CNT_NCOMP] : comp_cap;
   c[branch == FITRIG_IMAGE ? CNT_IMG : CNT_FREQ] += nc;
   c[CNT_OUTBASE] += nc;
@@ -252,7 +254,7 @@ fitrig_status compact(fitrig_ctx* ctx, hipStream_t st, F f, E e, int64_t ne_stat
   uint32_t* cnt = (uint32_t*)ctx->chunk_cnt.p;
   hipLaunchKernelGGL((k_compact_count<F>), dim3((unsigned)nch), dim3(256), 0, st, f, ne_static, ne_dyn, cap, mult,
                      cnt);
-  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, cnt, nch, total);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, cnt, nch, ne_dyn, cap, mult, total);
   hipLaunchKernelGGL((k_compact_write<F, E>), dim3((unsigned)nch), dim3(256), 0, st, f, e, ne_static, ne_dyn, cap,
                      mult, (const uint32_t*)cnt);
   LAUNCH_CHECK(ctx);
@@ -274,9 +276,41 @@ fitrig_status select_run(fitrig_ctx* ctx, const Call& c, const SegLayout& L, flo
   int32_t* parent = (int32_t*)ctx->parent.p;
   fitrig_status rc;
 
-  SegFlag fl{seg_max, mu, sigma, flags, c.tau, L};
-  SegEmit em{(int32_t*)seg_max, seg_entry, cap};
-  if ((rc = compact(ctx, st, fl, em, NE, nullptr, 0, 1, cnt + CNT_NSEL)) != FITRIG_OK) return rc;
+  // blocks of L.br rows x one segment: flag (maxima of the block's rows),
+  // compact, then compact the rows of the flagged blocks in raster order
+  const int64_t NB = (int64_t)L.nsets * L.nbr * L.nseg_row;
+  const int64_t nbands = (int64_t)L.nsets * L.nbr;
+  const int64_t bcap = std::max<int64_t>(4096, cap / 2);
+  const int64_t nchb = std::max<int64_t>(1, (NB + kChunk - 1) / kChunk);
+  if ((rc = ensure(ctx, ctx->bflag, (size_t)NB)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->blk_slot, (size_t)NB * 4)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->band_start, (size_t)nbands * 4)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->band_end, (size_t)nbands * 4)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->blk_entry, (size_t)bcap * 8)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->rowslot, (size_t)bcap * L.br * 4)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->chunk_cnt, (size_t)nchb * 4)) != FITRIG_OK)
+    return rc;
+  uint8_t* bflag = (uint8_t*)ctx->bflag.p;
+  int64_t* blk_entry = (int64_t*)ctx->blk_entry.p;
+  int32_t* blk_slot = (int32_t*)ctx->blk_slot.p;
+  int32_t* band_start = (int32_t*)ctx->band_start.p;
+  int32_t* band_end = (int32_t*)ctx->band_end.p;
+  int32_t* rowslot = (int32_t*)ctx->rowslot.p;
+  uint32_t* ccnt = (uint32_t*)ctx->chunk_cnt.p;
+  hipLaunchKernelGGL(k_blk_count, dim3((unsigned)nchb), dim3(256), 0, st, (const float*)seg_max, mu, sigma, flags,
+                     c.tau, L, bflag, ccnt);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, ccnt, nchb, (const int64_t*)nullptr, (int64_t)0, 1,
+                     cnt + CNT_NBLK);
+  hipLaunchKernelGGL((k_compact_write<ByteFlag, BlkEmit>), dim3((unsigned)nchb), dim3(256), 0, st,
+                     ByteFlag{bflag}, BlkEmit{blk_entry, blk_slot, bcap}, NB, (const int64_t*)nullptr, (int64_t)0, 1,
+                     (const uint32_t*)ccnt);
+  hipLaunchKernelGGL(k_blk_bands, dim3(grid_for(bcap, 256, 2048)), dim3(256), 0, st, (const int64_t*)blk_entry,
+                     (const int64_t*)(cnt + CNT_NBLK), bcap, L, band_start, band_end);
+  LAUNCH_CHECK(ctx);
+  const RowOf ro{blk_entry, band_start, band_end, L};
+  if ((rc = compact(ctx, st, RowFlag{ro, seg_max, mu, sigma, c.tau}, RowEmit{ro, rowslot, seg_entry, cap}, 0,
+                    cnt + CNT_NBLK, bcap, L.br, cnt + CNT_NSEL)) != FITRIG_OK)
+    return rc;
 
   const int gsel = (int)std::min<int64_t>(cap, 4096);
   if (direct_vals) {
@@ -299,7 +333,8 @@ fitrig_status select_run(fitrig_ctx* ctx, const Call& c, const SegLayout& L, flo
   const int gcell = grid_for(cap * 64, 256, 4096);
   hipLaunchKernelGGL(k_uf_init, dim3(gcell), dim3(256), 0, st, (const uint64_t*)mask, (const int64_t*)(cnt + CNT_NSEL),
                      cap, parent);
-  hipLaunchKernelGGL(k_uf_union, dim3(gcell), dim3(256), 0, st, (const int32_t*)seg_max, (const uint64_t*)mask,
+  hipLaunchKernelGGL(k_uf_union, dim3(gcell), dim3(256), 0, st, SlotMap{blk_slot, band_start, band_end, rowslot},
+                     (const uint64_t*)mask,
                      (const int64_t*)seg_entry, L, (const int64_t*)(cnt + CNT_NSEL), cap, parent);
   hipLaunchKernelGGL(k_uf_flatten, dim3(gcell), dim3(256), 0, st, (const int64_t*)(cnt + CNT_NSEL), cap, parent);
   LAUNCH_CHECK(ctx);
@@ -322,7 +357,7 @@ fitrig_status select_run(fitrig_ctx* ctx, const Call& c, const SegLayout& L, flo
                      (const int32_t*)ctx->c_npix.p, (const unsigned long long*)ctx->c_key.p,
                      (const unsigned long long*)ctx->c_w.p, (const int32_t*)ctx->c_box.p, cnt + CNT_OUTBASE,
                      (fitrig_candidate*)ctx->c_out.p, 2 * ccap);
-  hipLaunchKernelGGL(k_run_done, dim3(1), dim3(64), 0, st, cnt, cap, ccap, branch);
+  hipLaunchKernelGGL(k_run_done, dim3(1), dim3(64), 0, st, cnt, cap, bcap, ccap, branch);
   LAUNCH_CHECK(ctx);
   return FITRIG_OK;
 }
@@ -541,7 +576,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   // ---- image-branch selection ---------------------------------------------
   if (img) {
     if (sliding) {
-      SegLayout L{c.H, c.W, np, kSegsPerGroup, out_w, nseg_row};
+      SegLayout L{c.H, c.W, np, kSegsPerGroup, out_w, nseg_row, kBand, (c.H + kBand - 1) / kBand};
       if ((rc = ensure_selection(ctx, (int64_t)np * c.H * nseg_row)) != FITRIG_OK) return rc;
       if ((rc = select_run(ctx, c, L, (float*)ctx->seg_max.p, mu, sigma, flags, FITRIG_IMAGE, nullptr, halo)) !=
           FITRIG_OK)
@@ -555,7 +590,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
         if ((rc = robust_spread(ctx, st, (const float*)ctx->cube_f.p, np, ncell, mu, sigma, flags)) != FITRIG_OK)
           return rc;
       }
-      SegLayout L{Ty, Tx, np, 1, 64, (Tx + 63) / 64};
+      SegLayout L{Ty, Tx, np, 1, 64, (Tx + 63) / 64, 1, Ty};
       if ((rc = ensure(ctx, ctx->seg_max, (size_t)np * Ty * L.nseg_row * 4)) != FITRIG_OK) return rc;
       hipLaunchKernelGGL(k_segmax_direct, dim3(grid_for((int64_t)np * Ty * L.nseg_row)), dim3(256), 0, st,
                          (const float*)ctx->cube_f.p, L, (float*)ctx->seg_max.p);
@@ -586,7 +621,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
       if ((rc = robust_spread(ctx, st, (const float*)ctx->eta_f.p, 1, ntiles, eta_mu, eta_sig, eta_flag)) != FITRIG_OK)
         return rc;
     }
-    SegLayout L{Ty, Tx, 1, 1, 64, (Tx + 63) / 64};
+    SegLayout L{Ty, Tx, 1, 1, 64, (Tx + 63) / 64, 1, Ty};
     // segment maxima of eta go to a region of seg_max past anything still in use
     const int64_t ne = (int64_t)Ty * L.nseg_row;
     if ((rc = ensure(ctx, ctx->seg_max2, (size_t)ne * 4)) != FITRIG_OK) return rc;
@@ -776,7 +811,8 @@ fitrig_status fitrig_destroy(fitrig_ctx* ctx) {
                     &ctx->M,         &ctx->qscratch, &ctx->hist,      &ctx->rs_state, &ctx->rs_med,  &ctx->rs_dev,
                     &ctx->chunk_cnt, &ctx->counters, &ctx->seg_entry, &ctx->seg_mask, &ctx->cell_q,  &ctx->parent,
                     &ctx->comp_of,   &ctx->c_root,   &ctx->c_npix,    &ctx->c_key,    &ctx->c_w,     &ctx->c_box,
-                    &ctx->c_out};
+                    &ctx->c_out,     &ctx->bflag,    &ctx->blk_entry, &ctx->blk_slot, &ctx->band_start,
+                    &ctx->band_end,  &ctx->rowslot};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);

@@ -64,6 +64,8 @@ struct SegLayout {
   int32_t spg;           // segments per column group
   int32_t gw;            // column-group width (cells)
   int32_t nseg_row;      // segments per row
+  int32_t br;            // rows per selection block (a block is br rows of one segment)
+  int32_t nbr;           // blocks per column of segments: ceil(Ho / br)
 };
 
 __host__ __device__ inline int seg_x0(const SegLayout& L, int g) {

@@ -921,35 +921,159 @@ __global__ void k_segmax_direct(const float* vals, SegLayout L, float* seg_max) 
   }
 }
 
+constexpr int kPerThread = 16;
+constexpr int kChunk = 256 * kPerThread;
+
 __device__ __forceinline__ bool zsel(float q, double mu, double sg, double tau) {
   return ((double)q - mu) / sg > tau;
 }
 
-struct SegFlag {
+// Two-level selection. A block is br rows of one 64-cell segment column
+// (block b = (set, yb, g) in raster order); a block is flagged when the
+// largest row-segment maximum in it passes the threshold. Flagged blocks are
+// compacted, then their rows (ordered set, row, segment: raster order) are
+// compacted to the selected row segments ("slots") whose cells are
+// recomputed. With br = 1 the blocks are the row segments themselves.
+struct BlkIdx {
+  int s, yb, g;
+};
+__device__ __forceinline__ BlkIdx blk_decode(const SegLayout& L, int64_t b) {
+  BlkIdx r;
+  if (b < (int64_t)INT32_MAX) {
+    const uint32_t u = (uint32_t)b, ns = (uint32_t)L.nseg_row, nb = (uint32_t)L.nbr;
+    const uint32_t rb = u / ns;
+    r.g = (int)(u - rb * ns);
+    r.s = (int)(rb / nb);
+    r.yb = (int)(rb - (uint32_t)r.s * nb);
+  } else {
+    const int64_t rb = b / L.nseg_row;
+    r.g = (int)(b - rb * L.nseg_row);
+    r.s = (int)(rb / L.nbr);
+    r.yb = (int)(rb - (int64_t)r.s * L.nbr);
+  }
+  return r;
+}
+
+// Flag of every block into a byte array, one thread per block with
+// consecutive threads on consecutive segments (coalesced maxima reads), and
+// the number of flagged blocks per chunk of kChunk blocks.
+__global__ __launch_bounds__(256) void k_blk_count(const float* seg_max, const double* mu, const double* sigma,
+                                                   const uint32_t* flags, double tau, SegLayout L, uint8_t* bflag,
+                                                   uint32_t* cnt) {
+  __shared__ uint32_t sh[256];
+  const int64_t NB = (int64_t)L.nsets * L.nbr * L.nseg_row;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  uint32_t c = 0;
+  for (int j = 0; j < kPerThread; ++j) {
+    const int64_t b = base + (int64_t)j * 256 + threadIdx.x;
+    if (b >= NB) break;
+    const BlkIdx q = blk_decode(L, b);
+    bool f = false;
+    if (seg_width(L, q.g) > 0 && !flags[q.s]) {
+      const int y0 = q.yb * L.br, y1 = min(y0 + L.br, L.Ho);
+      const float* p = seg_max + ((int64_t)q.s * L.Ho + y0) * L.nseg_row + q.g;
+      float m = p[0];
+      for (int y = y0 + 1; y < y1; ++y) {
+        p += L.nseg_row;
+        m = fmaxf(m, *p);
+      }
+      f = zsel(m, mu[q.s], sigma[q.s], tau);
+    }
+    bflag[b] = f ? 1 : 0;
+    c += f ? 1u : 0u;
+  }
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[blockIdx.x] = sh[0];
+}
+
+struct ByteFlag {
+  const uint8_t* bflag;
+  __device__ bool operator()(int64_t b) const { return bflag[b] != 0; }
+};
+
+// flagged block -> list position (or -1 for every other block)
+struct BlkEmit {
+  int64_t* blk_entry;
+  int32_t* blk_slot;
+  int64_t cap;
+  __device__ void operator()(int64_t b, bool f, int64_t pos) const {
+    if (f && pos < cap) {
+      blk_entry[pos] = b;
+      blk_slot[b] = (int32_t)pos;
+    } else {
+      blk_slot[b] = -1;
+    }
+  }
+};
+
+// Range of each band (set, yb) in the flagged-block list: [start, end).
+__global__ void k_blk_bands(const int64_t* blk_entry, const int64_t* nblk_p, int64_t bcap, SegLayout L,
+                            int32_t* band_start, int32_t* band_end) {
+  int64_t n = nblk_p[0];
+  if (n > bcap) n = bcap;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t B = blk_entry[k] / L.nseg_row;
+    if (k == 0 || blk_entry[k - 1] / L.nseg_row != B) band_start[B] = (int32_t)k;
+    if (k + 1 == n || blk_entry[k + 1] / L.nseg_row != B) band_end[B] = (int32_t)(k + 1);
+  }
+}
+
+// Row j of the flagged blocks in raster order: the rows of band B occupy
+// [start*br, end*br), row r of the band's i-th block sits at
+// start*br + r*nf + i (nf = blocks of the band).
+struct RowOf {
+  const int64_t* blk_entry;
+  const int32_t* band_start;
+  const int32_t* band_end;
+  SegLayout L;
+  // row-segment entry (set * Ho + y) * nseg_row + g, or -1 past the last row
+  __device__ int64_t entry(int64_t j) const {
+    const int64_t b0 = blk_entry[j / L.br];
+    const int64_t B = b0 / L.nseg_row;
+    const int st = band_start[B];
+    const int nf = band_end[B] - st;
+    const int64_t loc = j - (int64_t)st * L.br;
+    const int r = (int)(loc / nf);
+    const int64_t k = st + (loc - (int64_t)r * nf);
+    const int64_t b = blk_entry[k];
+    const int s = (int)(B / L.nbr);
+    const int yb = (int)(B - (int64_t)s * L.nbr);
+    const int y = yb * L.br + r;
+    if (y >= L.Ho) return -1;
+    return ((int64_t)s * L.Ho + y) * L.nseg_row + (b - B * L.nseg_row);
+  }
+};
+
+struct RowFlag {
+  RowOf ro;
   const float* seg_max;
   const double* mu;
   const double* sigma;
-  const uint32_t* flags;
   double tau;
-  SegLayout L;
-  __device__ bool operator()(int64_t e) const {
-    const int g = (int)(e % L.nseg_row);
-    const int s = (int)(e / ((int64_t)L.Ho * L.nseg_row));
-    if (seg_width(L, g) <= 0 || flags[s]) return false;
+  __device__ bool operator()(int64_t j) const {
+    const int64_t e = ro.entry(j);
+    if (e < 0) return false;
+    const int s = (int)(e / ((int64_t)ro.L.Ho * ro.L.nseg_row));
     return zsel(seg_max[e], mu[s], sigma[s], tau);
   }
 };
 
-struct SegEmit {
-  int32_t* slot_of;  // aliases seg_max
+struct RowEmit {
+  RowOf ro;
+  int32_t* rowslot;
   int64_t* seg_entry;
   int64_t cap;
-  __device__ void operator()(int64_t e, bool f, int64_t pos) const {
+  __device__ void operator()(int64_t j, bool f, int64_t pos) const {
     if (f && pos < cap) {
-      seg_entry[pos] = e;
-      slot_of[e] = (int32_t)pos;
+      rowslot[j] = (int32_t)pos;
+      seg_entry[pos] = ro.entry(j);
     } else {
-      slot_of[e] = -1;
+      rowslot[j] = -1;
     }
   }
 };
@@ -974,8 +1098,6 @@ struct RootEmit {
   }
 };
 
-constexpr int kPerThread = 16;
-constexpr int kChunk = 256 * kPerThread;
 
 __device__ __forceinline__ int64_t dyn_count(int64_t ne_static, const int64_t* ne_dyn, int64_t cap, int mult) {
   if (!ne_dyn) return ne_static;
@@ -1006,9 +1128,13 @@ __global__ __launch_bounds__(256) void k_compact_count(F f, int64_t ne_static, c
 }
 
 // Exclusive scan of nchunks counts in place (one workgroup of 1024); total -> out[0].
-__global__ __launch_bounds__(1024) void k_compact_scan(uint32_t* cnt, int64_t nchunks, int64_t* out) {
+__global__ __launch_bounds__(1024) void k_compact_scan(uint32_t* cnt, int64_t nch_static, const int64_t* ne_dyn,
+                                                        int64_t cap, int mult, int64_t* out) {
   __shared__ int64_t sh[1024];
   const int t = threadIdx.x;
+  // only the chunks the count pass filled (dynamic element counts)
+  const int64_t nchunks =
+      ne_dyn ? (dyn_count(0, ne_dyn, cap, mult) + kChunk - 1) / kChunk : nch_static;
   const int64_t per = (nchunks + 1023) / 1024;
   const int64_t a = t * per, b = min(a + per, nchunks);
   int64_t loc = 0;
@@ -1207,11 +1333,24 @@ __global__ void k_uf_init(const uint64_t* seg_mask, const int64_t* nsel_p, int64
     parent[i] = ((seg_mask[i >> 6] >> (i & 63)) & 1ull) ? (int32_t)i : -1;
 }
 
-__device__ __forceinline__ int32_t slot_at(const int32_t* slot_of, const uint64_t* seg_mask, const SegLayout& L,
+struct SlotMap {
+  const int32_t* blk_slot;
+  const int32_t* band_start;
+  const int32_t* band_end;
+  const int32_t* rowslot;
+};
+
+__device__ __forceinline__ int32_t slot_at(const SlotMap& M, const uint64_t* seg_mask, const SegLayout& L,
                                            int64_t set, int y, int x) {
   if (y < 0 || y >= L.Ho || x < 0 || x >= L.Wo) return -1;
   const int g = seg_of_x(L, x);
-  const int32_t si = slot_of[(set * L.Ho + y) * L.nseg_row + g];
+  const int yb = y / L.br;
+  const int64_t B = set * L.nbr + yb;
+  const int32_t k = M.blk_slot[B * L.nseg_row + g];
+  if (k < 0) return -1;
+  const int st = M.band_start[B];
+  const int nf = M.band_end[B] - st;
+  const int32_t si = M.rowslot[(int64_t)st * L.br + (int64_t)(y - yb * L.br) * nf + (k - st)];
   if (si < 0) return -1;
   const int off = x - seg_x0(L, g);
   if (!((seg_mask[si] >> off) & 1ull)) return -1;
@@ -1228,7 +1367,7 @@ __device__ __forceinline__ void slot_pos(const int64_t* seg_entry, const SegLayo
   x = seg_x0(L, g) + (int)(slot & 63);
 }
 
-__global__ void k_uf_union(const int32_t* slot_of, const uint64_t* seg_mask, const int64_t* seg_entry, SegLayout L,
+__global__ void k_uf_union(SlotMap M, const uint64_t* seg_mask, const int64_t* seg_entry, SegLayout L,
                            const int64_t* nsel_p, int64_t cap, int32_t* parent) {
   int64_t nsel = nsel_p[0];
   if (nsel > cap) nsel = cap;
@@ -1241,7 +1380,7 @@ __global__ void k_uf_union(const int32_t* slot_of, const uint64_t* seg_mask, con
     const int dy[4] = {0, 1, 1, 1};
     const int dx[4] = {1, -1, 0, 1};
     for (int k = 0; k < 4; ++k) {
-      const int32_t nb = slot_at(slot_of, seg_mask, L, set, y + dy[k], x + dx[k]);
+      const int32_t nb = slot_at(M, seg_mask, L, set, y + dy[k], x + dx[k]);
       if (nb >= 0) uf_union(parent, (int32_t)i, nb);
     }
   }
