@@ -203,8 +203,13 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 template <bool RS>
 __device__ __forceinline__ void pix_ratio(float dl, float ref, float Cf, float& rl) {
   const float den = (ref == 0.0f) ? Cf : ref;
-  // dl >= 0, so for |x_hat| the product is already >= 0 and min(., 1) is the clamp
-  rl = fminf(dl * __builtin_amdgcn_rcpf(RS ? den : fabsf(den)), 1.0f);
+  if constexpr (RS) {
+    rl = fminf(dl * __builtin_amdgcn_rcpf(den), 1.0f);
+  } else {
+    // dl >= 0 and den != 0, so the product is finite and >= 0 and min(., 1)
+    // is the [0, 1] clamp, which folds into the multiply
+    rl = __builtin_amdgcn_fmed3f(dl * __builtin_amdgcn_rcpf(fabsf(den)), 0.0f, 1.0f);
+  }
 }
 
 template <bool RS>
