@@ -197,7 +197,8 @@ typedef struct {
   fitrig_config base;   /* index / selection settings of every request; its
                            capacity hints size each slot's scratch up front */
   int32_t n_slots;      /* requests on the device at once (default 4) */
-  int32_t max_fields;   /* fields with resident state (default 64) */
+  int32_t max_fields;   /* fields with resident state (default 64); a new field
+                           beyond it evicts the least recently used idle field */
   int64_t mem_budget;   /* device bytes for slot scratch plus field state; 0 = no limit */
   int64_t cand_cap;     /* candidates kept per result (default 65536) */
 } fitrig_server_config;
@@ -228,9 +229,10 @@ fitrig_status fitrig_server_create(const fitrig_server_config* cfg, fitrig_serve
  * admission; blocking = 0 returns E_BUSY when the request does not fit now.
  * *ticket identifies the request.
  * Errors: E_INVAL (null, n_snap < 1, a field's first request with n_snap < 3,
- * sizes as fitrig_detect, sigma not finite or <= 0, too many fields),
- * E_BUSY (non-blocking and not admitted; also when the request alone exceeds
- * mem_budget). */
+ * sizes as fitrig_detect, sigma not finite or <= 0, a new size or dtype for a
+ * field with requests in flight), E_BUSY (non-blocking and not admitted; the
+ * request alone exceeds mem_budget; max_fields fields all have requests in
+ * flight), E_NOMEM. */
 fitrig_status fitrig_submit(fitrig_server* srv, int64_t field_id, const void* stack, fitrig_dtype dtype,
                             int32_t n_snap, int32_t H, int32_t W, double sigma, int32_t blocking,
                             int64_t* ticket);

@@ -61,6 +61,7 @@ struct Field {
   int64_t frames_seen = 0;   // frames of finished requests
   int64_t frames_submitted = 0;
   double M = -INFINITY;
+  int64_t last_use = 0;      // submit counter of the field's latest request
   bool busy = false;         // a request of this field is ready or running
   std::deque<int64_t> pending;
 };
@@ -77,6 +78,7 @@ struct fitrig_server {
   std::vector<std::thread> workers;
   std::vector<fitrig_ctx*> ctxs;
   int64_t next_ticket = 1;
+  int64_t use_clock = 0;
   int64_t mem_charged = 0;  // queued + running requests
   int64_t mem_fields = 0;   // resident field state
   int outstanding = 0;      // admitted, not finished
@@ -211,25 +213,41 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
   if (n_snap < 1 || H < 1 || W < 1 || (uint64_t)H * (uint64_t)W >= (1ull << 32)) return FITRIG_E_INVAL;
   if (!(sigma > 0.0) || !isfinite(sigma)) return FITRIG_E_INVAL;
   const int64_t t_submit = now_ns();
-  std::unique_lock<std::mutex> lk(S->mu);
-  auto it = S->fields.find(field_id);
-  const bool fresh = it == S->fields.end();
-  if (fresh && (int64_t)S->fields.size() >= S->cfg.max_fields) return FITRIG_E_INVAL;
-  Field* f = fresh ? nullptr : &it->second;
-  const bool resize = f && (f->H != H || f->W != W || f->dtype != dtype);
-  if (resize && (f->busy || !f->pending.empty())) return FITRIG_E_INVAL;
-  const int64_t carried = (f && !resize) ? std::min<int64_t>(2, f->frames_submitted) : 0;
-  if (carried + n_snap < 3) return FITRIG_E_INVAL;
   const size_t fb = (size_t)H * W * dtype_bytes(dtype);
-  const int64_t field_mem = (fresh || resize) ? (int64_t)(2 * fb) : 0;
-  const int64_t mem = fitrig::scratch_estimate(S->cfg.base, (int)(carried + n_snap), H, W);
   const int64_t budget = S->cfg.mem_budget;
-  auto fits = [&] { return budget == 0 || S->mem_charged + S->mem_fields + field_mem + mem <= budget; };
-  if (budget > 0 && field_mem + mem + S->mem_fields > budget) return FITRIG_E_BUSY;
-  if (!fits()) {
+  std::unique_lock<std::mutex> lk(S->mu);
+  // the field's state and the charge are re-read after every wait, so
+  // concurrent submits to the same field see each other
+  bool fresh, resize;
+  int64_t mem, field_mem;
+  for (;;) {
+    auto it = S->fields.find(field_id);
+    fresh = it == S->fields.end();
+    const Field* f0 = fresh ? nullptr : &it->second;
+    resize = f0 && (f0->H != H || f0->W != W || f0->dtype != dtype);
+    if (resize && (f0->busy || !f0->pending.empty())) return FITRIG_E_INVAL;
+    const int64_t carried = (f0 && !resize) ? std::min<int64_t>(2, f0->frames_submitted) : 0;
+    if (carried + n_snap < 3) return FITRIG_E_INVAL;
+    field_mem = (fresh || resize) ? (int64_t)(2 * fb) : 0;
+    mem = fitrig::scratch_estimate(S->cfg.base, (int)(carried + n_snap), H, W);
+    if (budget > 0 && field_mem + mem + S->mem_fields > budget) return FITRIG_E_BUSY;
+    if (budget == 0 || S->mem_charged + S->mem_fields + field_mem + mem <= budget) break;
     if (!blocking) return FITRIG_E_BUSY;
-    S->cv_done.wait(lk, fits);
+    S->cv_done.wait(lk);
   }
+  if (fresh && (int64_t)S->fields.size() >= S->cfg.max_fields) {
+    // evict the least recently used idle field (its carried frames and M)
+    auto lru = S->fields.end();
+    for (auto jt = S->fields.begin(); jt != S->fields.end(); ++jt)
+      if (!jt->second.busy && jt->second.pending.empty() &&
+          (lru == S->fields.end() || jt->second.last_use < lru->second.last_use))
+        lru = jt;
+    if (lru == S->fields.end()) return FITRIG_E_BUSY;
+    if (lru->second.carry) (void)hipFree(lru->second.carry);
+    S->mem_fields -= (int64_t)(2 * lru->second.frame_bytes);
+    S->fields.erase(lru);
+  }
+  Field* f = fresh ? nullptr : &S->fields[field_id];
   // (re)create the field state
   if (fresh || resize) {
     Field& nf = S->fields[field_id];
@@ -265,6 +283,7 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
   S->mem_charged += mem;
   S->outstanding += 1;
   f->frames_submitted += n_snap;
+  f->last_use = ++S->use_clock;
   if (!f->busy) {
     f->busy = true;
     S->ready.push_back(r->ticket);

@@ -111,3 +111,20 @@ def test_server_admission_by_memory():
         tk2 = srv.submit(0, X[:1].contiguous(), 5.0)  # later requests may bring a single frame
         r2 = srv.poll(tk2)
         assert r2["n_triples"] == 1 and r2["first_triple"] == 2
+
+
+def test_server_evicts_least_recently_used_idle_field():
+    from paper_2509_21754_amd import Server
+
+    X = torch.from_numpy(structured_stack(9, 5, 40, 300)).cuda()
+    one = X[:1].contiguous()
+    with Server(n_slots=2, max_fields=2, window=5) as srv:
+        for f in (0, 1):
+            srv.poll(srv.submit(f, X, 5.0))
+        srv.poll(srv.submit(1, one, 5.0))          # field 1 used last
+        r2 = srv.poll(srv.submit(2, X, 5.0))       # evicts field 0
+        assert r2["first_triple"] == 0
+        r1 = srv.poll(srv.submit(1, one, 5.0))     # field 1 kept its frames
+        assert r1["first_triple"] == 4 and r1["n_triples"] == 1
+        r0 = srv.poll(srv.submit(0, X, 5.0))       # field 0 starts over (evicts field 2)
+        assert r0["first_triple"] == 0 and r0["n_triples"] == 3
