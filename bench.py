@@ -323,6 +323,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sigma-est", default="mean_std", choices=("mean_std", "median_mad"))
+    ap.add_argument("--mode", default="sliding", choices=("sliding", "tiles"),
+                    help="sliding window (per pixel) or the paper's tiles")
+    ap.add_argument("--tile", type=int, default=32, help="tile size (tile mode and frequency branch)")
     ap.add_argument("--no-fp16-form", action="store_true", help="skip the FP16-storage run of the same stack")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving replay")
     ap.add_argument("--no-precision-report", action="store_true",
@@ -366,7 +370,10 @@ def main() -> int:
         del a, b
     tau = spec.taus[0]
     n, H, W = spec.n, spec.H, spec.W
-    ctx = Context(window=spec.window, profile=1, max_pixels=H * W, max_snap=n)
+    est = {"mean_std": 0, "median_mad": 1}[args.sigma_est]
+    mode = {"sliding": 0, "tiles": 1}[args.mode]
+    ctx = Context(window=spec.window, profile=1, max_pixels=H * W, max_snap=n, sigma_est=est, mode=mode,
+                  tile=args.tile)
     stream = torch.cuda.current_stream(dev)
     print(f"[bench] timing {args.steps} steps after {args.warmup} warmup", file=sys.stderr, flush=True)
     ms_per_step, step_ms, phases, cands, stats = time_detect(ctx, stack, tau, args.steps, args.warmup, stream)
@@ -376,10 +383,11 @@ def main() -> int:
     kmean = statistics.mean(kern_ms)
     alg_bytes = px * BYTES_IN[spec.dtype]
     achieved = alg_bytes / (kmean / 1e3) / 1e9
-    traffic = stored_traffic(args.workload)
+    traffic = stored_traffic(args.workload) if args.mode == "sliding" else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_stream (streaming index pass)", "kernel_ms": round(kmean, 4),
+            "kernel": "k_stream (streaming index pass)" if args.mode == "sliding" else "k_tile (tile-mode pass)",
+            "kernel_ms": round(kmean, 4),
             "alg_bytes_per_launch": alg_bytes}
     phase_mean = {k: round(statistics.mean(p[k] for p in phases), 4) for k in phases[0]}
     out = {
@@ -396,7 +404,8 @@ def main() -> int:
         "dtype": spec.dtype,
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "n_snap": n, "H": H, "W": W,
-                   "window": spec.window, "tau": tau, "branches": "image+freq", "sigma_est": "mean_std"},
+                   "window": spec.window, "tau": tau, "branches": "image+freq", "sigma_est": args.sigma_est,
+                   "mode": args.mode, "tile": args.tile},
         "hbm_peak_frac_whole_step": round(px * BYTES_IN[spec.dtype] / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "p50_ms": round(statistics.median(step_ms), 4),
         "p99_ms": round(pctl(step_ms, 0.99), 4),

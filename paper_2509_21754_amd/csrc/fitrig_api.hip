@@ -51,7 +51,7 @@ struct fitrig_ctx {
   hipStream_t stream = nullptr;
   int32_t last_hip = 0;
   DevBuf stat_part, seg_max, seg_max2, tile_part, cube, cube_f, eta_d, eta_f, mu, sigma, flags, eta_st, M, qscratch;
-  DevBuf hist, rs_state, rs_med, rs_dev, chunk_cnt, counters, mom_tmp, max_key;
+  DevBuf hist, rs_state, rs_med, rs_dev, rs_next, chunk_cnt, counters, mom_tmp, max_key;
   DevBuf seg_entry, seg_mask, cell_q, parent, comp_of, c_root, c_npix, c_key, c_w, c_box, c_out;
   DevBuf bflag, blk_entry, blk_slot, band_start, band_end, rowslot;
   int64_t seg_cap = 0, comp_cap = 0;
@@ -225,16 +225,29 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
   const int shifts[3] = {21, 10, 0};
   const int nbits[3] = {11, 11, 10};
   const int gx = grid_for(per_set, 256 * 16, 1024);
+  // median (mode 0), then MAD (mode 1): the lower middle order statistic by
+  // three radix passes; the upper one (even counts) by one more pass
+  if ((rc = ensure(ctx, ctx->rs_next, (size_t)nsets * 12)) != FITRIG_OK) return rc;
+  unsigned long long* cnt_le = (unsigned long long*)ctx->rs_next.p;
+  uint32_t* min_gt = (uint32_t*)(cnt_le + nsets);
   for (int mode = 0; mode < 2; ++mode) {
-    for (int which = 0; which < 2; ++which) {
-      hipLaunchKernelGGL(k_rs_init, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, per_set, which);
-      for (int p = 0; p < 3; ++p) {
-        hipLaunchKernelGGL(k_rs_hist, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, mode, (const double*)mu, rs,
-                           shifts[p], nbits[p], hist);
-        hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(64), 0, st, rs, hist, shifts[p], nbits[p]);
-      }
-      hipLaunchKernelGGL(k_rs_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, mode, which,
-                         (double*)(mode ? ctx->rs_dev.p : ctx->rs_med.p));
+    double* out = (double*)(mode ? ctx->rs_dev.p : ctx->rs_med.p);
+    hipLaunchKernelGGL(k_rs_init, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, per_set, 0);
+    for (int p = 0; p < 3; ++p) {
+      hipLaunchKernelGGL(k_rs_hist, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, mode, (const double*)mu, rs,
+                         shifts[p], nbits[p], hist);
+      hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(64), 0, st, rs, hist, shifts[p], nbits[p]);
+    }
+    hipLaunchKernelGGL(k_rs_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, mode, 0, out);
+    if (per_set % 2 == 0) {
+      hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, (int64_t*)cnt_le, (int64_t)nsets, (int64_t)0);
+      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, min_gt, (int64_t)nsets, 0xFFFFFFFFu);
+      hipLaunchKernelGGL(k_rs_next, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, mode, (const double*)mu, rs,
+                         cnt_le, min_gt);
+      hipLaunchKernelGGL(k_rs_next_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, per_set, mode,
+                         (const unsigned long long*)cnt_le, (const uint32_t*)min_gt, out);
+    } else {
+      hipLaunchKernelGGL(k_rs_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, mode, 1, out);
     }
     hipLaunchKernelGGL(k_rs_finish, dim3((nsets + 63) / 64), dim3(64), 0, st, (const double*)ctx->rs_med.p,
                        (const double*)ctx->rs_dev.p, nsets, mu, sigma, flags, mode);
@@ -812,7 +825,7 @@ fitrig_status fitrig_destroy(fitrig_ctx* ctx) {
                     &ctx->chunk_cnt, &ctx->counters, &ctx->seg_entry, &ctx->seg_mask, &ctx->cell_q,  &ctx->parent,
                     &ctx->comp_of,   &ctx->c_root,   &ctx->c_npix,    &ctx->c_key,    &ctx->c_w,     &ctx->c_box,
                     &ctx->c_out,     &ctx->bflag,    &ctx->blk_entry, &ctx->blk_slot, &ctx->band_start,
-                    &ctx->band_end,  &ctx->rowslot};
+                    &ctx->band_end,  &ctx->rowslot,  &ctx->rs_next};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);

@@ -552,9 +552,16 @@ struct Stream {
       A.seg_max[((int64_t)s * A.H + y) * nseg_row + grp * kSegsPerGroup + (ch >> 2)] = gmax;
     if (A.qmap && chv) {
       float* dst = A.qmap + ((int64_t)s * A.H + y) * A.W + xc;
+      if (xc + NT <= A.W && ((uintptr_t)dst & 15) == 0) {
+        // whole chunk inside the row, 16-byte aligned: four 16-byte stores
 #pragma unroll
-      for (int c = 0; c < NT; ++c)
-        if (xc + c < A.W) dst[c] = qv[c];
+        for (int c = 0; c < NT; c += 4)
+          *reinterpret_cast<float4*>(dst + c) = make_float4(qv[c], qv[c + 1], qv[c + 2], qv[c + 3]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+          if (xc + c < A.W) dst[c] = qv[c];
+      }
     }
     const double a1 = row_sum_f64(s1);
     const double a2 = row_sum_f64(s2);
@@ -884,6 +891,49 @@ __global__ void k_rs_init(RsState* st, int nsets, int64_t per_set, int which) {
   S.known = 0;
   S.rank = which ? per_set / 2 : (per_set - 1) / 2;
   st[s] = S;
+}
+
+// The order statistic just above the selected one (rank + 1): the selected
+// key itself when more than rank + 1 keys are <= it, else the smallest key
+// above it. One pass: count of keys <= the selected key, minimum key above.
+__global__ __launch_bounds__(256) void k_rs_next(const float* vals, int64_t per_set, int mode, const double* med,
+                                                 const RsState* st, unsigned long long* cnt_le, uint32_t* min_gt) {
+  __shared__ uint32_t sh_c[256];
+  __shared__ uint32_t sh_m[256];
+  const int s = blockIdx.y;
+  const uint32_t sel = st[s].prefix;
+  const float* v = vals + (int64_t)s * per_set;
+  const double m = mode ? med[s] : 0.0;
+  uint32_t c = 0, mn = 0xFFFFFFFFu;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < per_set; i += (int64_t)gridDim.x * 256) {
+    const float q = v[i];
+    const uint32_t key = mode ? __float_as_uint((float)fabs((double)q - m)) : ord_key(q);
+    if (key <= sel) ++c;
+    else mn = min(mn, key);
+  }
+  sh_c[threadIdx.x] = c;
+  sh_m[threadIdx.x] = mn;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) {
+      sh_c[threadIdx.x] += sh_c[threadIdx.x + w];
+      sh_m[threadIdx.x] = min(sh_m[threadIdx.x], sh_m[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(cnt_le + s, (unsigned long long)sh_c[0]);
+    atomicMin(min_gt + s, sh_m[0]);
+  }
+}
+
+__global__ void k_rs_next_store(const RsState* st, int nsets, int64_t per_set, int mode,
+                                const unsigned long long* cnt_le, const uint32_t* min_gt, double* out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  const int64_t rank_hi = per_set / 2;
+  const uint32_t k = ((int64_t)cnt_le[s] >= rank_hi + 1) ? st[s].prefix : min_gt[s];
+  out[2 * s + 1] = mode ? (double)__uint_as_float(k) : (double)ord_val(k);
 }
 
 // value of the selected key: mode 0 -> q, mode 1 -> |q - med| (as float)

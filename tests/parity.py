@@ -56,6 +56,7 @@ def check_components(gpu: list, refc: list, values_ref: np.ndarray, mu: float, s
     """Compare the components of one set (triple or eta grid)."""
     z = (values_ref - mu) / sigma
     border = np.abs(z - tau) <= Z_BAND
+    labels = None
     g_by = {c["label"]: c for c in gpu}
     r_by = {c["label"]: c for c in refc}
     if not border.any():
@@ -68,13 +69,15 @@ def check_components(gpu: list, refc: list, values_ref: np.ndarray, mu: float, s
         gc = g_by[lab]
         for k in ("n_pix", "y0", "x0", "y1", "x1"):
             assert gc[k] == rc[k], (where, k, gc, rc)
-        W = values_ref.shape[1]
-        ys = slice(rc["y0"], rc["y1"] + 1)
-        xs = slice(rc["x0"], rc["x1"] + 1)
-        patch = values_ref[ys, xs]
-        top = patch.max()
-        cand = np.argwhere(patch >= top * (1 - 1e-5) if top > 0 else patch >= top * (1 + 1e-5))
-        allowed = {(rc["y0"] + a, rc["x0"] + b) for a, b in cand}
+        # cells of this component (other components may share its box)
+        if labels is None:
+            from scipy import ndimage
+
+            labels, _ = ndimage.label(z > tau, structure=np.ones((3, 3)))
+        own = labels == labels[rc["peak_y"], rc["peak_x"]]
+        top = values_ref[own].max()
+        near = (values_ref >= top * (1 - 1e-5)) if top > 0 else (values_ref >= top * (1 + 1e-5))
+        allowed = {(int(a), int(b)) for a, b in np.argwhere(own & near)}
         assert (gc["peak_y"], gc["peak_x"]) in allowed, (where, "peak", gc, rc)
         if len(allowed) == 1:
             assert (gc["peak_y"], gc["peak_x"]) == (rc["peak_y"], rc["peak_x"])

@@ -138,6 +138,33 @@ def test_median_mad_parity():
     check_candidates(cands, out, tau)
 
 
+def test_median_mad_odd_count():
+    """Odd cell count per triple: the middle order statistic is one value."""
+    X = structured_stack(43, 7, 37, 53)
+    tau = 3.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, window=3, sigma_est=1)
+    out = ref.detect(used, tau=tau, window=3, sigma_est=ref.MEDIAN_MAD)
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"])
+    check_candidates(cands, out, tau)
+
+
+def test_median_mad_ties():
+    """A periodic stack gives q maps whose values repeat many times: the two
+    middle order statistics (even count) and the MAD land inside runs of equal
+    values."""
+    rng = np.random.default_rng(44)
+    n, H, W = 8, 64, 256
+    tileval = rng.normal(size=(n, 8, 8)) * 2.0 + 5.0
+    X = np.tile(tileval, (1, H // 8, W // 8)).astype(np.float32)
+    tau = 2.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, window=1, sigma_est=1, branches=1)
+    out = ref.detect(used, tau=tau, window=1, sigma_est=ref.MEDIAN_MAD, branches=ref.IMAGE)
+    check_maps(q, out["q"])
+    assert len(np.unique(q[0])) <= 64
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"])
+    check_candidates(cands, out, tau)
+
+
 def test_median_mad_tiles_and_freq():
     X = structured_stack(42, 12, 96, 320)
     tau = 3.0
