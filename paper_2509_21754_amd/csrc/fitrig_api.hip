@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <numeric>
 #include <new>
 
 #include "fitrig.h"
@@ -52,6 +53,7 @@ struct fitrig_ctx {
   int32_t last_hip = 0;
   DevBuf stat_part, seg_max, seg_max2, tile_part, cube, cube_f, eta_d, eta_f, mu, sigma, flags, eta_st, M, qscratch;
   DevBuf hist, rs_state, rs_med, rs_dev, rs_next, chunk_cnt, counters, mom_tmp, max_key;
+  DevBuf rs_samp, rs_gbuf, rs_bkt, rs_cnt, rs_nvalid;
   DevBuf seg_entry, seg_mask, cell_q, parent, comp_of, c_root, c_npix, c_key, c_w, c_box, c_out;
   DevBuf bflag, blk_entry, blk_slot, band_start, band_end, rowslot;
   int64_t seg_cap = 0, comp_cap = 0;
@@ -161,6 +163,10 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
+__global__ void k_copy_stride2_u64(const unsigned long long* src, unsigned long long* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[2 * i];
+}
 // counters[CNT_TRUNC] |= overflow of this run; per-branch count; output base.
 __global__ void k_run_done(int64_t* c, int64_t seg_cap, int64_t blk_cap, int64_t comp_cap, int branch) {
   if (threadIdx.x || blockIdx.x) return;
@@ -211,6 +217,53 @@ fitrig_status moments(fitrig_ctx* ctx, hipStream_t st, const double* src, int ns
 }
 
 // Spread by exact median / MAD of a float array [nsets][per_set].
+// Exact median (mode 0) and MAD (mode 1) of every set. The order statistics
+// come from a three-pass radix selection (11, 11, 10 bits) on the keys; the
+// upper middle one of an even count from one more counting pass. For large
+// sets the selection runs on a gathered bracket: a sample of 2^20
+// keys gives two keys whose sample ranks lie 8 binomial standard deviations
+// either side of the middle; one pass counts the keys below the bracket and
+// gathers those inside; the bracket is checked on the host to hold both
+// middle ranks (else the full-array selection runs) and the selection runs
+// on the gathered keys. Same keys, same order statistics, either way.
+// n_max: largest number of valid keys in a set (sizes the grids: about 64 K
+// keys per workgroup, so the per-workgroup histograms merged into the global
+// one stay few).
+fitrig_status rs_select_middle(fitrig_ctx* ctx, hipStream_t st, const float* vals, int nsets, int64_t per_set,
+                               int kmode, int vmode, const double* med, const unsigned long long* nvalid,
+                               const unsigned long long* base, int64_t rank_lo, int64_t rank_hi, int64_t n_max,
+                               double* out) {
+  uint32_t* hist = (uint32_t*)ctx->hist.p;
+  RsState* rs = (RsState*)ctx->rs_state.p;
+  unsigned long long* cnt_le = (unsigned long long*)ctx->rs_next.p;
+  uint32_t* min_gt = (uint32_t*)(cnt_le + nsets);
+  const int shifts[3] = {21, 10, 0};
+  const int nbits[3] = {11, 11, 10};
+  const int gx = grid_for(n_max, 1 << 16, 1024);
+  if (base)
+    hipLaunchKernelGGL(k_rs_init_gathered, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, rank_lo, base);
+  else
+    hipLaunchKernelGGL(k_rs_init_rank, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, rank_lo);
+  for (int p = 0; p < 3; ++p) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, kmode, med, rs, shifts[p],
+                       nbits[p], hist, nvalid);
+    hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(64), 0, st, rs, hist, shifts[p], nbits[p]);
+  }
+  hipLaunchKernelGGL(k_rs_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, vmode, 0, out);
+  if (rank_hi != rank_lo) {
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, (int64_t*)cnt_le, (int64_t)nsets, (int64_t)0);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, min_gt, (int64_t)nsets, 0xFFFFFFFFu);
+    hipLaunchKernelGGL(k_rs_next, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, kmode, med, rs, cnt_le, min_gt,
+                       nvalid);
+    hipLaunchKernelGGL(k_rs_next_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, rank_hi, vmode,
+                       (const unsigned long long*)cnt_le, (const uint32_t*)min_gt, base, out);
+  } else {
+    hipLaunchKernelGGL(k_rs_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, vmode, 1, out);
+  }
+  LAUNCH_CHECK(ctx);
+  return FITRIG_OK;
+}
+
 fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, int nsets, int64_t per_set,
                             double* mu, double* sigma, uint32_t* flags) {
   fitrig_status rc;
@@ -218,37 +271,93 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
   if ((rc = ensure(ctx, ctx->rs_state, (size_t)nsets * sizeof(RsState))) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->rs_med, (size_t)nsets * 2 * 8)) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->rs_dev, (size_t)nsets * 2 * 8)) != FITRIG_OK) return rc;
-  uint32_t* hist = (uint32_t*)ctx->hist.p;
-  RsState* rs = (RsState*)ctx->rs_state.p;
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((int64_t)nsets * kHistBins)), dim3(256), 0, st, hist,
-                     (int64_t)nsets * kHistBins, 0u);
-  const int shifts[3] = {21, 10, 0};
-  const int nbits[3] = {11, 11, 10};
-  const int gx = grid_for(per_set, 256 * 16, 1024);
-  // median (mode 0), then MAD (mode 1): the lower middle order statistic by
-  // three radix passes; the upper one (even counts) by one more pass
   if ((rc = ensure(ctx, ctx->rs_next, (size_t)nsets * 12)) != FITRIG_OK) return rc;
-  unsigned long long* cnt_le = (unsigned long long*)ctx->rs_next.p;
-  uint32_t* min_gt = (uint32_t*)(cnt_le + nsets);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((int64_t)nsets * kHistBins)), dim3(256), 0, st, (uint32_t*)ctx->hist.p,
+                     (int64_t)nsets * kHistBins, 0u);
+  const int64_t r_lo = (per_set - 1) / 2, r_hi = per_set / 2;
+  constexpr int64_t kSample = 1 << 20;
+  const bool bracket = per_set >= 8 * kSample;
+  int64_t S = 0, a = 0, b = 0, cap = 0;
+  uint64_t mult = 0;
+  const bool vec = per_set % 4 == 0 && ((uintptr_t)vals & 15) == 0;
+  if (bracket) {
+    S = kSample;
+    // an odd multiplier near per_set * (golden ratio - 1), made coprime to per_set
+    mult = (uint64_t)((double)per_set * 0.6180339887498949) | 1u;
+    while (std::gcd(mult, (uint64_t)per_set) != 1) mult += 2;
+    // sample ranks of the two middle values, widened by 8 standard deviations
+    // of a binomial(S, 1/2) rank (4096 for S = 2^20)
+    const int64_t d = 4 * (int64_t)std::ceil(std::sqrt((double)S));
+    a = std::max<int64_t>(0, (r_lo * S) / per_set - d);
+    b = std::min<int64_t>(S - 1, (r_hi * S) / per_set + d + 1);
+    // expected gathered count (b - a) * per_set / S, room for four times it
+    cap = std::min<int64_t>(per_set, 4 * ((b - a + 1) * (per_set / S + 1)));
+    if ((rc = ensure(ctx, ctx->rs_samp, (size_t)nsets * S * 4)) != FITRIG_OK ||
+        (rc = ensure(ctx, ctx->rs_gbuf, (size_t)nsets * cap * 4)) != FITRIG_OK ||
+        (rc = ensure(ctx, ctx->rs_bkt, (size_t)nsets * 2 * 4)) != FITRIG_OK ||
+        (rc = ensure(ctx, ctx->rs_cnt, (size_t)nsets * 2 * 8)) != FITRIG_OK ||
+        (rc = ensure_host(ctx, (size_t)nsets * 2 * 8)) != FITRIG_OK)
+      return rc;
+  }
   for (int mode = 0; mode < 2; ++mode) {
     double* out = (double*)(mode ? ctx->rs_dev.p : ctx->rs_med.p);
-    hipLaunchKernelGGL(k_rs_init, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, per_set, 0);
-    for (int p = 0; p < 3; ++p) {
-      hipLaunchKernelGGL(k_rs_hist, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, mode, (const double*)mu, rs,
-                         shifts[p], nbits[p], hist);
-      hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(64), 0, st, rs, hist, shifts[p], nbits[p]);
+    bool done = false;
+    if (bracket) {
+      uint32_t* samp = (uint32_t*)ctx->rs_samp.p;
+      uint32_t* bkt = (uint32_t*)ctx->rs_bkt.p;
+      unsigned long long* cnt = (unsigned long long*)ctx->rs_cnt.p;
+      uint32_t* gbuf = (uint32_t*)ctx->rs_gbuf.p;
+      hipLaunchKernelGGL(k_rs_sample, dim3(grid_for(S, 256, 1024), nsets), dim3(256), 0, st, vals, per_set, mode,
+                         (const double*)mu, S, mult, samp);
+      // bracket keys: sample order statistics a and b (keys, mode 2)
+      for (int w = 0; w < 2; ++w) {
+        RsState* rs = (RsState*)ctx->rs_state.p;
+        const int shifts[3] = {21, 10, 0};
+        const int nbits[3] = {11, 11, 10};
+        hipLaunchKernelGGL(k_rs_init_rank, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, w ? b : a);
+        for (int p = 0; p < 3; ++p) {
+          hipLaunchKernelGGL(k_rs_hist, dim3(grid_for(S, 1 << 16, 1024), nsets), dim3(256), 0, st,
+                             (const float*)samp, S, 2, (const double*)mu, rs, shifts[p], nbits[p],
+                             (uint32_t*)ctx->hist.p, (const unsigned long long*)nullptr);
+          hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(64), 0, st, rs, (uint32_t*)ctx->hist.p, shifts[p],
+                             nbits[p]);
+        }
+        hipLaunchKernelGGL(k_rs_key_out, dim3((nsets + 63) / 64), dim3(64), 0, st, (const RsState*)rs, nsets, w,
+                           bkt);
+      }
+      hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, (int64_t*)cnt, (int64_t)(2 * nsets), (int64_t)0);
+      if (vec)
+        hipLaunchKernelGGL(k_rs_gather<true>, dim3(grid_for(per_set, 256 * 16, 512), nsets), dim3(256), 0, st, vals,
+                           per_set, mode, (const double*)mu, (const uint32_t*)bkt, cap, cnt, gbuf);
+      else
+        hipLaunchKernelGGL(k_rs_gather<false>, dim3(grid_for(per_set, 256 * 16, 512), nsets), dim3(256), 0, st,
+                           vals, per_set, mode, (const double*)mu, (const uint32_t*)bkt, cap, cnt, gbuf);
+      LAUNCH_CHECK(ctx);
+      unsigned long long* h = (unsigned long long*)ctx->h_stage;
+      HIP_TRY(ctx, hipMemcpyAsync(h, cnt, (size_t)nsets * 16, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipStreamSynchronize(st));
+      bool ok = true;
+      int64_t in_max = 1;
+      for (int s = 0; s < nsets && ok; ++s) {
+        const int64_t below = (int64_t)h[2 * s], in = (int64_t)h[2 * s + 1];
+        ok = in <= cap && below <= r_lo && r_hi < below + in;
+        in_max = std::max(in_max, in);
+      }
+      if (ok) {
+        // counts of gathered keys per set sit at cnt[2 s + 1]; rank offsets at cnt[2 s]
+        if ((rc = ensure(ctx, ctx->rs_nvalid, (size_t)nsets * 8)) != FITRIG_OK) return rc;
+        unsigned long long* nv = (unsigned long long*)ctx->rs_nvalid.p;
+        hipLaunchKernelGGL(k_copy_stride2_u64, dim3(1), dim3(64), 0, st, (const unsigned long long*)cnt + 1, nv,
+                           (int64_t)nsets);
+        if ((rc = rs_select_middle(ctx, st, (const float*)gbuf, nsets, cap, 2, mode, mu, nv, cnt, r_lo, r_hi,
+                                   in_max, out)) != FITRIG_OK)
+          return rc;
+        done = true;
+      }
     }
-    hipLaunchKernelGGL(k_rs_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, mode, 0, out);
-    if (per_set % 2 == 0) {
-      hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, (int64_t*)cnt_le, (int64_t)nsets, (int64_t)0);
-      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, min_gt, (int64_t)nsets, 0xFFFFFFFFu);
-      hipLaunchKernelGGL(k_rs_next, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, mode, (const double*)mu, rs,
-                         cnt_le, min_gt);
-      hipLaunchKernelGGL(k_rs_next_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, per_set, mode,
-                         (const unsigned long long*)cnt_le, (const uint32_t*)min_gt, out);
-    } else {
-      hipLaunchKernelGGL(k_rs_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, mode, 1, out);
-    }
+    if (!done && (rc = rs_select_middle(ctx, st, vals, nsets, per_set, mode, mode, mu, nullptr, nullptr, r_lo, r_hi,
+                                        per_set, out)) != FITRIG_OK)
+      return rc;
     hipLaunchKernelGGL(k_rs_finish, dim3((nsets + 63) / 64), dim3(64), 0, st, (const double*)ctx->rs_med.p,
                        (const double*)ctx->rs_dev.p, nsets, mu, sigma, flags, mode);
   }
@@ -825,7 +934,8 @@ fitrig_status fitrig_destroy(fitrig_ctx* ctx) {
                     &ctx->chunk_cnt, &ctx->counters, &ctx->seg_entry, &ctx->seg_mask, &ctx->cell_q,  &ctx->parent,
                     &ctx->comp_of,   &ctx->c_root,   &ctx->c_npix,    &ctx->c_key,    &ctx->c_w,     &ctx->c_box,
                     &ctx->c_out,     &ctx->bflag,    &ctx->blk_entry, &ctx->blk_slot, &ctx->band_start,
-                    &ctx->band_end,  &ctx->rowslot,  &ctx->rs_next};
+                    &ctx->band_end,  &ctx->rowslot,  &ctx->rs_next,  &ctx->rs_samp,  &ctx->rs_gbuf,
+                    &ctx->rs_bkt,    &ctx->rs_cnt,   &ctx->rs_nvalid};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);

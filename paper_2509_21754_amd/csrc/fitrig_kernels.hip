@@ -841,8 +841,18 @@ struct RsState {
 };
 
 
+// Selection key of a value: mode 0 -> order key of q, 1 -> bits of the
+// float |q - med| (non-negative, so the bits order like the values), 2 -> the
+// array already holds keys.
+__device__ __forceinline__ uint32_t rs_key(float q, int mode, double m) {
+  return mode == 2 ? __float_as_uint(q) : mode ? __float_as_uint((float)fabs((double)q - m)) : ord_key(q);
+}
+
+// Histogram of the next digit of the keys that match the prefix selected so
+// far. nvalid (nullable): valid entries per set (arrays of per_set slots).
 __global__ __launch_bounds__(256) void k_rs_hist(const float* vals, int64_t per_set, int mode, const double* med,
-                                                 const RsState* st, int shift, int nbits, uint32_t* hist) {
+                                                 const RsState* st, int shift, int nbits, uint32_t* hist,
+                                                 const unsigned long long* nvalid) {
   __shared__ uint32_t h[kHistBins];
   const int s = blockIdx.y;
   for (int i = threadIdx.x; i < kHistBins; i += 256) h[i] = 0;
@@ -850,10 +860,10 @@ __global__ __launch_bounds__(256) void k_rs_hist(const float* vals, int64_t per_
   const RsState S = st[s];
   const uint32_t dmask = (1u << nbits) - 1u;
   const float* v = vals + (int64_t)s * per_set;
-  const double m = mode ? med[s] : 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < per_set; i += (int64_t)gridDim.x * 256) {
-    const float q = v[i];
-    const uint32_t key = mode ? __float_as_uint((float)fabs((double)q - m)) : ord_key(q);
+  const double m = mode == 1 ? med[s] : 0.0;
+  const int64_t n = nvalid ? min((int64_t)nvalid[s], per_set) : per_set;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint32_t key = rs_key(v[i], mode, m);
     if ((key & S.known) == S.prefix) atomicAdd(&h[(key >> shift) & dmask], 1u);
   }
   __syncthreads();
@@ -883,6 +893,150 @@ __global__ void k_rs_pick(RsState* st, uint32_t* hist, int shift, int nbits) {
   for (int i = 0; i < nb; ++i) h[i] = 0;
 }
 
+// Every set searches the same rank.
+__global__ void k_rs_init_rank(RsState* st, int nsets, int64_t rank) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  RsState S;
+  S.prefix = 0;
+  S.known = 0;
+  S.rank = rank;
+  st[s] = S;
+}
+
+// Rank within the gathered keys: global rank minus the keys below them.
+__global__ void k_rs_init_gathered(RsState* st, int nsets, int64_t rank, const unsigned long long* cnt) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  RsState S;
+  S.prefix = 0;
+  S.known = 0;
+  S.rank = rank - (int64_t)cnt[2 * s];
+  st[s] = S;
+}
+
+// Keys of a sample of each set: sample i is value (i * mult) mod per_set
+// with mult odd and coprime to per_set, so the samples spread over the set
+// without following its rows or columns.
+__global__ void k_rs_sample(const float* vals, int64_t per_set, int mode, const double* med, int64_t S,
+                            uint64_t mult, uint32_t* samp) {
+  const int s = blockIdx.y;
+  const double m = mode == 1 ? med[s] : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x) {
+    // i < 2^20 and mult < per_set < 2^32: the product fits in 64 bits
+    const uint64_t pos = ((uint64_t)i * mult) % (uint64_t)per_set;
+    samp[(int64_t)s * S + i] = rs_key(vals[(int64_t)s * per_set + (int64_t)pos], mode, m);
+  }
+}
+
+// selected key of each set -> bkt[2 s + which]
+__global__ void k_rs_key_out(const RsState* st, int nsets, int which, uint32_t* bkt) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nsets) bkt[2 * s + which] = st[s].prefix;
+}
+
+// One pass over a set: keys below bkt[2s] are counted (cnt[2s]); keys in
+// [bkt[2s], bkt[2s+1]] are counted (cnt[2s+1]) and the first cap of them
+// gathered into gbuf[s * cap ...] (in no particular order: a selection does
+// not need one). A workgroup stages its keys in LDS and appends them with one
+// global atomic per flush.
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Each thread takes 16 keys per round (four 16-byte loads when VEC); a
+// workgroup scan places the keys inside the bracket in an LDS stage, which is
+// appended to the set's output with one global atomic per flush (atomics on
+// one address per round would serialise the whole pass).
+constexpr int kGatherStage = 8192;
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_rs_gather(const float* vals, int64_t per_set, int mode, const double* med,
+                                                   const uint32_t* bkt, int64_t cap, unsigned long long* cnt,
+                                                   uint32_t* gbuf) {
+  __shared__ uint32_t stage[kGatherStage];
+  __shared__ uint32_t wsum[4];
+  __shared__ unsigned long long gbase;
+  __shared__ uint32_t sh[256];
+  const int s = blockIdx.y;
+  const uint32_t lo = bkt[2 * s], hi = bkt[2 * s + 1];
+  const float* v = vals + (int64_t)s * per_set;
+  uint32_t* out = gbuf + (int64_t)s * cap;
+  const double m = mode == 1 ? med[s] : 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t below = 0, nst = 0;
+  constexpr int64_t kRound = 256 * 16;
+  const int64_t step = (int64_t)gridDim.x * kRound;
+  // every thread of the workgroup runs the same rounds (barriers inside)
+  for (int64_t base = blockIdx.x * kRound; base < per_set; base += step) {
+    uint32_t k[16];
+    bool ok[16];
+    if (VEC) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t i = base + 4 * ((int64_t)j * 256 + threadIdx.x);  // per_set % 4 == 0
+        const bool in_set = i < per_set;
+        const float4 q = in_set ? *reinterpret_cast<const float4*>(v + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+        k[4 * j + 0] = rs_key(q.x, mode, m);
+        k[4 * j + 1] = rs_key(q.y, mode, m);
+        k[4 * j + 2] = rs_key(q.z, mode, m);
+        k[4 * j + 3] = rs_key(q.w, mode, m);
+        ok[4 * j + 0] = ok[4 * j + 1] = ok[4 * j + 2] = ok[4 * j + 3] = in_set;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int64_t i = base + (int64_t)j * 256 + threadIdx.x;
+        ok[j] = i < per_set;
+        k[j] = ok[j] ? rs_key(v[i], mode, m) : 0u;
+      }
+    }
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      below += (ok[j] && k[j] < lo) ? 1u : 0u;
+      c += (ok[j] && k[j] >= lo && k[j] <= hi) ? 1u : 0u;
+    }
+    const uint32_t inc = wave_incl_scan(c);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    const uint32_t w0 = wsum[0], w1 = wsum[1], w2 = wsum[2], w3 = wsum[3];
+    const uint32_t tot = w0 + w1 + w2 + w3;
+    const uint32_t woff = (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
+    if (c) {
+      uint32_t p = nst + woff + inc - c;  // nst <= kGatherStage - kRound, p < kGatherStage
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (ok[j] && k[j] >= lo && k[j] <= hi) stage[p++] = k[j];
+    }
+    nst += tot;
+    const bool flush = nst > kGatherStage - kRound || base + step >= per_set;
+    __syncthreads();  // stage written and wsum read by every thread
+    if (flush) {
+      if (threadIdx.x == 0) gbase = nst ? atomicAdd(cnt + 2 * s + 1, (unsigned long long)nst) : 0ull;
+      __syncthreads();
+      const unsigned long long g0 = gbase;
+      for (uint32_t j = threadIdx.x; j < nst; j += 256)
+        if ((int64_t)(g0 + j) < cap) out[g0 + j] = stage[j];
+      nst = 0;
+      __syncthreads();
+    }
+  }
+  sh[threadIdx.x] = below;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(cnt + 2 * s, (unsigned long long)sh[0]);
+}
+
 __global__ void k_rs_init(RsState* st, int nsets, int64_t per_set, int which) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsets) return;
@@ -897,17 +1051,18 @@ __global__ void k_rs_init(RsState* st, int nsets, int64_t per_set, int which) {
 // key itself when more than rank + 1 keys are <= it, else the smallest key
 // above it. One pass: count of keys <= the selected key, minimum key above.
 __global__ __launch_bounds__(256) void k_rs_next(const float* vals, int64_t per_set, int mode, const double* med,
-                                                 const RsState* st, unsigned long long* cnt_le, uint32_t* min_gt) {
+                                                 const RsState* st, unsigned long long* cnt_le, uint32_t* min_gt,
+                                                 const unsigned long long* nvalid) {
   __shared__ uint32_t sh_c[256];
   __shared__ uint32_t sh_m[256];
   const int s = blockIdx.y;
   const uint32_t sel = st[s].prefix;
   const float* v = vals + (int64_t)s * per_set;
-  const double m = mode ? med[s] : 0.0;
+  const double m = mode == 1 ? med[s] : 0.0;
+  const int64_t n = nvalid ? min((int64_t)nvalid[s], per_set) : per_set;
   uint32_t c = 0, mn = 0xFFFFFFFFu;
-  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < per_set; i += (int64_t)gridDim.x * 256) {
-    const float q = v[i];
-    const uint32_t key = mode ? __float_as_uint((float)fabs((double)q - m)) : ord_key(q);
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint32_t key = rs_key(v[i], mode, m);
     if (key <= sel) ++c;
     else mn = min(mn, key);
   }
@@ -927,12 +1082,14 @@ __global__ __launch_bounds__(256) void k_rs_next(const float* vals, int64_t per_
   }
 }
 
-__global__ void k_rs_next_store(const RsState* st, int nsets, int64_t per_set, int mode,
-                                const unsigned long long* cnt_le, const uint32_t* min_gt, double* out) {
+// base (nullable): keys below the searched range, not in the counted array
+__global__ void k_rs_next_store(const RsState* st, int nsets, int64_t rank_hi, int mode,
+                                const unsigned long long* cnt_le, const uint32_t* min_gt,
+                                const unsigned long long* base, double* out) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsets) return;
-  const int64_t rank_hi = per_set / 2;
-  const uint32_t k = ((int64_t)cnt_le[s] >= rank_hi + 1) ? st[s].prefix : min_gt[s];
+  const int64_t le = (int64_t)cnt_le[s] + (base ? (int64_t)base[2 * s] : 0);
+  const uint32_t k = (le >= rank_hi + 1) ? st[s].prefix : min_gt[s];
   out[2 * s + 1] = mode ? (double)__uint_as_float(k) : (double)ord_val(k);
 }
 

@@ -165,6 +165,32 @@ def test_median_mad_ties():
     check_candidates(cands, out, tau)
 
 
+@pytest.mark.parametrize("W", [4096, 4097])
+def test_median_mad_large_sets(W):
+    """Sets of more than 8 * 2^20 cells take the sample-bracket-gather
+    selection (even and odd counts)."""
+    rng = np.random.default_rng(W)
+    X = (rng.normal(size=(4, 4096, W)) + 3.0).astype(np.float32)
+    tau = 10.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, window=3, sigma_est=1, branches=1, with_maps=False)
+    out = ref.detect(used, tau=tau, window=3, sigma_est=ref.MEDIAN_MAD, branches=ref.IMAGE)
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"])
+    assert rc == 0
+    check_candidates(cands, out, tau)
+
+
+def test_median_mad_large_periodic():
+    """A map periodic along rows at the sampling stride: the strided sample
+    sees one phase only, the bracket misses and the full selection runs."""
+    rng = np.random.default_rng(45)
+    tileval = rng.normal(size=(4, 8, 8)) * 2.0 + 5.0
+    X = np.tile(tileval, (1, 512, 512)).astype(np.float32)
+    tau = 2.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, window=1, sigma_est=1, branches=1, with_maps=False)
+    out = ref.detect(used, tau=tau, window=1, sigma_est=ref.MEDIAN_MAD, branches=ref.IMAGE, keep_maps=False)
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"])
+
+
 def test_median_mad_tiles_and_freq():
     X = structured_stack(42, 12, 96, 320)
     tau = 3.0
