@@ -117,6 +117,22 @@ void launch_stream(int H, dim3 grid, hipStream_t st, const StreamArgs& A) {
   }
 }
 
+template <typename T>
+void launch_tile_stream(int tile, bool rs, dim3 grid, hipStream_t st, const TileStreamArgs& A) {
+  switch (tile) {
+#define CASE(t)                                                                                           \
+  case t:                                                                                                 \
+    if (rs)                                                                                               \
+      hipLaunchKernelGGL((k_tile_stream<T, t, true>), grid, dim3(kLanes), 0, st, A);                      \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_tile_stream<T, t, false>), grid, dim3(kLanes), 0, st, A);                     \
+    break;
+    CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+    default: break;
+  }
+}
+
 struct RecomputeArgs {
   const void* base;
   const void* c0;
@@ -647,6 +663,47 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     }
   }
 
+  // power-of-two tiles up to 32: streaming kernel (every frame read once);
+  // other sizes: the tile kernel that reads three frames per triple
+  const bool pow2_tile = tile <= 32 && (tile & (tile - 1)) == 0;
+  if (!have_cube && (freq || (img && !sliding)) && pow2_tile) {
+    // streaming tile kernel: every frame read once, the cube written directly
+    if ((rc = ensure(ctx, ctx->cube, (size_t)np * Ty * Tx * 8)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->cube_f, (size_t)np * Ty * Tx * 4)) != FITRIG_OK) return rc;
+    TileStreamArgs A;
+    A.base = c.stack;
+    A.carry0 = c.carry0;
+    A.carry1 = c.carry1;
+    A.ncarry = c.ncarry;
+    A.n = c.n;
+    A.plane = plane;
+    A.H = c.H;
+    A.W = c.W;
+    A.tile = tile;
+    A.nchunk = (c.W + kLanes - 1) / kLanes;
+    const int tpb = std::min(32 / tile, kTileTpbMax);
+    A.nbands = (Ty + tpb - 1) / tpb;
+    A.Ty = Ty;
+    A.Tx = Tx;
+    A.r_signed = cfg.r_signed;
+    A.Cf = (float)cfg.C;
+    A.cube = (double*)ctx->cube.p;
+    A.cube_f = (float*)ctx->cube_f.p;
+    A.max_key = (uint32_t*)ctx->max_key.p;
+    const int64_t nwg = (int64_t)A.nchunk * A.nbands;
+    if (nwg > INT32_MAX) return FITRIG_E_INVAL;
+    switch (c.dtype) {
+      case FITRIG_F32: launch_tile_stream<float>(tile, cfg.r_signed != 0, dim3((unsigned)nwg), st, A); break;
+      case FITRIG_F16: launch_tile_stream<__half>(tile, cfg.r_signed != 0, dim3((unsigned)nwg), st, A); break;
+      default: launch_tile_stream<bf16_t>(tile, cfg.r_signed != 0, dim3((unsigned)nwg), st, A); break;
+    }
+    LAUNCH_CHECK(ctx);
+    if (!have_max) {
+      have_max = true;
+      if ((rc = mark(1)) != FITRIG_OK) return rc;
+    }
+    have_cube = true;
+  }
   if ((!have_cube && (freq || (img && !sliding)))) {
     const int nchunk = (c.W + kLanes - 1) / kLanes;
     const int pieces = (kLanes + tile - 1) / tile + 1;

@@ -57,6 +57,27 @@ struct TileArgs {
   uint32_t* max_key;     // order-preserving key of the stack maximum (atomic max)
 };
 
+// Streaming tile-mode kernel arguments (tile a power of two <= 32): one
+// workgroup per band of whole tile rows and chunk of 256 columns, every frame
+// read once.
+struct TileStreamArgs {
+  const void* base;
+  const void* carry0;
+  const void* carry1;
+  int32_t ncarry;
+  int32_t n;
+  int64_t plane;
+  int32_t H, W;
+  int32_t tile;
+  int32_t nchunk, nbands;
+  int32_t Ty, Tx;
+  int32_t r_signed;
+  float Cf;
+  double* cube;          // [n-2][Ty][Tx]
+  float* cube_f;         // [n-2][Ty][Tx]
+  uint32_t* max_key;     // order-preserving key of the stack maximum (atomic max)
+};
+
 // Layout of the 64-cell row segments a selection works on.
 struct SegLayout {
   int32_t Ho, Wo;        // cell grid of one set (one triple)

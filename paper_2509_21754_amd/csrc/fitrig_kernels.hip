@@ -709,6 +709,111 @@ __global__ __launch_bounds__(kLanes) void k_tile(TileArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Streaming tile-mode kernel (tile a power of two <= 32): one workgroup per (band of tpb
+// whole tile rows, chunk of whole tiles); each lane owns a column, keeps the
+// previous frame and the previous difference of the band's rows in
+// registers and walks every frame once. Per triple it accumulates, per tile
+// row of the band, the column's sum Delta, max Delta and sum r (FP32 over at
+// most 32 rows), then one job per tile sums its columns in FP64 and writes
+// the tile's q (Eq. (6) with the in-image count) to the cube.
+// ---------------------------------------------------------------------------
+constexpr int kTileTpbMax = 8;    // tile rows per band
+template <typename T, int TILE, bool RS>
+__global__ __launch_bounds__(kLanes) void k_tile_stream(TileStreamArgs A) {
+  constexpr int TPB = (32 / TILE) < kTileTpbMax ? (32 / TILE) : kTileTpbMax;
+  constexpr int ROWS = TPB * TILE;
+  constexpr int TPC = kLanes / TILE;        // whole tiles per chunk
+  __shared__ float col[TPB][3][kLanes];
+  __shared__ int mxs[kLanes / 64];
+  const int lane = threadIdx.x;
+  const int chunk = blockIdx.x % A.nchunk, band = blockIdx.x / A.nchunk;
+  const int x = chunk * kLanes + lane;
+  const bool cv = x < A.W;
+  const int y0 = band * ROWS;
+  float P[ROWS], D[ROWS];
+  int mxi = INT32_MIN;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    P[i] = 0.0f;
+    D[i] = 0.0f;
+  }
+  for (int k = 0; k < A.n; ++k) {
+    const T* fr = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, k);
+    float sd[TPB], md[TPB], sr[TPB];
+#pragma unroll
+    for (int t = 0; t < TPB; ++t) {
+      sd[t] = 0.0f;
+      md[t] = 0.0f;
+      sr[t] = 0.0f;
+    }
+    // all rows of the frame are requested before any is used
+    float C[ROWS];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      const int y = y0 + i;
+      C[i] = (cv && y < A.H) ? to_f<T>(fr[(int64_t)y * A.W + x]) : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      const int y = y0 + i;
+      const bool in = cv && y < A.H;
+      const float c = C[i];
+      mxi = max(mxi, __float_as_int(c));
+      const float dn = c - P[i];
+      if (k >= 2 && in) {
+        float dl, rl;
+        pix_terms<RS>(dn, D[i], P[i], A.Cf, dl, rl);
+        sd[i / TILE] += dl;
+        md[i / TILE] = fmaxf(md[i / TILE], dl);
+        sr[i / TILE] += rl;
+      }
+      D[i] = dn;
+      P[i] = c;
+    }
+    if (k < 2) continue;
+    const int s = k - 2;
+    __syncthreads();  // the previous triple's jobs have read col
+#pragma unroll
+    for (int t = 0; t < TPB; ++t) {
+      col[t][0][lane] = sd[t];
+      col[t][1][lane] = md[t];
+      col[t][2][lane] = sr[t];
+    }
+    __syncthreads();
+    // one job per (tile row of the band, tile of the chunk)
+    for (int job = lane; job < TPB * TPC; job += kLanes) {
+      const int t = job / TPC, j = job - t * TPC;
+      const int ty = band * TPB + t;
+      const int tx = chunk * TPC + j;
+      if (ty >= A.Ty || tx >= A.Tx) continue;
+      const int ca = j * TILE;
+      const int cb = min(ca + TILE, A.W - chunk * kLanes);
+      double a0 = 0.0, a2 = 0.0;
+      float a1 = 0.0f;
+      for (int c = ca; c < cb; ++c) {
+        a0 += (double)col[t][0][c];
+        a1 = fmaxf(a1, col[t][1][c]);
+        a2 += (double)col[t][2][c];
+      }
+      const double n = (double)(min(ty * TILE + TILE, A.H) - ty * TILE) * (double)(cb - ca);
+      const double v = (a0 / n) * (double)a1 * (a2 / n);
+      const int64_t o = ((int64_t)s * A.Ty + ty) * A.Tx + tx;
+      A.cube[o] = v;
+      A.cube_f[o] = (float)v;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mxi = max(mxi, __shfl_xor(mxi, off));
+  if ((lane & 63) == 0) mxs[lane >> 6] = mxi;
+  __syncthreads();
+  if (lane == 0) {
+    int m = mxs[0];
+    for (int w = 1; w < kLanes / 64; ++w) m = max(m, mxs[w]);
+    atomicMax(A.max_key, ord_key(__int_as_float(m)));
+  }
+}
+
 // Tile q from pieces: (sum Delta / n) max Delta (sum r / n), n = cells of the
 // (possibly partial) tile in the image (Eq. (6) with the actual count).
 __global__ void k_tile_merge(const double* part, int nsets, int nbands_part, int bpt, int nchunk, int cw,

@@ -115,7 +115,8 @@ def test_workload_c1_crop(tau):
 
 
 @pytest.mark.parametrize("tile,H,W,n", [(32, 100, 300, 8), (5, 37, 53, 6), (1, 9, 11, 4), (64, 70, 300, 6),
-                                        (7, 64, 512, 5)])
+                                        (7, 64, 512, 5), (8, 203, 777, 7), (2, 70, 530, 5), (16, 260, 1030, 6),
+                                        (4, 33, 257, 9)])
 def test_tile_mode_parity(tile, H, W, n):
     X = structured_stack(30 + tile, n, H, W)
     tau = 2.5
