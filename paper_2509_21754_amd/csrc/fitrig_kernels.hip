@@ -488,16 +488,17 @@ struct Stream {
     const int cb = chv ? 17 * ch : 0;
     float os[NT], om[NT], orr[NT];
     {
-      float h[NH];
+      // all three rows of inputs are requested before the windows run
+      float h0[NH], h1[NH], h2[NH];
 #pragma unroll
-      for (int i = 0; i < NH; ++i) h[i] = sh.V[0][r][cb + i + (i >> 4)];
-      Win<H, NT, false>::run(h, os, nullptr);
-#pragma unroll
-      for (int i = 0; i < NH; ++i) h[i] = sh.V[1][r][cb + i + (i >> 4)];
-      WinMax<H, NT>::run(h, om);
-#pragma unroll
-      for (int i = 0; i < NH; ++i) h[i] = sh.V[2][r][cb + i + (i >> 4)];
-      Win<H, NT, false>::run(h, orr, nullptr);
+      for (int i = 0; i < NH; ++i) {
+        h0[i] = sh.V[0][r][cb + i + (i >> 4)];
+        h1[i] = sh.V[1][r][cb + i + (i >> 4)];
+        h2[i] = sh.V[2][r][cb + i + (i >> 4)];
+      }
+      Win<H, NT, false>::run(h0, os, nullptr);
+      WinMax<H, NT>::run(h1, om);
+      Win<H, NT, false>::run(h2, orr, nullptr);
     }
     float qv[NT];
     // FP64 moments: q^2 of a float is exact in double, so a constant map
