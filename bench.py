@@ -235,11 +235,12 @@ def precision_report(spec, stack, raw, origins, stats, cands) -> dict:
     }
 
 
-def serving_replay(n_req: int, slots: int, rate_hz: float, budget_gib: float, dev) -> dict:
+def serving_replay(n_req: int, slots: int, rate_hz: float, budget_gib: float, dev, freq_window: int = 30) -> dict:
     """The serving workload: Poisson arrivals of snapshot stacks of 16 fields
     (size class 2048^2 / 4096^2 / 8192^2 and storage dtype fixed per field,
     16 / 32 / 128 snapshots per request) replayed in real time through the
-    server, then the same requests submitted at once (capacity)."""
+    server, then the same requests submitted at once (capacity). Each
+    request's frequency branch covers its field's last freq_window triples."""
     import numpy as np
     import torch
 
@@ -263,7 +264,7 @@ def serving_replay(n_req: int, slots: int, rate_hz: float, budget_gib: float, de
     def run(realtime: bool):
         cursor = {}
         with Server(n_slots=slots, max_fields=32, mem_budget=int(budget_gib * (1 << 30)), window=7,
-                    max_pixels=max_px, max_snap=n_pool + 2) as srv:
+                    max_pixels=max_px, max_snap=n_pool + 2, freq_window=freq_window) as srv:
             # warm every slot and size class outside the timed part (fields 100+)
             for j, key in enumerate(sorted(pools)):
                 tk = srv.submit(100 + j, pools[key][:3], 6.0)
@@ -291,7 +292,7 @@ def serving_replay(n_req: int, slots: int, rate_hz: float, budget_gib: float, de
         return res, wall
 
     out = {"requests": n_req, "rate_hz": rate_hz, "slots": slots, "mem_budget_gib": budget_gib,
-           "fields": 16, "window": 7, "tau": 6.0}
+           "fields": 16, "window": 7, "tau": 6.0, "freq_window": freq_window}
     for mode in ("realtime", "saturated"):
         res, wall = run(mode == "realtime")
         bad = [o["status"] for o, _ in res if o["status"] not in (0, -4)]
@@ -302,7 +303,8 @@ def serving_replay(n_req: int, slots: int, rate_hz: float, budget_gib: float, de
         px = sum(r["n"] * r["size"] ** 2 for _, r in res)
         d = {"mpix_s": round(px / ((last - first) / 1e9) / 1e6, 1), "wall_s": round(wall, 3),
              "p50_ms": round(pctl(lat, 0.5), 3), "p99_ms": round(pctl(lat, 0.99), 3),
-             "queue_wait_p50_ms": round(pctl(wait, 0.5), 3), "errors": len(bad)}
+             "queue_wait_p50_ms": round(pctl(wait, 0.5), 3), "errors": len(bad),
+             "freq_branch_runs": sum(1 for o, _ in res if o["freq_triples"] > 0)}
         for dt in ("f16", "f32"):
             l2 = [x for x, (_, r) in zip(lat, res) if r["dtype"] == dt]
             pxd = [r["n"] * r["size"] ** 2 for _, r in res if r["dtype"] == dt]
@@ -334,6 +336,8 @@ def main() -> int:
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-budget-gib", type=float, default=48.0)
+    ap.add_argument("--serving-freq-window", type=int, default=30,
+                    help="triples of a field's history the frequency branch covers (0 = the request's own)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -444,7 +448,8 @@ def main() -> int:
     torch.cuda.empty_cache()
     if not args.no_serving:
         print("[bench] serving replay", file=sys.stderr, flush=True)
-        out["serving"] = serving_replay(args.serving_requests, args.serving_slots, 40.0, args.serving_budget_gib, dev)
+        out["serving"] = serving_replay(args.serving_requests, args.serving_slots, 40.0, args.serving_budget_gib, dev,
+                                        args.serving_freq_window)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)

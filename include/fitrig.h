@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define FITRIG_ABI_VERSION 1
+#define FITRIG_ABI_VERSION 2
 
 typedef int32_t fitrig_status;
 #define FITRIG_OK 0
@@ -186,7 +186,10 @@ int32_t fitrig_abi_version(void);
  * snapshots and its running maximum M resident on the device (the paper
  * estimates M from past snapshots in real time, Sec. 2.2.4), so a request's
  * first two triples reach back into the previous request and triples are
- * numbered per field. Requests are admitted while a slot and the memory
+ * numbered per field. With freq_window > 0 it also keeps the tile cube of
+ * the field's last freq_window triples, and each request's frequency branch
+ * (Sec. 2.3) transforms that window of the field's history rather than the
+ * request's own triples alone. Requests are admitted while a slot and the memory
  * budget allow; admitted requests of different fields run concurrently on
  * separate streams, requests of one field run in submission order. Each
  * result is identical to running the same frames alone.
@@ -201,6 +204,12 @@ typedef struct {
                            beyond it evicts the least recently used idle field */
   int64_t mem_budget;   /* device bytes for slot scratch plus field state; 0 = no limit */
   int64_t cand_cap;     /* candidates kept per result (default 65536) */
+  int32_t freq_window;  /* 0 (default): a request's frequency branch covers its
+                           own triples; 1..2048: it covers the field's last
+                           freq_window triples (FP64 tile cube kept per field,
+                           freq_window * ceil(H/tile) * ceil(W/tile) * 8 bytes,
+                           counted in mem_budget). The branch runs once the
+                           covered series has at least 4 triples. */
 } fitrig_server_config;
 
 typedef struct {
@@ -213,6 +222,9 @@ typedef struct {
   const fitrig_candidate* cand; /* min(n_cand, cand_cap) records, owned by the server until released */
   double M;                 /* running max(max over every frame of the field so far, C) */
   int64_t t_submit_ns, t_start_ns, t_done_ns; /* steady-clock stamps: submit, launch, results on the host */
+  int32_t freq_triples;     /* triples the frequency branch covered: the field's
+                               triples first_triple + n_triples - freq_triples ..
+                               first_triple + n_triples - 1 (0 = it did not run) */
 } fitrig_result;
 
 /* Fills cfg with the defaults above. */
@@ -220,7 +232,7 @@ void fitrig_server_config_default(fitrig_server_config* cfg);
 
 /* Creates the server: one context and stream per slot, worker threads.
  * Errors: E_INVAL (null, bad base config, n_slots < 1, max_fields < 1,
- * cand_cap < 0, mem_budget < 0), E_NOMEM, E_HIP. */
+ * cand_cap < 0, mem_budget < 0, freq_window outside 0..2048), E_NOMEM, E_HIP. */
 fitrig_status fitrig_server_create(const fitrig_server_config* cfg, fitrig_server** out);
 
 /* Submits a stack (device, [n_snap][H][W], must stay valid and unchanged

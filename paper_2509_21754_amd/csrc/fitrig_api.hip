@@ -52,6 +52,7 @@ struct fitrig_ctx {
   hipStream_t stream = nullptr;
   int32_t last_hip = 0;
   DevBuf stat_part, seg_max, seg_max2, tile_part, cube, cube_f, eta_d, eta_f, mu, sigma, flags, eta_st, M, qscratch;
+  DevBuf fseries;  // frequency series over [history | call] (serving)
   DevBuf hist, rs_state, rs_med, rs_dev, rs_next, chunk_cnt, counters, mom_tmp, max_key;
   DevBuf rs_samp, rs_gbuf, rs_bkt, rs_cnt, rs_nvalid;
   DevBuf seg_entry, seg_mask, cell_q, parent, comp_of, c_root, c_npix, c_key, c_w, c_box, c_out;
@@ -217,6 +218,7 @@ struct Call {
   float* index_map;
   float* eta_map;
   hipStream_t st;
+  const FreqHist* hist;   // serving: frequency branch over the field's recent triples, nullable
 };
 
 // Mean / population std per set, two fixed-order stages.
@@ -557,7 +559,13 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   const int halo = cfg.window / 2;
   const int64_t plane = (int64_t)c.H * c.W;
   const bool img = (cfg.branches & FITRIG_IMAGE) != 0;
-  const bool freq = (cfg.branches & FITRIG_FREQ) != 0 && np >= 4 && np <= 2048;
+  // frequency branch: over this call's triples, or (with a history) over
+  // the last hist->cap triples of [history | this call]
+  const bool want_freq = (cfg.branches & FITRIG_FREQ) != 0;
+  const bool ring = want_freq && c.hist && c.hist->cap > 0;
+  const int nfreq = ring ? (int)std::min<int64_t>(c.hist->cap, (int64_t)c.hist->n_in + np) : np;
+  const bool freq = want_freq && nfreq >= 4 && nfreq <= 2048;
+  const bool cube_needed = freq || ring;
   const bool sliding = cfg.mode == FITRIG_SLIDING;
   const int tile = cfg.tile;
   const int Ty = (c.H + tile - 1) / tile, Tx = (c.W + tile - 1) / tile;
@@ -600,7 +608,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   if (img && sliding) {
     const int64_t nwg = (int64_t)ncol * nbands;
     if (nwg > INT32_MAX) return FITRIG_E_INVAL;
-    const bool byprod = freq && tile == 32;
+    const bool byprod = cube_needed && tile == 32;
     if ((rc = ensure(ctx, ctx->stat_part, (size_t)np * nwg * 16 * 16)) != FITRIG_OK) return rc;
     if ((rc = ensure(ctx, ctx->seg_max, (size_t)np * c.H * nseg_row * 4)) != FITRIG_OK) return rc;
     if (byprod && (rc = ensure(ctx, ctx->tile_part, (size_t)np * nbands * ncol * kPieces * 3 * 8)) != FITRIG_OK)
@@ -666,7 +674,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   // power-of-two tiles up to 32: streaming kernel (every frame read once);
   // other sizes: the tile kernel that reads three frames per triple
   const bool pow2_tile = tile <= 32 && (tile & (tile - 1)) == 0;
-  if (!have_cube && (freq || (img && !sliding)) && pow2_tile) {
+  if (!have_cube && (cube_needed || (img && !sliding)) && pow2_tile) {
     // streaming tile kernel: every frame read once, the cube written directly
     if ((rc = ensure(ctx, ctx->cube, (size_t)np * Ty * Tx * 8)) != FITRIG_OK) return rc;
     if ((rc = ensure(ctx, ctx->cube_f, (size_t)np * Ty * Tx * 4)) != FITRIG_OK) return rc;
@@ -704,7 +712,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     }
     have_cube = true;
   }
-  if ((!have_cube && (freq || (img && !sliding)))) {
+  if ((!have_cube && (cube_needed || (img && !sliding)))) {
     const int nchunk = (c.W + kLanes - 1) / kLanes;
     const int pieces = (kLanes + tile - 1) / tile + 1;
     if ((rc = ensure(ctx, ctx->tile_part, (size_t)np * Ty * nchunk * pieces * 3 * 8)) != FITRIG_OK) return rc;
@@ -784,13 +792,31 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
 
   if ((rc = mark(3)) != FITRIG_OK) return rc;
   // ---- frequency branch ----------------------------------------------------
+  const double* series = (const double*)ctx->cube.p;
+  if (ring) {
+    // the covered series: the newest slices of the history, then the newest
+    // of this call's (oldest first); written back as the field's history
+    const int64_t ntiles = (int64_t)Ty * Tx;
+    const size_t sl = (size_t)ntiles * 8;
+    const int from_call = std::min(np, nfreq);
+    const int from_hist = nfreq - from_call;
+    if ((rc = ensure(ctx, ctx->fseries, (size_t)nfreq * sl)) != FITRIG_OK) return rc;
+    char* fs = (char*)ctx->fseries.p;
+    if (from_hist > 0)
+      HIP_TRY(ctx, hipMemcpyAsync(fs, (const char*)c.hist->in + (size_t)(c.hist->n_in - from_hist) * sl,
+                                  (size_t)from_hist * sl, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(fs + (size_t)from_hist * sl, (const char*)ctx->cube.p + (size_t)(np - from_call) * sl,
+                                (size_t)from_call * sl, hipMemcpyDeviceToDevice, st));
+    if (c.hist->out)
+      HIP_TRY(ctx, hipMemcpyAsync(c.hist->out, fs, (size_t)nfreq * sl, hipMemcpyDeviceToDevice, st));
+    series = (const double*)fs;
+  }
   if (freq) {
     const int64_t ntiles = (int64_t)Ty * Tx;
     if ((rc = ensure(ctx, ctx->eta_d, ntiles * 8)) != FITRIG_OK) return rc;
     if ((rc = ensure(ctx, ctx->eta_f, ntiles * 4)) != FITRIG_OK) return rc;
-    hipLaunchKernelGGL(k_eta, dim3(grid_for(ntiles, 256, 4096)), dim3(256), (size_t)2 * np * 8, st,
-                       (const double*)ctx->cube.p, np, ntiles, cfg.harm, (double*)ctx->eta_d.p,
-                       (float*)ctx->eta_f.p);
+    hipLaunchKernelGGL(k_eta, dim3(grid_for(ntiles, 256, 4096)), dim3(256), (size_t)2 * nfreq * 8, st, series, nfreq,
+                       ntiles, cfg.harm, (double*)ctx->eta_d.p, (float*)ctx->eta_f.p);
     LAUNCH_CHECK(ctx);
     if (!robust) {
       if ((rc = moments(ctx, st, (const double*)ctx->eta_d.p, 1, ntiles, 1, ntiles, eta_mu, eta_sig, eta_flag)) !=
@@ -985,7 +1011,7 @@ fitrig_status fitrig_destroy(fitrig_ctx* ctx) {
   if (!ctx) return FITRIG_E_INVAL;
   (void)hipSetDevice(ctx->cfg.device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&ctx->mom_tmp, &ctx->max_key, &ctx->seg_max2, &ctx->stat_part, &ctx->seg_max,  &ctx->tile_part, &ctx->cube,    &ctx->cube_f,
+  DevBuf* bufs[] = {&ctx->fseries, &ctx->mom_tmp, &ctx->max_key, &ctx->seg_max2, &ctx->stat_part, &ctx->seg_max,  &ctx->tile_part, &ctx->cube,    &ctx->cube_f,
                     &ctx->eta_d,     &ctx->eta_f,    &ctx->mu,        &ctx->sigma,    &ctx->flags,   &ctx->eta_st,
                     &ctx->M,         &ctx->qscratch, &ctx->hist,      &ctx->rs_state, &ctx->rs_med,  &ctx->rs_dev,
                     &ctx->chunk_cnt, &ctx->counters, &ctx->seg_entry, &ctx->seg_mask, &ctx->cell_q,  &ctx->parent,
@@ -1026,6 +1052,7 @@ fitrig_status fitrig_detect(fitrig_ctx* ctx, const void* stack, fitrig_dtype dty
   c.index_map = index_map;
   c.eta_map = eta_map;
   c.st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+  c.hist = nullptr;
   return detect_impl(ctx, c, cand, cand_cap, n_cand, stats);
 }
 
@@ -1038,8 +1065,11 @@ namespace fitrig {
 fitrig_status detect_frames(fitrig_ctx* ctx, const void* carry0, const void* carry1, int ncarry, const void* stack,
                             fitrig_dtype dtype, int32_t n_new, int32_t H, int32_t W, double sigma,
                             fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand, fitrig_stats* stats,
-                            void* hip_stream) {
+                            void* hip_stream, const FreqHist* hist) {
   if (!ctx || !stack || !n_cand || ncarry < 0 || ncarry > 2) return FITRIG_E_INVAL;
+  if (hist && (hist->n_in < 0 || hist->cap < 0 || hist->cap > 2048 || hist->n_in > hist->cap ||
+               (hist->n_in > 0 && !hist->in)))
+    return FITRIG_E_INVAL;
   if ((ncarry >= 1 && !carry0) || (ncarry == 2 && !carry1)) return FITRIG_E_INVAL;
   if (dtype != FITRIG_F32 && dtype != FITRIG_F16 && dtype != FITRIG_BF16) return FITRIG_E_INVAL;
   if (n_new < 1 || ncarry + n_new < 3 || H < 1 || W < 1) return FITRIG_E_INVAL;
@@ -1061,6 +1091,7 @@ fitrig_status detect_frames(fitrig_ctx* ctx, const void* carry0, const void* car
   c.index_map = nullptr;
   c.eta_map = nullptr;
   c.st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+  c.hist = hist;
   return detect_impl(ctx, c, cand, cand_cap, n_cand, stats);
 }
 

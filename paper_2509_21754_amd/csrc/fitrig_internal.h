@@ -129,11 +129,23 @@ struct SelBuffers {
 #include "fitrig.h"
 
 namespace fitrig {
+// Tile-cube history of a field for the frequency branch (serving): the
+// branch covers the last `cap` triples of [history | this call's triples].
+//   in:  device, FP64 [n_in][Ty][Tx], oldest first (nullable when n_in = 0)
+//   out: device, receives the covered slices, [min(cap, n_in + n')][Ty][Tx]
+//        (may be the same memory as `in`)
+struct FreqHist {
+  const double* in;
+  int n_in;
+  int cap;
+  double* out;
+};
+
 // Host-side entry points shared between translation units of the library.
 fitrig_status detect_frames(fitrig_ctx* ctx, const void* carry0, const void* carry1, int ncarry, const void* stack,
                             fitrig_dtype dtype, int32_t n_new, int32_t H, int32_t W, double sigma,
                             fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand, fitrig_stats* stats,
-                            void* hip_stream);
+                            void* hip_stream, const FreqHist* hist);
 hipStream_t ctx_stream(fitrig_ctx* ctx);
 int32_t& ctx_last_hip(fitrig_ctx* ctx);
 int64_t scratch_estimate(const fitrig_config& cfg, int n, int H, int W);

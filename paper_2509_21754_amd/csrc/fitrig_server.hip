@@ -1,9 +1,11 @@
 // FITrig serving form: a trigger loop over fields (sky position + image size).
 //
-// Per field the server keeps the last two snapshots (device) and the running
-// maximum M, so every request continues the field's sequence of triples and
-// its M estimate from past snapshots (the paper's real-time rule for M,
-// Sec. 2.2.4). Requests are admitted while the memory budget allows
+// Per field the server keeps the last two snapshots (device), the running
+// maximum M and, when freq_window > 0, the tile cube (q~ per tile, which does
+// not depend on M) of the field's last freq_window triples, so every request
+// continues the field's sequence of triples, its M estimate from past
+// snapshots (the paper's real-time rule for M, Sec. 2.2.4) and the time
+// series the frequency branch transforms (Sec. 2.3). Requests are admitted while the memory budget allows
 // (estimated slot scratch of the running and queued requests plus the
 // resident field state); admitted requests wait for one of n_slots worker
 // slots, each with its own context and HIP stream, so requests of different
@@ -49,6 +51,7 @@ struct Req {
   int64_t n_cand = 0;
   int n_triples = 0;
   int64_t first_triple = 0;
+  int freq_triples = 0;
   double M = 0.0;
 };
 
@@ -57,6 +60,9 @@ struct Field {
   fitrig_dtype dtype = FITRIG_F32;
   char* carry = nullptr;     // two frames on the device
   size_t frame_bytes = 0;
+  double* ring = nullptr;    // tile-cube slices of the latest triples, oldest first
+  size_t ring_bytes = 0;     // capacity: freq_window slices
+  int nring = 0;             // slices held
   int ncarry = 0;            // frames held (0..2) once every submitted request has run
   int64_t frames_seen = 0;   // frames of finished requests
   int64_t frames_submitted = 0;
@@ -87,6 +93,16 @@ struct fitrig_server {
 
 namespace {
 
+// Device bytes of a field's resident state.
+size_t field_bytes(const Field& f) { return 2 * f.frame_bytes + f.ring_bytes; }
+
+void free_field(Field& f) {
+  if (f.carry) (void)hipFree(f.carry);
+  if (f.ring) (void)hipFree(f.ring);
+  f.carry = nullptr;
+  f.ring = nullptr;
+}
+
 void worker_main(fitrig_server* S, int slot) {
   fitrig_ctx* ctx = S->ctxs[slot];
   std::vector<fitrig_candidate> buf((size_t)std::max<int64_t>(S->cfg.cand_cap, 1));
@@ -95,6 +111,7 @@ void worker_main(fitrig_server* S, int slot) {
     const void *c0 = nullptr, *c1 = nullptr;
     int nc = 0;
     int64_t first = 0;
+    fitrig::FreqHist fh{nullptr, 0, 0, nullptr};
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_ready.wait(lk, [&] { return S->stop || !S->ready.empty(); });
@@ -107,13 +124,14 @@ void worker_main(fitrig_server* S, int slot) {
       if (nc >= 1) c0 = f.carry + (2 - nc) * f.frame_bytes;
       if (nc == 2) c1 = f.carry + f.frame_bytes;
       first = f.frames_seen - nc;
+      if (f.ring) fh = fitrig::FreqHist{f.ring, f.nring, S->cfg.freq_window, f.ring};
     }
     r->t_start = now_ns();
     fitrig_stats st;
     memset(&st, 0, sizeof(st));
     int64_t ncand = 0;
     fitrig_status rc = fitrig::detect_frames(ctx, c0, c1, nc, r->stack, r->dtype, r->n, r->H, r->W, r->tau,
-                                             buf.data(), S->cfg.cand_cap, &ncand, &st, nullptr);
+                                             buf.data(), S->cfg.cand_cap, &ncand, &st, nullptr, fh.cap ? &fh : nullptr);
     // the field keeps the last two frames of [carried | new]
     Field* fp;
     {
@@ -149,6 +167,15 @@ void worker_main(fitrig_server* S, int slot) {
       r->n_cand = ncand;
       r->n_triples = nc + r->n - 2 > 0 ? nc + r->n - 2 : 0;
       r->first_triple = first;
+      if (f.ring) {
+        // the history holds what the run wrote; after a failed run it is dropped
+        const bool ok = rc == FITRIG_OK || rc == FITRIG_E_TRUNC;
+        f.nring = ok ? (int)std::min<int64_t>(S->cfg.freq_window, (int64_t)f.nring + r->n_triples) : 0;
+        r->freq_triples = (ok && (S->cfg.base.branches & FITRIG_FREQ) && f.nring >= 4) ? f.nring : 0;
+      } else {
+        r->freq_triples =
+            ((S->cfg.base.branches & FITRIG_FREQ) && r->n_triples >= 4 && r->n_triples <= 2048) ? r->n_triples : 0;
+      }
       f.M = fmax(f.M, st.M);
       r->M = f.M;
       f.frames_seen += r->n;
@@ -180,12 +207,14 @@ void fitrig_server_config_default(fitrig_server_config* cfg) {
   cfg->max_fields = 64;
   cfg->mem_budget = 0;
   cfg->cand_cap = 65536;
+  cfg->freq_window = 0;
 }
 
 fitrig_status fitrig_server_create(const fitrig_server_config* cfg, fitrig_server** out) {
   if (!cfg || !out) return FITRIG_E_INVAL;
   *out = nullptr;
-  if (cfg->n_slots < 1 || cfg->n_slots > 64 || cfg->max_fields < 1 || cfg->cand_cap < 0 || cfg->mem_budget < 0)
+  if (cfg->n_slots < 1 || cfg->n_slots > 64 || cfg->max_fields < 1 || cfg->cand_cap < 0 || cfg->mem_budget < 0 ||
+      cfg->freq_window < 0 || cfg->freq_window > 2048 || cfg->base.tile < 1)
     return FITRIG_E_INVAL;
   fitrig_server* S = new (std::nothrow) fitrig_server();
   if (!S) return FITRIG_E_NOMEM;
@@ -214,6 +243,9 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
   if (!(sigma > 0.0) || !isfinite(sigma)) return FITRIG_E_INVAL;
   const int64_t t_submit = now_ns();
   const size_t fb = (size_t)H * W * dtype_bytes(dtype);
+  const int tile = S->cfg.base.tile;
+  const bool keep_ring = S->cfg.freq_window > 0 && (S->cfg.base.branches & FITRIG_FREQ) != 0;
+  const size_t rb = keep_ring ? (size_t)S->cfg.freq_window * ((H + tile - 1) / tile) * ((W + tile - 1) / tile) * 8 : 0;
   const int64_t budget = S->cfg.mem_budget;
   std::unique_lock<std::mutex> lk(S->mu);
   // the field's state and the charge are re-read after every wait, so
@@ -228,7 +260,7 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
     if (resize && (f0->busy || !f0->pending.empty())) return FITRIG_E_INVAL;
     const int64_t carried = (f0 && !resize) ? std::min<int64_t>(2, f0->frames_submitted) : 0;
     if (carried + n_snap < 3) return FITRIG_E_INVAL;
-    field_mem = (fresh || resize) ? (int64_t)(2 * fb) : 0;
+    field_mem = (fresh || resize) ? (int64_t)(2 * fb + rb) : 0;
     mem = fitrig::scratch_estimate(S->cfg.base, (int)(carried + n_snap), H, W);
     if (budget > 0 && field_mem + mem + S->mem_fields > budget) return FITRIG_E_BUSY;
     if (budget == 0 || S->mem_charged + S->mem_fields + field_mem + mem <= budget) break;
@@ -243,28 +275,31 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
           (lru == S->fields.end() || jt->second.last_use < lru->second.last_use))
         lru = jt;
     if (lru == S->fields.end()) return FITRIG_E_BUSY;
-    if (lru->second.carry) (void)hipFree(lru->second.carry);
-    S->mem_fields -= (int64_t)(2 * lru->second.frame_bytes);
+    free_field(lru->second);
+    S->mem_fields -= (int64_t)field_bytes(lru->second);
     S->fields.erase(lru);
   }
   Field* f = fresh ? nullptr : &S->fields[field_id];
   // (re)create the field state
   if (fresh || resize) {
     Field& nf = S->fields[field_id];
-    if (nf.carry) {
-      (void)hipFree(nf.carry);
-      S->mem_fields -= (int64_t)(2 * nf.frame_bytes);
+    if (nf.carry || nf.ring) {
+      free_field(nf);
+      S->mem_fields -= (int64_t)field_bytes(nf);
     }
     nf = Field();
     nf.H = H;
     nf.W = W;
     nf.dtype = dtype;
     nf.frame_bytes = fb;
-    if (hipSetDevice(S->cfg.base.device) != hipSuccess || hipMalloc((void**)&nf.carry, 2 * fb) != hipSuccess) {
+    nf.ring_bytes = rb;
+    if (hipSetDevice(S->cfg.base.device) != hipSuccess || hipMalloc((void**)&nf.carry, 2 * fb) != hipSuccess ||
+        (rb && hipMalloc((void**)&nf.ring, rb) != hipSuccess)) {
+      free_field(nf);
       S->fields.erase(field_id);
       return FITRIG_E_NOMEM;
     }
-    S->mem_fields += (int64_t)(2 * fb);
+    S->mem_fields += (int64_t)field_bytes(nf);
     f = &nf;
   }
   Req* r = new (std::nothrow) Req();
@@ -313,6 +348,7 @@ fitrig_status fitrig_poll(fitrig_server* S, int64_t ticket, int32_t wait, fitrig
   out->n_cand = r->n_cand;
   out->cand = r->cand.empty() ? nullptr : r->cand.data();
   out->M = r->M;
+  out->freq_triples = r->freq_triples;
   out->t_submit_ns = r->t_submit;
   out->t_start_ns = r->t_start;
   out->t_done_ns = r->t_done;
@@ -340,8 +376,7 @@ fitrig_status fitrig_server_destroy(fitrig_server* S) {
   S->cv_ready.notify_all();
   for (std::thread& t : S->workers) t.join();
   for (fitrig_ctx* c : S->ctxs) fitrig_destroy(c);
-  for (auto& kv : S->fields)
-    if (kv.second.carry) (void)hipFree(kv.second.carry);
+  for (auto& kv : S->fields) free_field(kv.second);
   for (auto& kv : S->reqs) delete kv.second;
   delete S;
   return FITRIG_OK;

@@ -68,11 +68,11 @@ def test_status_strings_and_version():
 def test_defaults():
     c = F.fitrig_config_default()
     assert (c.abi_version, c.mode, c.window, c.tile, c.branches, c.sigma_est, c.harm, c.r_signed,
-            c.map_kind, c.C) == (1, F.SLIDING, 7, 32, F.IMAGE | F.FREQ, F.MEAN_STD, 0, 0, F.MAP_QTILDE, 1e-6)
+            c.map_kind, c.C) == (F.ABI_VERSION, F.SLIDING, 7, 32, F.IMAGE | F.FREQ, F.MEAN_STD, 0, 0, F.MAP_QTILDE, 1e-6)
 
 
 @pytest.mark.parametrize("bad", [
-    dict(abi_version=2), dict(mode=2), dict(window=4), dict(window=0), dict(window=19), dict(tile=0),
+    dict(abi_version=F.ABI_VERSION + 1), dict(abi_version=1), dict(mode=2), dict(window=4), dict(window=0), dict(window=19), dict(tile=0),
     dict(branches=0), dict(branches=4), dict(sigma_est=2), dict(harm=1), dict(harm=-1), dict(r_signed=2),
     dict(map_kind=3), dict(profile=2), dict(C=0.0), dict(C=-1.0), dict(C=float("nan")), dict(max_pixels=-1),
 ])
@@ -90,7 +90,8 @@ def test_detect_rejects_null_context():
 
 
 def test_server_rejects_bad_config_on_cpu():
-    for bad in (dict(n_slots=0), dict(max_fields=0), dict(cand_cap=-1), dict(mem_budget=-5), dict(window=2)):
+    for bad in (dict(n_slots=0), dict(max_fields=0), dict(cand_cap=-1), dict(mem_budget=-5), dict(window=2),
+                dict(freq_window=-1), dict(freq_window=2049)):
         rc, h = F.fitrig_server_create(F.fitrig_server_config_default(**bad))
         assert rc == F.E_INVAL and h is None
     t = ctypes.c_int64()
@@ -99,4 +100,4 @@ def test_server_rejects_bad_config_on_cpu():
     assert F.fitrig_release(None, 1) == F.E_INVAL
     assert F.fitrig_server_destroy(None) == F.E_INVAL
     c = F.fitrig_server_config_default()
-    assert (c.n_slots, c.max_fields, c.mem_budget, c.cand_cap, c.base.window) == (4, 64, 0, 65536, 7)
+    assert (c.n_slots, c.max_fields, c.mem_budget, c.cand_cap, c.freq_window, c.base.window) == (4, 64, 0, 65536, 0, 7)

@@ -128,3 +128,45 @@ def test_server_evicts_least_recently_used_idle_field():
         assert r1["first_triple"] == 4 and r1["n_triples"] == 1
         r0 = srv.poll(srv.submit(0, X, 5.0))       # field 0 starts over (evicts field 2)
         assert r0["first_triple"] == 0 and r0["n_triples"] == 3
+
+
+@pytest.mark.parametrize("branches,tile", [(2, 16), (3, 32)])
+def test_server_freq_window_covers_field_history(branches, tile):
+    """With freq_window > 0 a request's frequency branch transforms the field's
+    last freq_window triples (tile cube kept per field): its candidates equal
+    those of the frames covering that window run alone."""
+    from paper_2509_21754_amd import Server
+    from paper_2509_21754_amd.fitrig import _rec_dict
+
+    tau, win = 2.5, 6
+    cfg = dict(window=5, branches=branches, tile=tile)
+    H, W = 96, 200
+    frames = []
+    n_freq = 0
+    with Server(n_slots=2, freq_window=win, **cfg) as srv:
+        for i, n in enumerate([3, 2, 1, 4, 3, 1]):
+            X = structured_stack(300 + i, n, H, W)
+            t = torch.from_numpy(X).cuda()
+            torch.cuda.synchronize()
+            frames.extend(list(X))
+            tk = srv.submit(0, t, tau)
+            r = srv.poll(tk, as_dicts=False)
+            assert r["status"] == 0
+            T = len(frames) - 2
+            nf = min(T, win)
+            assert r["freq_triples"] == (nf if nf >= 4 else 0)
+            got = r["cands"]
+            gf = got[got["branch"] == ref.FREQ]
+            if nf < 4:
+                assert len(gf) == 0
+            else:
+                used = np.stack(frames[T - nf:T + 2])
+                alone, _, rc = _alone(torch.from_numpy(used).cuda(), tau, **cfg)
+                assert rc == 0
+                af = alone[alone["branch"] == ref.FREQ]
+                assert gf.tobytes() == af.tobytes(), i
+                n_freq += len(af)
+                out = ref.detect(used.astype(np.float64), tau=tau, window=5, branches=branches, tile=tile)
+                check_candidates([_rec_dict(x) for x in alone], out, tau)
+            srv.release(tk)
+    assert n_freq > 0
