@@ -257,7 +257,7 @@ fitrig_status rs_select_middle(fitrig_ctx* ctx, hipStream_t st, const float* val
   uint32_t* min_gt = (uint32_t*)(cnt_le + nsets);
   const int shifts[3] = {21, 10, 0};
   const int nbits[3] = {11, 11, 10};
-  const int gx = grid_for(n_max, 1 << 16, 1024);
+  const int gx = grid_for(n_max, 1 << 13, 1024);
   if (base)
     hipLaunchKernelGGL(k_rs_init_gathered, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, rank_lo, base);
   else
@@ -265,7 +265,7 @@ fitrig_status rs_select_middle(fitrig_ctx* ctx, hipStream_t st, const float* val
   for (int p = 0; p < 3; ++p) {
     hipLaunchKernelGGL(k_rs_hist, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, kmode, med, rs, shifts[p],
                        nbits[p], hist, nvalid);
-    hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(64), 0, st, rs, hist, shifts[p], nbits[p]);
+    hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(256), 0, st, rs, hist, shifts[p], nbits[p]);
   }
   hipLaunchKernelGGL(k_rs_store, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, vmode, 0, out);
   if (rank_hi != rank_lo) {
@@ -325,8 +325,13 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
       uint32_t* bkt = (uint32_t*)ctx->rs_bkt.p;
       unsigned long long* cnt = (unsigned long long*)ctx->rs_cnt.p;
       uint32_t* gbuf = (uint32_t*)ctx->rs_gbuf.p;
-      hipLaunchKernelGGL(k_rs_sample, dim3(grid_for(S, 256, 1024), nsets), dim3(256), 0, st, vals, per_set, mode,
-                         (const double*)mu, S, mult, samp);
+      // the dispersion sample is |q - med| at the median sample's positions
+      if (mode == 0)
+        hipLaunchKernelGGL(k_rs_sample, dim3(grid_for(S, 256, 1024), nsets), dim3(256), 0, st, vals, per_set, 0,
+                           (const double*)mu, S, mult, samp);
+      else
+        hipLaunchKernelGGL(k_rs_sample_dev, dim3(grid_for(S, 256, 1024), nsets), dim3(256), 0, st, samp, S,
+                           (const double*)mu);
       // bracket keys: sample order statistics a and b (keys, mode 2)
       for (int w = 0; w < 2; ++w) {
         RsState* rs = (RsState*)ctx->rs_state.p;
@@ -334,10 +339,10 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
         const int nbits[3] = {11, 11, 10};
         hipLaunchKernelGGL(k_rs_init_rank, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, w ? b : a);
         for (int p = 0; p < 3; ++p) {
-          hipLaunchKernelGGL(k_rs_hist, dim3(grid_for(S, 1 << 16, 1024), nsets), dim3(256), 0, st,
+          hipLaunchKernelGGL(k_rs_hist, dim3(grid_for(S, 1 << 13, 1024), nsets), dim3(256), 0, st,
                              (const float*)samp, S, 2, (const double*)mu, rs, shifts[p], nbits[p],
                              (uint32_t*)ctx->hist.p, (const unsigned long long*)nullptr);
-          hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(64), 0, st, rs, (uint32_t*)ctx->hist.p, shifts[p],
+          hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(256), 0, st, rs, (uint32_t*)ctx->hist.p, shifts[p],
                              nbits[p]);
         }
         hipLaunchKernelGGL(k_rs_key_out, dim3((nsets + 63) / 64), dim3(64), 0, st, (const RsState*)rs, nsets, w,

@@ -968,35 +968,75 @@ __global__ __launch_bounds__(256) void k_rs_hist(const float* vals, int64_t per_
   const float* v = vals + (int64_t)s * per_set;
   const double m = mode == 1 ? med[s] : 0.0;
   const int64_t n = nvalid ? min((int64_t)nvalid[s], per_set) : per_set;
+  const int lane = threadIdx.x & 63;
   for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const uint32_t key = rs_key(v[i], mode, m);
-    if ((key & S.known) == S.prefix) atomicAdd(&h[(key >> shift) & dmask], 1u);
+    if ((key & S.known) == S.prefix) {
+      // keys near a middle value share their leading digits: the lanes whose
+      // bin equals the first matching lane's add with one atomic
+      const uint32_t bin = (key >> shift) & dmask;
+      const uint32_t b0 = __builtin_amdgcn_readfirstlane(bin);
+      const uint64_t same = __ballot(bin == b0);
+      if (bin != b0)
+        atomicAdd(&h[bin], 1u);
+      else if (lane == __ffsll((unsigned long long)same) - 1)
+        atomicAdd(&h[b0], (uint32_t)__popcll(same));
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= (int)dmask; i += 256)
     if (h[i]) atomicAdd(&hist[(int64_t)s * kHistBins + i], h[i]);
 }
 
-__global__ void k_rs_pick(RsState* st, uint32_t* hist, int shift, int nbits) {
-  const int s = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  RsState S = st[s];
+// Digit of the rank-th key: the first bin whose running count exceeds the
+// rank (the last bin when none does); the histogram is cleared for the next
+// digit. One workgroup of 256 per set, nbits 10 or 11.
+__global__ __launch_bounds__(256) void k_rs_pick(RsState* st, uint32_t* hist, int shift, int nbits) {
+  __shared__ int64_t part[256];
+  const int s = blockIdx.x, t = threadIdx.x;
+  const RsState S = st[s];
   uint32_t* h = hist + (int64_t)s * kHistBins;
-  const int nb = 1 << nbits;
-  int64_t acc = 0;
-  int dig = nb - 1;
-  for (int i = 0; i < nb; ++i) {
-    if (acc + (int64_t)h[i] > S.rank) {
-      dig = i;
-      break;
-    }
-    acc += h[i];
+  const int nb = 1 << nbits, per = nb / 256;
+  uint32_t c[kHistBins / 256];
+  int64_t own = 0;
+#pragma unroll
+  for (int j = 0; j < kHistBins / 256; ++j) {
+    c[j] = j < per ? h[t * per + j] : 0u;
+    own += c[j];
   }
-  S.rank -= acc;
-  S.prefix |= ((uint32_t)dig) << shift;
-  S.known |= ((uint32_t)(nb - 1)) << shift;
-  st[s] = S;
-  for (int i = 0; i < nb; ++i) h[i] = 0;
+  part[t] = own;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t x = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += x;
+    __syncthreads();
+  }
+  const int64_t incl = part[t], excl = incl - own;
+  int dig = -1;
+  int64_t acc = excl;
+  if (excl <= S.rank && S.rank < incl) {
+#pragma unroll
+    for (int j = 0; j < kHistBins / 256; ++j) {
+      if (dig < 0 && j < per) {
+        if (acc + (int64_t)c[j] > S.rank)
+          dig = t * per + j;
+        else
+          acc += c[j];
+      }
+    }
+  } else if (t == 255 && S.rank >= incl) {
+    dig = nb - 1;  // rank beyond the count
+    acc = incl;
+  }
+  if (dig >= 0) {
+    RsState o = S;
+    o.rank -= acc;
+    o.prefix |= ((uint32_t)dig) << shift;
+    o.known |= ((uint32_t)(nb - 1)) << shift;
+    st[s] = o;
+  }
+  for (int j = 0; j < per; ++j) h[t * per + j] = 0u;
 }
 
 // Every set searches the same rank.
@@ -1061,15 +1101,16 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 // workgroup scan places the keys inside the bracket in an LDS stage, which is
 // appended to the set's output with one global atomic per flush (atomics on
 // one address per round would serialise the whole pass).
-constexpr int kGatherStage = 8192;
+constexpr int kGatherStage = 4096;  // one round of keys
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_rs_gather(const float* vals, int64_t per_set, int mode, const double* med,
                                                    const uint32_t* bkt, int64_t cap, unsigned long long* cnt,
                                                    uint32_t* gbuf) {
+  constexpr int64_t kRound = 256 * 16;
+  static_assert(kGatherStage >= kRound, "a stage holds one round");
   __shared__ uint32_t stage[kGatherStage];
   __shared__ uint32_t wsum[4];
   __shared__ unsigned long long gbase;
-  __shared__ uint32_t sh[256];
   const int s = blockIdx.y;
   const uint32_t lo = bkt[2 * s], hi = bkt[2 * s + 1];
   const float* v = vals + (int64_t)s * per_set;
@@ -1077,31 +1118,54 @@ __global__ __launch_bounds__(256) void k_rs_gather(const float* vals, int64_t pe
   const double m = mode == 1 ? med[s] : 0.0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t below = 0, nst = 0;
-  constexpr int64_t kRound = 256 * 16;
   const int64_t step = (int64_t)gridDim.x * kRound;
-  // every thread of the workgroup runs the same rounds (barriers inside)
-  for (int64_t base = blockIdx.x * kRound; base < per_set; base += step) {
-    uint32_t k[16];
-    bool ok[16];
+  // appends the staged keys to the set's output (every thread calls it)
+  auto flush = [&]() {
+    if (threadIdx.x == 0) gbase = atomicAdd(cnt + 2 * s + 1, (unsigned long long)nst);
+    __syncthreads();
+    const unsigned long long g0 = gbase;
+    for (uint32_t j = threadIdx.x; j < nst; j += 256)
+      if ((int64_t)(g0 + j) < cap) out[g0 + j] = stage[j];
+    nst = 0;
+    __syncthreads();  // stage and gbase read before they are reused
+  };
+  // the values of a round: 16 per thread (four 16-byte loads when VEC)
+  auto fetch = [&](int64_t base, float (&q)[16]) {
     if (VEC) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int64_t i = base + 4 * ((int64_t)j * 256 + threadIdx.x);  // per_set % 4 == 0
-        const bool in_set = i < per_set;
-        const float4 q = in_set ? *reinterpret_cast<const float4*>(v + i) : make_float4(0.f, 0.f, 0.f, 0.f);
-        k[4 * j + 0] = rs_key(q.x, mode, m);
-        k[4 * j + 1] = rs_key(q.y, mode, m);
-        k[4 * j + 2] = rs_key(q.z, mode, m);
-        k[4 * j + 3] = rs_key(q.w, mode, m);
-        ok[4 * j + 0] = ok[4 * j + 1] = ok[4 * j + 2] = ok[4 * j + 3] = in_set;
+        const float4 x = i < per_set ? *reinterpret_cast<const float4*>(v + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+        q[4 * j + 0] = x.x;
+        q[4 * j + 1] = x.y;
+        q[4 * j + 2] = x.z;
+        q[4 * j + 3] = x.w;
       }
     } else {
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int64_t i = base + (int64_t)j * 256 + threadIdx.x;
-        ok[j] = i < per_set;
-        k[j] = ok[j] ? rs_key(v[i], mode, m) : 0u;
+        q[j] = i < per_set ? v[i] : 0.0f;
       }
+    }
+  };
+  auto index_of = [&](int64_t base, int j) -> int64_t {
+    return VEC ? base + 4 * ((int64_t)(j >> 2) * 256 + threadIdx.x) + (j & 3) : base + (int64_t)j * 256 + threadIdx.x;
+  };
+  float q[16];
+  int64_t base = blockIdx.x * kRound;
+  if (base < per_set) fetch(base, q);
+  // every thread of the workgroup runs the same rounds (barriers inside)
+  for (; base < per_set; base += step) {
+    // the next round's loads are in flight while this round is placed
+    float nq[16];
+    if (base + step < per_set) fetch(base + step, nq);
+    uint32_t k[16];
+    bool ok[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      ok[j] = index_of(base, j) < per_set;
+      k[j] = rs_key(q[j], mode, m);
     }
     uint32_t c = 0;
 #pragma unroll
@@ -1115,32 +1179,37 @@ __global__ __launch_bounds__(256) void k_rs_gather(const float* vals, int64_t pe
     const uint32_t w0 = wsum[0], w1 = wsum[1], w2 = wsum[2], w3 = wsum[3];
     const uint32_t tot = w0 + w1 + w2 + w3;
     const uint32_t woff = (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
+    if (nst + tot > (uint32_t)kGatherStage) flush();  // uniform: nst and tot are
     if (c) {
-      uint32_t p = nst + woff + inc - c;  // nst <= kGatherStage - kRound, p < kGatherStage
+      uint32_t p = nst + woff + inc - c;  // nst + tot <= kGatherStage
 #pragma unroll
       for (int j = 0; j < 16; ++j)
         if (ok[j] && k[j] >= lo && k[j] <= hi) stage[p++] = k[j];
     }
     nst += tot;
-    const bool flush = nst > kGatherStage - kRound || base + step >= per_set;
     __syncthreads();  // stage written and wsum read by every thread
-    if (flush) {
-      if (threadIdx.x == 0) gbase = nst ? atomicAdd(cnt + 2 * s + 1, (unsigned long long)nst) : 0ull;
-      __syncthreads();
-      const unsigned long long g0 = gbase;
-      for (uint32_t j = threadIdx.x; j < nst; j += 256)
-        if ((int64_t)(g0 + j) < cap) out[g0 + j] = stage[j];
-      nst = 0;
-      __syncthreads();
-    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) q[j] = nq[j];
   }
-  sh[threadIdx.x] = below;
+  if (nst) flush();
+  // keys below the bracket: wave sums, then one atomic per workgroup
+  uint32_t b = below;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) b += __shfl_xor(b, off);
+  if (lane == 0) wsum[wave] = b;
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
+  if (threadIdx.x == 0)
+    atomicAdd(cnt + 2 * s, (unsigned long long)wsum[0] + wsum[1] + wsum[2] + wsum[3]);
+}
+
+// Dispersion keys of a sample of order keys: |q - med| of the sampled q.
+__global__ void k_rs_sample_dev(uint32_t* samp, int64_t S, const double* med) {
+  const int s = blockIdx.y;
+  const double m = med[s];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t* p = samp + (int64_t)s * S + i;
+    *p = rs_key(ord_val(*p), 1, m);
   }
-  if (threadIdx.x == 0) atomicAdd(cnt + 2 * s, (unsigned long long)sh[0]);
 }
 
 __global__ void k_rs_init(RsState* st, int nsets, int64_t per_set, int which) {
