@@ -54,7 +54,7 @@ struct fitrig_ctx {
   DevBuf stat_part, seg_max, seg_max2, tile_part, cube, cube_f, eta_d, eta_f, mu, sigma, flags, eta_st, M, qscratch;
   DevBuf fseries;  // frequency series over [history | call] (serving)
   DevBuf hist, rs_state, rs_med, rs_dev, rs_next, chunk_cnt, counters, mom_tmp, max_key;
-  DevBuf rs_samp, rs_gbuf, rs_bkt, rs_cnt, rs_nvalid;
+  DevBuf rs_samp, rs_gbuf, rs_bkt, rs_cnt, rs_nvalid, rs_plan;
   DevBuf seg_entry, seg_mask, cell_q, parent, comp_of, c_root, c_npix, c_key, c_w, c_box, c_out;
   DevBuf bflag, blk_entry, blk_slot, band_start, band_end, rowslot;
   int64_t seg_cap = 0, comp_cap = 0;
@@ -282,8 +282,36 @@ fitrig_status rs_select_middle(fitrig_ctx* ctx, hipStream_t st, const float* val
   return FITRIG_OK;
 }
 
+// Sample order statistics a and b of each set's sample (keys) -> bkt[2 s],
+// bkt[2 s + 1].
+void sample_bracket(fitrig_ctx* ctx, hipStream_t st, const uint32_t* samp, int nsets, int64_t S, int64_t a, int64_t b,
+                    uint32_t* bkt) {
+  RsState* rs = (RsState*)ctx->rs_state.p;
+  const int shifts[3] = {21, 10, 0};
+  const int nbits[3] = {11, 11, 10};
+  for (int w = 0; w < 2; ++w) {
+    hipLaunchKernelGGL(k_rs_init_rank, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, w ? b : a);
+    for (int p = 0; p < 3; ++p) {
+      hipLaunchKernelGGL(k_rs_hist, dim3(grid_for(S, 1 << 13, 1024), nsets), dim3(256), 0, st, (const float*)samp, S,
+                         2, (const double*)nullptr, rs, shifts[p], nbits[p], (uint32_t*)ctx->hist.p,
+                         (const unsigned long long*)nullptr);
+      hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(256), 0, st, rs, (uint32_t*)ctx->hist.p, shifts[p], nbits[p]);
+    }
+    hipLaunchKernelGGL(k_rs_key_out, dim3((nsets + 63) / 64), dim3(64), 0, st, (const RsState*)rs, nsets, w, bkt);
+  }
+}
+
+// Robust spread per set (Sec. 2.3, median and MAD): mu = median of the
+// values, sigma = 1.482602218505602 * median |q - mu| (two middle order
+// statistics averaged for an even count), by exact radix selection.
+// Large sets select inside brackets taken from a hashed sample: one pass
+// over the values gathers the cells of both the median bracket and a MAD
+// window placed around the sample median (k_rs_gather2); every bracket is
+// checked by its counts (or, for the MAD window, against the exact median)
+// and a failed one falls back to a per-statistic pass or to full selection.
+// nonneg: every value is +0 or positive (q with |x_hat| in Eq. (4), eta).
 fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, int nsets, int64_t per_set,
-                            double* mu, double* sigma, uint32_t* flags) {
+                            bool nonneg, double* mu, double* sigma, uint32_t* flags) {
   fitrig_status rc;
   if ((rc = ensure(ctx, ctx->hist, (size_t)nsets * kHistBins * 4)) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->rs_state, (size_t)nsets * sizeof(RsState))) != FITRIG_OK) return rc;
@@ -293,97 +321,159 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((int64_t)nsets * kHistBins)), dim3(256), 0, st, (uint32_t*)ctx->hist.p,
                      (int64_t)nsets * kHistBins, 0u);
   const int64_t r_lo = (per_set - 1) / 2, r_hi = per_set / 2;
+  double* med_out = (double*)ctx->rs_med.p;
+  double* dev_out = (double*)ctx->rs_dev.p;
+  auto finish = [&](int mode) {
+    hipLaunchKernelGGL(k_rs_finish, dim3((nsets + 63) / 64), dim3(64), 0, st, (const double*)med_out,
+                       (const double*)dev_out, nsets, mu, sigma, flags, mode);
+  };
   constexpr int64_t kSample = 1 << 20;
-  const bool bracket = per_set >= 8 * kSample;
-  int64_t S = 0, a = 0, b = 0, cap = 0;
-  uint64_t mult = 0;
-  const bool vec = per_set % 4 == 0 && ((uintptr_t)vals & 15) == 0;
-  if (bracket) {
-    S = kSample;
-    // an odd multiplier near per_set * (golden ratio - 1), made coprime to per_set
-    mult = (uint64_t)((double)per_set * 0.6180339887498949) | 1u;
-    while (std::gcd(mult, (uint64_t)per_set) != 1) mult += 2;
-    // sample ranks of the two middle values, widened by 8 standard deviations
-    // of a binomial(S, 1/2) rank (4096 for S = 2^20)
-    const int64_t d = 4 * (int64_t)std::ceil(std::sqrt((double)S));
-    a = std::max<int64_t>(0, (r_lo * S) / per_set - d);
-    b = std::min<int64_t>(S - 1, (r_hi * S) / per_set + d + 1);
-    // expected gathered count (b - a) * per_set / S, room for four times it
-    cap = std::min<int64_t>(per_set, 4 * ((b - a + 1) * (per_set / S + 1)));
-    if ((rc = ensure(ctx, ctx->rs_samp, (size_t)nsets * S * 4)) != FITRIG_OK ||
-        (rc = ensure(ctx, ctx->rs_gbuf, (size_t)nsets * cap * 4)) != FITRIG_OK ||
-        (rc = ensure(ctx, ctx->rs_bkt, (size_t)nsets * 2 * 4)) != FITRIG_OK ||
-        (rc = ensure(ctx, ctx->rs_cnt, (size_t)nsets * 2 * 8)) != FITRIG_OK ||
-        (rc = ensure_host(ctx, (size_t)nsets * 2 * 8)) != FITRIG_OK)
-      return rc;
-  }
-  for (int mode = 0; mode < 2; ++mode) {
-    double* out = (double*)(mode ? ctx->rs_dev.p : ctx->rs_med.p);
-    bool done = false;
-    if (bracket) {
-      uint32_t* samp = (uint32_t*)ctx->rs_samp.p;
-      uint32_t* bkt = (uint32_t*)ctx->rs_bkt.p;
-      unsigned long long* cnt = (unsigned long long*)ctx->rs_cnt.p;
-      uint32_t* gbuf = (uint32_t*)ctx->rs_gbuf.p;
-      // the dispersion sample is |q - med| at the median sample's positions
-      if (mode == 0)
-        hipLaunchKernelGGL(k_rs_sample, dim3(grid_for(S, 256, 1024), nsets), dim3(256), 0, st, vals, per_set, 0,
-                           (const double*)mu, S, mult, samp);
-      else
-        hipLaunchKernelGGL(k_rs_sample_dev, dim3(grid_for(S, 256, 1024), nsets), dim3(256), 0, st, samp, S,
-                           (const double*)mu);
-      // bracket keys: sample order statistics a and b (keys, mode 2)
-      for (int w = 0; w < 2; ++w) {
-        RsState* rs = (RsState*)ctx->rs_state.p;
-        const int shifts[3] = {21, 10, 0};
-        const int nbits[3] = {11, 11, 10};
-        hipLaunchKernelGGL(k_rs_init_rank, dim3((nsets + 63) / 64), dim3(64), 0, st, rs, nsets, w ? b : a);
-        for (int p = 0; p < 3; ++p) {
-          hipLaunchKernelGGL(k_rs_hist, dim3(grid_for(S, 1 << 13, 1024), nsets), dim3(256), 0, st,
-                             (const float*)samp, S, 2, (const double*)mu, rs, shifts[p], nbits[p],
-                             (uint32_t*)ctx->hist.p, (const unsigned long long*)nullptr);
-          hipLaunchKernelGGL(k_rs_pick, dim3(nsets), dim3(256), 0, st, rs, (uint32_t*)ctx->hist.p, shifts[p],
-                             nbits[p]);
-        }
-        hipLaunchKernelGGL(k_rs_key_out, dim3((nsets + 63) / 64), dim3(64), 0, st, (const RsState*)rs, nsets, w,
-                           bkt);
-      }
-      hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, (int64_t*)cnt, (int64_t)(2 * nsets), (int64_t)0);
-      if (vec)
-        hipLaunchKernelGGL(k_rs_gather<true>, dim3(grid_for(per_set, 256 * 16, 512), nsets), dim3(256), 0, st, vals,
-                           per_set, mode, (const double*)mu, (const uint32_t*)bkt, cap, cnt, gbuf);
-      else
-        hipLaunchKernelGGL(k_rs_gather<false>, dim3(grid_for(per_set, 256 * 16, 512), nsets), dim3(256), 0, st,
-                           vals, per_set, mode, (const double*)mu, (const uint32_t*)bkt, cap, cnt, gbuf);
-      LAUNCH_CHECK(ctx);
-      unsigned long long* h = (unsigned long long*)ctx->h_stage;
-      HIP_TRY(ctx, hipMemcpyAsync(h, cnt, (size_t)nsets * 16, hipMemcpyDeviceToHost, st));
-      HIP_TRY(ctx, hipStreamSynchronize(st));
-      bool ok = true;
-      int64_t in_max = 1;
-      for (int s = 0; s < nsets && ok; ++s) {
-        const int64_t below = (int64_t)h[2 * s], in = (int64_t)h[2 * s + 1];
-        ok = in <= cap && below <= r_lo && r_hi < below + in;
-        in_max = std::max(in_max, in);
-      }
-      if (ok) {
-        // counts of gathered keys per set sit at cnt[2 s + 1]; rank offsets at cnt[2 s]
-        if ((rc = ensure(ctx, ctx->rs_nvalid, (size_t)nsets * 8)) != FITRIG_OK) return rc;
-        unsigned long long* nv = (unsigned long long*)ctx->rs_nvalid.p;
-        hipLaunchKernelGGL(k_copy_stride2_u64, dim3(1), dim3(64), 0, st, (const unsigned long long*)cnt + 1, nv,
-                           (int64_t)nsets);
-        if ((rc = rs_select_middle(ctx, st, (const float*)gbuf, nsets, cap, 2, mode, mu, nv, cnt, r_lo, r_hi,
-                                   in_max, out)) != FITRIG_OK)
-          return rc;
-        done = true;
-      }
+  if (per_set < 8 * kSample) {
+    for (int mode = 0; mode < 2; ++mode) {
+      if ((rc = rs_select_middle(ctx, st, vals, nsets, per_set, mode, mode, mu, nullptr, nullptr, r_lo, r_hi, per_set,
+                                 mode ? dev_out : med_out)) != FITRIG_OK)
+        return rc;
+      finish(mode);
     }
-    if (!done && (rc = rs_select_middle(ctx, st, vals, nsets, per_set, mode, mode, mu, nullptr, nullptr, r_lo, r_hi,
-                                        per_set, out)) != FITRIG_OK)
-      return rc;
-    hipLaunchKernelGGL(k_rs_finish, dim3((nsets + 63) / 64), dim3(64), 0, st, (const double*)ctx->rs_med.p,
-                       (const double*)ctx->rs_dev.p, nsets, mu, sigma, flags, mode);
+    LAUNCH_CHECK(ctx);
+    return FITRIG_OK;
   }
+
+  const int64_t S = kSample;
+  // sample i is value (i * mult) mod per_set: an odd multiplier near
+  // per_set * (golden ratio - 1), made coprime to per_set
+  uint64_t mult = (uint64_t)((double)per_set * 0.6180339887498949) | 1u;
+  while (std::gcd(mult, (uint64_t)per_set) != 1) mult += 2;
+  // sample ranks of the two middle values, widened by 8 standard deviations
+  // of a binomial(S, 1/2) rank (4096 for S = 2^20)
+  const int64_t d = 4 * (int64_t)std::ceil(std::sqrt((double)S));
+  const int64_t a = std::max<int64_t>(0, (r_lo * S) / per_set - d);
+  const int64_t b = std::min<int64_t>(S - 1, (r_hi * S) / per_set + d + 1);
+  // expected median-bracket count (b - a) * per_set / S: room for four times
+  // it; the MAD window is wider by the median's uncertainty: eight times
+  const int64_t expect = (b - a + 1) * (per_set / S + 1);
+  const int64_t cap0 = std::min<int64_t>(per_set, 4 * expect);
+  const int64_t cap1 = std::min<int64_t>(per_set, 8 * expect);
+  const bool vec = per_set % 4 == 0 && ((uintptr_t)vals & 15) == 0;
+  if ((rc = ensure(ctx, ctx->rs_samp, (size_t)nsets * S * 4)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->rs_gbuf, (size_t)nsets * (cap0 + cap1) * 4)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->rs_bkt, (size_t)nsets * 8 * 4)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->rs_cnt, (size_t)nsets * (4 * 8 + 4))) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->rs_nvalid, (size_t)nsets * 2 * 8)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->rs_plan, (size_t)nsets * 5 * 8)) != FITRIG_OK ||
+      (rc = ensure_host(ctx, (size_t)nsets * 4 * 8)) != FITRIG_OK)
+    return rc;
+  uint32_t* samp = (uint32_t*)ctx->rs_samp.p;
+  uint32_t* bkt0 = (uint32_t*)ctx->rs_bkt.p;
+  uint32_t* bkt1 = bkt0 + 2 * nsets;
+  uint32_t* wk = bkt0 + 4 * nsets;
+  unsigned long long* cnt0 = (unsigned long long*)ctx->rs_cnt.p;
+  unsigned long long* cnt1 = cnt0 + 2 * nsets;
+  unsigned long long* nv0 = (unsigned long long*)ctx->rs_nvalid.p;
+  unsigned long long* nv1 = nv0 + nsets;
+  uint32_t* g0 = (uint32_t*)ctx->rs_gbuf.p;
+  uint32_t* g1 = g0 + (size_t)nsets * cap0;
+  double* pl = (double*)ctx->rs_plan.p;
+  double* mhat = pl + 4 * nsets;
+  const dim3 gs(grid_for(S, 256, 1024), nsets), g1d((nsets + 63) / 64);
+  unsigned long long* h = (unsigned long long*)ctx->h_stage;
+
+  // brackets from the sample: median keys, then the MAD window around its midpoint
+  hipLaunchKernelGGL(k_rs_sample, gs, dim3(256), 0, st, vals, per_set, 0, (const double*)nullptr, S, mult, samp);
+  sample_bracket(ctx, st, samp, nsets, S, a, b, bkt0);
+  hipLaunchKernelGGL(k_rs_mad_center, g1d, dim3(64), 0, st, (const uint32_t*)bkt0, nsets, pl, mhat);
+  hipLaunchKernelGGL(k_rs_sample_dev, gs, dim3(256), 0, st, samp, S, (const double*)mhat);
+  sample_bracket(ctx, st, samp, nsets, S, a, b, bkt1);
+  hipLaunchKernelGGL(k_rs_mad_window, g1d, dim3(64), 0, st, (const uint32_t*)bkt1, nsets, pl, wk);
+  // one pass over the values for both
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(256), 0, st, (int64_t*)cnt0, (int64_t)(4 * nsets), (int64_t)0);
+  const dim3 gg(grid_for(per_set, kGather2Round * 2, 1024), nsets);
+#define GATHER2(V, NN)                                                                                          \
+  hipLaunchKernelGGL((k_rs_gather2<V, NN>), gg, dim3(256), 0, st, vals, per_set, (const uint32_t*)bkt0,            \
+                     (const uint32_t*)wk, cap0, cap1, cnt0, cnt1, g0, g1)
+  if (vec && nonneg)
+    GATHER2(true, true);
+  else if (vec)
+    GATHER2(true, false);
+  else if (nonneg)
+    GATHER2(false, true);
+  else
+    GATHER2(false, false);
+#undef GATHER2
+  LAUNCH_CHECK(ctx);
+  HIP_TRY(ctx, hipMemcpyAsync(h, cnt0, (size_t)nsets * 32, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  bool ok0 = true, ok1 = true;
+  int64_t max0 = 1, max1 = 1;
+  for (int s = 0; s < nsets; ++s) {
+    const int64_t below = (int64_t)h[2 * s], in = (int64_t)h[2 * s + 1];
+    const int64_t inner = (int64_t)h[2 * nsets + 2 * s], win = (int64_t)h[2 * nsets + 2 * s + 1];
+    ok0 = ok0 && in <= cap0 && below <= r_lo && r_hi < below + in;
+    ok1 = ok1 && win <= cap1 && inner <= r_lo && r_hi < inner + win;
+    max0 = std::max(max0, in);
+    max1 = std::max(max1, win);
+  }
+  // median: inside the bracket (rank offsets at cnt0[2 s], counts at cnt0[2 s + 1])
+  if (ok0) {
+    hipLaunchKernelGGL(k_copy_stride2_u64, dim3(1), dim3(64), 0, st, (const unsigned long long*)cnt0 + 1, nv0,
+                       (int64_t)nsets);
+    rc = rs_select_middle(ctx, st, (const float*)g0, nsets, cap0, 2, 0, mu, nv0, cnt0, r_lo, r_hi, max0, med_out);
+  } else {
+    rc = rs_select_middle(ctx, st, vals, nsets, per_set, 0, 0, mu, nullptr, nullptr, r_lo, r_hi, per_set, med_out);
+  }
+  if (rc != FITRIG_OK) return rc;
+  finish(0);
+  // MAD: inside the window, then verified against the exact median
+  bool mad_done = false;
+  if (ok1) {
+    hipLaunchKernelGGL(k_copy_stride2_u64, dim3(1), dim3(64), 0, st, (const unsigned long long*)cnt1 + 1, nv1,
+                       (int64_t)nsets);
+    // g1 holds the values q: keys |q - med| are formed as the passes read them
+    if ((rc = rs_select_middle(ctx, st, (const float*)g1, nsets, cap1, 1, 1, mu, nv1, cnt1, r_lo, r_hi, max1,
+                               dev_out)) != FITRIG_OK)
+      return rc;
+    uint32_t* bad = (uint32_t*)(cnt1 + 2 * nsets);  // rs_cnt holds 4 counts then one flag per set
+    hipLaunchKernelGGL(k_rs_mad_verify, g1d, dim3(64), 0, st, (const double*)pl, (const double*)mu,
+                       (const double*)dev_out, (const unsigned long long*)cnt1, nsets, bad);
+    LAUNCH_CHECK(ctx);
+    uint32_t* hb = (uint32_t*)h;
+    HIP_TRY(ctx, hipMemcpyAsync(hb, bad, (size_t)nsets * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    mad_done = true;
+    for (int s = 0; s < nsets; ++s) mad_done = mad_done && hb[s] == 0;
+  }
+  if (!mad_done) {
+    // a pass of its own around the exact median
+    hipLaunchKernelGGL(k_rs_sample, gs, dim3(256), 0, st, vals, per_set, 1, (const double*)mu, S, mult, samp);
+    sample_bracket(ctx, st, samp, nsets, S, a, b, bkt1);
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, (int64_t*)cnt1, (int64_t)(2 * nsets), (int64_t)0);
+    const dim3 g1g(grid_for(per_set, 256 * 16, 512), nsets);
+    if (vec)
+      hipLaunchKernelGGL(k_rs_gather<true>, g1g, dim3(256), 0, st, vals, per_set, 1, (const double*)mu,
+                         (const uint32_t*)bkt1, cap1, cnt1, g1);
+    else
+      hipLaunchKernelGGL(k_rs_gather<false>, g1g, dim3(256), 0, st, vals, per_set, 1, (const double*)mu,
+                         (const uint32_t*)bkt1, cap1, cnt1, g1);
+    LAUNCH_CHECK(ctx);
+    HIP_TRY(ctx, hipMemcpyAsync(h, cnt1, (size_t)nsets * 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    bool ok = true;
+    int64_t mx = 1;
+    for (int s = 0; s < nsets; ++s) {
+      const int64_t below = (int64_t)h[2 * s], in = (int64_t)h[2 * s + 1];
+      ok = ok && in <= cap1 && below <= r_lo && r_hi < below + in;
+      mx = std::max(mx, in);
+    }
+    if (ok) {
+      hipLaunchKernelGGL(k_copy_stride2_u64, dim3(1), dim3(64), 0, st, (const unsigned long long*)cnt1 + 1, nv1,
+                         (int64_t)nsets);
+      rc = rs_select_middle(ctx, st, (const float*)g1, nsets, cap1, 2, 1, mu, nv1, cnt1, r_lo, r_hi, mx, dev_out);
+    } else {
+      rc = rs_select_middle(ctx, st, vals, nsets, per_set, 1, 1, mu, nullptr, nullptr, r_lo, r_hi, per_set, dev_out);
+    }
+    if (rc != FITRIG_OK) return rc;
+  }
+  finish(1);
   LAUNCH_CHECK(ctx);
   return FITRIG_OK;
 }
@@ -672,7 +762,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
           FITRIG_OK)
         return rc;
     } else {
-      if ((rc = robust_spread(ctx, st, qmap, np, plane, mu, sigma, flags)) != FITRIG_OK) return rc;
+      if ((rc = robust_spread(ctx, st, qmap, np, plane, !cfg.r_signed, mu, sigma, flags)) != FITRIG_OK) return rc;
     }
   }
 
@@ -779,7 +869,8 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
         if ((rc = moments(ctx, st, (const double*)ctx->cube.p, np, ncell, 1, ncell, mu, sigma, flags)) != FITRIG_OK)
           return rc;
       } else {
-        if ((rc = robust_spread(ctx, st, (const float*)ctx->cube_f.p, np, ncell, mu, sigma, flags)) != FITRIG_OK)
+        if ((rc = robust_spread(ctx, st, (const float*)ctx->cube_f.p, np, ncell, !cfg.r_signed, mu, sigma, flags)) !=
+            FITRIG_OK)
           return rc;
       }
       SegLayout L{Ty, Tx, np, 1, 64, (Tx + 63) / 64, 1, Ty};
@@ -828,7 +919,8 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
           FITRIG_OK)
         return rc;
     } else {
-      if ((rc = robust_spread(ctx, st, (const float*)ctx->eta_f.p, 1, ntiles, eta_mu, eta_sig, eta_flag)) != FITRIG_OK)
+      if ((rc = robust_spread(ctx, st, (const float*)ctx->eta_f.p, 1, ntiles, true, eta_mu, eta_sig, eta_flag)) !=
+          FITRIG_OK)
         return rc;
     }
     SegLayout L{Ty, Tx, 1, 1, 64, (Tx + 63) / 64, 1, Ty};
@@ -1023,7 +1115,7 @@ fitrig_status fitrig_destroy(fitrig_ctx* ctx) {
                     &ctx->comp_of,   &ctx->c_root,   &ctx->c_npix,    &ctx->c_key,    &ctx->c_w,     &ctx->c_box,
                     &ctx->c_out,     &ctx->bflag,    &ctx->blk_entry, &ctx->blk_slot, &ctx->band_start,
                     &ctx->band_end,  &ctx->rowslot,  &ctx->rs_next,  &ctx->rs_samp,  &ctx->rs_gbuf,
-                    &ctx->rs_bkt,    &ctx->rs_cnt,   &ctx->rs_nvalid};
+                    &ctx->rs_bkt,    &ctx->rs_cnt,   &ctx->rs_nvalid, &ctx->rs_plan};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
@@ -1114,7 +1206,8 @@ int64_t scratch_estimate(const fitrig_config& cfg, int n, int H, int W) {
   const int64_t Ty = (H + cfg.tile - 1) / cfg.tile, Tx = (W + cfg.tile - 1) / cfg.tile;
   int64_t b = np * nwg * 256 + nseg * 4 + np * nbands * ncol * kPieces * 24 + np * Ty * Tx * 12;
   b += segcap * (8 + 8 + 64 * 12) + 2 * segcap * (4 + 4 + 8 + 48 + 16 + 2 * (int64_t)sizeof(fitrig_candidate));
-  if (cfg.sigma_est == FITRIG_MEDIAN_MAD) b += np * plane * 4;
+  // median / MAD: the value map, plus the bracket gathers (about 4 % of it)
+  if (cfg.sigma_est == FITRIG_MEDIAN_MAD) b += np * plane * 4 + np * plane / 2;
   return b;
 }
 

@@ -1202,6 +1202,192 @@ __global__ __launch_bounds__(256) void k_rs_gather(const float* vals, int64_t pe
     atomicAdd(cnt + 2 * s, (unsigned long long)wsum[0] + wsum[1] + wsum[2] + wsum[3]);
 }
 
+// ---- one pass for both brackets (median and MAD) --------------------------
+// Before the pass the median is known only to lie in the sample bracket
+// [qlo, qhi]; with mhat its midpoint and w = max(mhat - qlo, qhi - mhat),
+// every cell's |q - med| is within w of |q - mhat|. The MAD bracket [dlo, dhi]
+// comes from the sample of |q - mhat|, so the cells whose |q - med| can fall
+// in [dlo - w, dhi + w] have |q - mhat| in [dlo - 2w, dhi + 2w]: those are
+// gathered, the ones below counted. After the exact median is known the
+// selection is verified against the actual |med - mhat| (k_rs_mad_verify).
+// Plan per set: pl[4 s + 0..3] = mhat, w, t_in, t_out.
+__global__ void k_rs_mad_center(const uint32_t* bkt0, int nsets, double* pl, double* mhat) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  const double lo = (double)ord_val(bkt0[2 * s]), hi = (double)ord_val(bkt0[2 * s + 1]);
+  const double m = 0.5 * lo + 0.5 * hi;
+  pl[4 * s + 0] = m;
+  pl[4 * s + 1] = fmax(m - lo, hi - m);
+  mhat[s] = m;
+}
+
+// The window as order-key bounds wk[4 s + 0..3] = kA, kB, kC, kD: inner
+// cells kB < key < kC, outer cells key < kA or key > kD, the window the
+// rest. The float bounds round inwards for the inner interval and outwards
+// for the outer one, so inner cells have |q - mhat| < t_in and outer cells
+// |q - mhat| > t_out exactly.
+__global__ void k_rs_mad_window(const uint32_t* bkt1, int nsets, double* pl, uint32_t* wk) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  const double m = pl[4 * s + 0], w = pl[4 * s + 1];
+  const double t_in = (double)__uint_as_float(bkt1[2 * s]) - 2.0 * w;
+  const double t_out = (double)__uint_as_float(bkt1[2 * s + 1]) + 2.0 * w;
+  pl[4 * s + 2] = t_in;
+  pl[4 * s + 3] = t_out;
+  const uint32_t kA = ord_key(__double2float_rd(m - t_out)), kD = ord_key(__double2float_ru(m + t_out));
+  uint32_t kB = ord_key(__double2float_ru(m - t_in)), kC = ord_key(__double2float_rd(m + t_in));
+  if (!(t_in > 0.0) || kC <= kB) kB = kC = kA;  // no inner cells
+  wk[4 * s + 0] = kA;
+  wk[4 * s + 1] = kB;
+  wk[4 * s + 2] = kC;
+  wk[4 * s + 3] = kD;
+}
+
+// Median part: order keys below bkt0[2s] counted (cnt0[2s]), keys in
+// [bkt0[2s], bkt0[2s+1]] counted (cnt0[2s+1]) and gathered into g0. MAD part
+// (bounds wk of k_rs_mad_window): inner cells counted (cnt1[2s]), window
+// cells counted (cnt1[2s+1]) and gathered (the bits of q) into g1. Two LDS
+// stages, each appended with one atomic per flush. NONNEG: every value is
+// +0 or positive (then its order key is its bits with the top bit set).
+constexpr int kGather2Round = 256 * 8;
+template <bool VEC, bool NONNEG>
+__global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t per_set, const uint32_t* bkt0,
+                                                    const uint32_t* wk, int64_t cap0, int64_t cap1,
+                                                    unsigned long long* cnt0, unsigned long long* cnt1, uint32_t* g0,
+                                                    uint32_t* g1) {
+  constexpr int kStage = kGather2Round;  // one round fits
+  __shared__ uint32_t stage[2][kStage];
+  __shared__ uint32_t wsum[4];
+  __shared__ unsigned long long gbase;
+  __shared__ uint32_t red[2][4];
+  const int s = blockIdx.y;
+  const uint32_t lo = bkt0[2 * s], hi = bkt0[2 * s + 1];
+  const uint32_t kA = wk[4 * s + 0], kB = wk[4 * s + 1], kC = wk[4 * s + 2], kD = wk[4 * s + 3];
+  const float* v = vals + (int64_t)s * per_set;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t below = 0, inner = 0, nst0 = 0, nst1 = 0;
+  const int64_t step = (int64_t)gridDim.x * kGather2Round;
+  auto flush = [&](int which, uint32_t n) {
+    unsigned long long* cnt = which ? cnt1 : cnt0;
+    uint32_t* out = (which ? g1 : g0) + (int64_t)s * (which ? cap1 : cap0);
+    const int64_t cap = which ? cap1 : cap0;
+    if (threadIdx.x == 0) gbase = atomicAdd(cnt + 2 * s + 1, (unsigned long long)n);
+    __syncthreads();
+    const unsigned long long b0 = gbase;
+    for (uint32_t j = threadIdx.x; j < n; j += 256)
+      if ((int64_t)(b0 + j) < cap) out[b0 + j] = stage[which][j];
+    __syncthreads();  // stage and gbase read before they are reused
+  };
+  auto fetch = [&](int64_t base, float (&q)[8]) {
+    if (VEC) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t i = base + 4 * ((int64_t)j * 256 + threadIdx.x);  // per_set % 4 == 0
+        const float4 x = i < per_set ? *reinterpret_cast<const float4*>(v + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+        q[4 * j + 0] = x.x;
+        q[4 * j + 1] = x.y;
+        q[4 * j + 2] = x.z;
+        q[4 * j + 3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t i = base + (int64_t)j * 256 + threadIdx.x;
+        q[j] = i < per_set ? v[i] : 0.0f;
+      }
+    }
+  };
+  auto index_of = [&](int64_t base, int j) -> int64_t {
+    return VEC ? base + 4 * ((int64_t)(j >> 2) * 256 + threadIdx.x) + (j & 3) : base + (int64_t)j * 256 + threadIdx.x;
+  };
+  float q[8];
+  int64_t base = blockIdx.x * (int64_t)kGather2Round;
+  if (base < per_set) fetch(base, q);
+  for (; base < per_set; base += step) {
+    float nq[8];
+    if (base + step < per_set) fetch(base + step, nq);
+    uint32_t k[8];
+    uint32_t sel = 0;  // bit j: median bracket, bit 8 + j: MAD window
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const bool ok = index_of(base, j) < per_set;
+      k[j] = NONNEG ? (__float_as_uint(q[j]) | 0x80000000u) : ord_key(q[j]);
+      const bool in_w = k[j] > kB && k[j] < kC;
+      below += (ok && k[j] < lo) ? 1u : 0u;
+      inner += (ok && in_w) ? 1u : 0u;
+      sel |= (ok && k[j] - lo <= hi - lo) ? (1u << j) : 0u;
+      sel |= (ok && !in_w && k[j] - kA <= kD - kA) ? (1u << (8 + j)) : 0u;
+    }
+    // counts of both stages packed in 16-bit halves (at most 2048 each)
+    const uint32_t c = (uint32_t)__popc(sel & 0xFFu) | ((uint32_t)__popc(sel >> 8) << 16);
+    const uint32_t inc = wave_incl_scan(c);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    const uint32_t w0 = wsum[0], w1 = wsum[1], w2 = wsum[2], w3 = wsum[3];
+    const uint32_t tot = w0 + w1 + w2 + w3;
+    const uint32_t woff = (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
+    const uint32_t tot0 = tot & 0xFFFFu, tot1 = tot >> 16;
+    // uniform decisions: nst and tot are the same in every thread
+    if (nst0 + tot0 > (uint32_t)kStage) {
+      flush(0, nst0);
+      nst0 = 0;
+    }
+    if (nst1 + tot1 > (uint32_t)kStage) {
+      flush(1, nst1);
+      nst1 = 0;
+    }
+    if (c) {
+      const uint32_t ex = woff + inc - c;
+      uint32_t p0 = nst0 + (ex & 0xFFFFu), p1 = nst1 + (ex >> 16);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (sel & (1u << j)) stage[0][p0++] = k[j];
+        if (sel & (1u << (8 + j))) stage[1][p1++] = __float_as_uint(q[j]);
+      }
+    }
+    nst0 += tot0;
+    nst1 += tot1;
+    __syncthreads();  // stages written and wsum read by every thread
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q[j] = nq[j];
+  }
+  if (nst0) flush(0, nst0);
+  if (nst1) flush(1, nst1);
+  uint32_t b = below, in = inner;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    b += __shfl_xor(b, off);
+    in += __shfl_xor(in, off);
+  }
+  if (lane == 0) {
+    red[0][wave] = b;
+    red[1][wave] = in;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(cnt0 + 2 * s, (unsigned long long)red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+    atomicAdd(cnt1 + 2 * s, (unsigned long long)red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+  }
+}
+
+// The MAD selected from the gathered window is exact when every counted
+// (inner) cell's key is at most the lower middle value and every cell beyond
+// the window has a key above the upper one: inner cells have |q - med| <
+// t_in + |med - mhat|, outer ones |q - med| > t_out - |med - mhat| (slack
+// 2^-40 covers the double roundings of these bounds). bad[s] = 1 otherwise.
+__global__ void k_rs_mad_verify(const double* pl, const double* med, const double* dev,
+                                const unsigned long long* cnt1, int nsets, uint32_t* bad) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets) return;
+  const double e = fabs(med[s] - pl[4 * s + 0]);
+  const double slack = 0x1p-40;
+  const float in_max = (float)((pl[4 * s + 2] + e) * (1.0 + slack));
+  const float out_min = (float)((pl[4 * s + 3] - e) * (1.0 - slack));
+  const bool ok_in = cnt1[2 * s] == 0 || (double)in_max <= dev[2 * s];
+  const bool ok_out = (double)out_min > dev[2 * s + 1];
+  bad[s] = (ok_in && ok_out && isfinite(med[s])) ? 0u : 1u;
+}
+
 // Dispersion keys of a sample of order keys: |q - med| of the sampled q.
 __global__ void k_rs_sample_dev(uint32_t* samp, int64_t S, const double* med) {
   const int s = blockIdx.y;

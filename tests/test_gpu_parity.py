@@ -180,6 +180,17 @@ def test_median_mad_large_sets(W):
     check_candidates(cands, out, tau)
 
 
+def test_median_mad_large_unaligned():
+    """A set of more than 8 * 2^20 cells whose count is odd and not a
+    multiple of 4: the bracket pass reads it one value at a time."""
+    rng = np.random.default_rng(4099)
+    X = (rng.normal(size=(3, 2049, 4097)) + 3.0).astype(np.float32)
+    tau = 10.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, window=3, sigma_est=1, branches=1, with_maps=False)
+    out = ref.detect(used, tau=tau, window=3, sigma_est=ref.MEDIAN_MAD, branches=ref.IMAGE, keep_maps=False)
+    check_stats(stats["mu"], stats["sigma"], out["mu"], out["sigma"])
+
+
 def test_median_mad_large_periodic():
     """A map periodic along rows at the sampling stride: the strided sample
     sees one phase only, the bracket misses and the full selection runs."""
