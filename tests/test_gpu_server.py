@@ -40,12 +40,13 @@ def _plan(seed):
     return fields, reqs
 
 
-@pytest.mark.parametrize("branches", [1, 3])
-def test_server_mix_equals_alone(branches):
+@pytest.mark.parametrize("branches,extra", [(1, {}), (3, {}), (3, dict(sigma_est=1)), (3, dict(mode=1, tile=8))])
+def test_server_mix_equals_alone(branches, extra):
     from paper_2509_21754_amd import Server
 
     tau = 4.0
     cfg = dict(window=5, branches=branches, tile=16)
+    cfg.update(extra)
     fields, reqs = _plan(7 + branches)
     frames = {f: [] for f in fields}   # every frame submitted so far, host float copies
     submitted = []
@@ -78,7 +79,8 @@ def test_server_mix_equals_alone(branches):
             # the running M covers every frame of the field so far and C
             seen = np.stack(frames[f][:first + used.shape[0]])
             assert r["M"] == max(float(seen.max()), 1e-6)
-            out = ref.detect(used.astype(np.float64), tau=tau, window=5, branches=branches, tile=16)
+            out = ref.detect(used.astype(np.float64), tau=tau, window=5, branches=branches, tile=cfg["tile"],
+                             sigma_est=cfg.get("sigma_est", 0), mode=cfg.get("mode", 0))
             from paper_2509_21754_amd.fitrig import _rec_dict
             check_candidates([_rec_dict(x) for x in alone], out, tau)
         # per-field submission order
