@@ -377,11 +377,14 @@ struct Stream {
   static constexpr int NR = kBand + 2 * H;
   static constexpr int NT = 16;            // outputs per horizontal task
   static constexpr int NH = NT + 2 * H;
-  // LDS row layout: column c at c + c/16 (one pad word per 16 columns) and a
-  // row stride of 16 mod 64 words, so the 16-column horizontal tasks of a
-  // wave read 64 distinct banks.
-  static constexpr int LDW = kLanes + 16;
-  __device__ static __forceinline__ int lcol(int c) { return c + (c >> 4); }
+  // LDS row layout for 32 banks (a half wave per cycle): column c at
+  // c + ((c >> 5) & 7), row stride 264 = 8 (mod 16). A half wave writes 32
+  // consecutive columns of one row (one 32-column run: 32 distinct banks); the
+  // horizontal tasks of a half wave (2 rows x 16 chunks of 16 columns) read
+  // 16 ch + i: run offsets 0..7 plus 8 per row and 16 per odd chunk give 32
+  // distinct banks for every i.
+  static constexpr int LDW = kLanes + 8;
+  __device__ static __forceinline__ int lcol(int c) { return c + ((c >> 5) & 7); }
 
   // per-column tile sums of the group's columns, with 32 zero words on each
   // side so a 32-column tile piece is always 32 in-range reads
@@ -482,19 +485,22 @@ struct Stream {
     const int y = y0 + r;
     const int xc = x0 + NT * ch;
     const bool chv = (NT * ch < A.out_w) && (xc < A.W) && (y < A.H);
-    // chunk base in the padded layout; column 16 ch + i sits at 17 ch + i + i/16.
-    // Reads past column 255 (last chunk) land in padding or the next row and
-    // only feed outputs outside the group.
-    const int cb = chv ? 17 * ch : 0;
+    // column 16 ch + i of the padded layout: cb + i for i < 16, cb2 + i past
+    // the chunk (the next run for odd ch). The last chunk's columns 256.. read
+    // words 256..263 of the row (bank-aligned with the rest; they only feed
+    // outputs outside the group).
+    const int cb = chv ? 16 * ch + (ch >> 1) : 0;
+    const int cb2 = chv ? cb + (ch & 1) - (ch == 15 ? 8 : 0) : 0;
     float os[NT], om[NT], orr[NT];
     {
       // all three rows of inputs are requested before the windows run
       float h0[NH], h1[NH], h2[NH];
 #pragma unroll
       for (int i = 0; i < NH; ++i) {
-        h0[i] = sh.V[0][r][cb + i + (i >> 4)];
-        h1[i] = sh.V[1][r][cb + i + (i >> 4)];
-        h2[i] = sh.V[2][r][cb + i + (i >> 4)];
+        const int ci = (i < 16 ? cb : cb2) + i;
+        h0[i] = sh.V[0][r][ci];
+        h1[i] = sh.V[1][r][ci];
+        h2[i] = sh.V[2][r][ci];
       }
       Win<H, NT, false>::run(h0, os, nullptr);
       WinMax<H, NT>::run(h1, om);
