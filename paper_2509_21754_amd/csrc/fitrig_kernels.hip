@@ -579,14 +579,18 @@ struct Stream {
     }
     if (A.tile_part) {
       // job = (quantity qd, piece p) on 8 lanes; lane sub sums columns
-      // 4 sub .. 4 sub + 3 of the 32 columns of tile x0/32 + p (zeros outside
-      // the group or the image), then the 8 lanes combine by DPP (fixed order)
+      // sub, sub + 8, sub + 16, sub + 24 of the 32 columns of tile x0/32 + p
+      // (zeros outside the group or the image), then the 8 lanes combine by
+      // DPP (fixed order). The four jobs of a half wave start at different
+      // 8-column segments, so each read touches 32 distinct banks.
       const int job = lane >> 3, sub = lane & 7;
       const int qd = job / kPieces, p = job - kPieces * (job / kPieces);
       const int qs = qd < 3 ? qd : 0;
-      const int c0 = (x0 / 32 + p) * 32 - x0 + 4 * sub;  // >= -31
+      const int c0 = (x0 / 32 + p) * 32 - x0 + sub;  // >= -31
       const float* cv = &sh.col[qs][CPAD + c0];
-      const float v0 = cv[0], v1 = cv[1], v2 = cv[2], v3 = cv[3];
+      const int rot = job & 3;
+      const float v0 = cv[8 * (rot & 3)], v1 = cv[8 * ((rot + 1) & 3)];
+      const float v2 = cv[8 * ((rot + 2) & 3)], v3 = cv[8 * ((rot + 3) & 3)];
       float sm = (v0 + v1) + (v2 + v3);
       uint32_t mb = umax3(__float_as_uint(v0), __float_as_uint(v1), max(__float_as_uint(v2), __float_as_uint(v3)));
       sm += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sm), 0xB1, 0xF, 0xF, false));
