@@ -260,3 +260,78 @@ def test_mad_sigma_consistent_on_gaussian():
     v = rng.normal(size=N)
     _, sig = ref.spread(v, ref.MEDIAN_MAD)
     assert abs(sig - 1.0) < 5 * 1.17 / math.sqrt(N)
+
+
+# ---- sub-cell peak localisation (oracle/interp.py) --------------------------
+
+def test_interp_spline_and_makima_match_scipy():
+    from scipy.interpolate import Akima1DInterpolator, CubicSpline
+
+    from oracle import interp as I
+
+    rng = np.random.default_rng(11)
+    x = np.arange(5.0)
+    ts = np.linspace(0.0, 4.0, 57)
+    for _ in range(20):
+        f = rng.normal(size=5) * rng.uniform(0.1, 10.0)
+        got_s = np.array([I.interp1(f, t, I.SPLINE) for t in ts])
+        got_m = np.array([I.interp1(f, t, I.MAKIMA) for t in ts])
+        assert np.allclose(got_s, CubicSpline(x, f)(ts), rtol=1e-12, atol=1e-12)
+        assert np.allclose(got_m, Akima1DInterpolator(x, f, method="makima")(ts), rtol=1e-12, atol=1e-12)
+
+
+def test_interp_methods_pass_through_nodes_and_reproduce_polynomials():
+    from oracle import interp as I
+
+    rng = np.random.default_rng(12)
+    f = rng.normal(size=5)
+    for meth in (I.BILINEAR, I.BICUBIC, I.SPLINE, I.MAKIMA):
+        for k in range(5):
+            assert I.interp1(f, float(k), meth) == pytest.approx(f[k], abs=1e-14)
+    lin = [0.5 + 1.25 * k for k in range(5)]
+    quad = [-(k - 2.3) ** 2 + 5.0 for k in range(5)]
+    cub = [0.1 * k ** 3 - k ** 2 + 2.0 for k in range(5)]
+    for t in np.linspace(1.0, 3.0, 17):
+        for meth in (I.BILINEAR, I.BICUBIC, I.SPLINE, I.MAKIMA):
+            assert I.interp1(lin, t, meth) == pytest.approx(0.5 + 1.25 * t, abs=1e-12)
+        # Keys' kernel (a = -1/2) is exact for quadratics away from the ends;
+        # the not-a-knot spline for cubics
+        assert I.interp1(quad, t, I.BICUBIC) == pytest.approx(-(t - 2.3) ** 2 + 5.0, abs=1e-12)
+        assert I.interp1(cub, t, I.SPLINE) == pytest.approx(0.1 * t ** 3 - t ** 2 + 2.0, abs=1e-12)
+    # Keys' weights are a partition of unity
+    for t in np.linspace(0.0, 1.0, 11):
+        assert sum(I.keys_weight(t - k) for k in range(-1, 3)) == pytest.approx(1.0, abs=1e-13)
+
+
+@pytest.mark.parametrize("y0,x0", [(10.25, 7.5), (9.8125, 8.0625), (10.0, 8.0)])
+def test_interp_peak_of_a_quadratic_surface_is_exact(y0, x0):
+    """A separable quadratic peak sampled on the cells: bicubic and spline
+    reproduce it, so the grid maximum is the true peak (on the 1/16 grid)."""
+    from oracle import interp as I
+
+    yy, xx = np.mgrid[0:20, 0:16].astype(np.float64)
+    m = 100.0 - 1.5 * (yy - y0) ** 2 - 0.75 * (xx - x0) ** 2
+    py, px = int(round(y0)), int(round(x0))
+    for meth in (I.BICUBIC, I.SPLINE):
+        y, x, v = I.interp_peak(m, py, px, meth, sub=16)
+        assert (y, x) == (y0, x0)
+        assert v == pytest.approx(100.0, abs=1e-9)
+    # bilinear surfaces peak at a node
+    y, x, _ = I.interp_peak(m, py, px, I.BILINEAR, sub=16)
+    assert y == int(y) and x == int(x)
+
+
+def test_interp_peak_ties_and_edges():
+    from oracle import interp as I
+
+    m = np.full((6, 7), 3.0)
+    # a flat bilinear surface: every grid value ties, the first (a, b) wins
+    assert I.interp_peak(m, 2, 3, I.BILINEAR, sub=4)[:2] == (1.0, 2.0)
+    # at a corner the neighbourhood repeats the edge cells: a peak cell with
+    # higher neighbours on the inside moves inward
+    m = np.zeros((6, 7))
+    m[0, 0], m[0, 1], m[1, 0], m[1, 1] = 5.0, 4.0, 4.0, 3.0
+    y, x, _ = I.interp_peak(m, 0, 0, I.SPLINE, sub=8)
+    assert -1.0 <= y <= 1.0 and -1.0 <= x <= 1.0
+    F = I.neighbourhood(m, 0, 0)
+    assert F[0, 0] == F[2, 2] == 5.0 and F[4, 4] == 0.0
