@@ -180,6 +180,35 @@ int32_t fitrig_phase_times(const fitrig_ctx* ctx, double* ms, int32_t cap);
 /* Library ABI version (FITRIG_ABI_VERSION of the build). */
 int32_t fitrig_abi_version(void);
 
+/* ---- sub-cell localisation ---------------------------------------------------
+ * The paper localises a source inside the selected tiles by interpolating the
+ * tile values (the spectrum matrix eta) with a bilinear, spline, bicubic or
+ * Makima cubic interpolant and taking the interpolated maximum (Sec. 2.4.2;
+ * Sec. 3.1 uses a spline on eta). For each peak cell (py[i], px[i]) of a value
+ * map (eta_map from fitrig_detect, or an index map), the 5 x 5 cells around
+ * it (indices clamped into the map, so edge values repeat) are interpolated
+ * along x for each row and then along y, the surface is evaluated at
+ * (py + a / sub, px + b / sub) for a, b = -sub .. sub, and the grid point of
+ * the largest value is returned (ties: smallest a, then smallest b).
+ * Methods, on unit-spaced nodes:
+ *   BILINEAR  straight lines between nodes;
+ *   BICUBIC   cubic convolution with Keys' kernel, a = -1/2;
+ *   SPLINE    cubic spline through the 5 nodes, not-a-knot end conditions;
+ *   MAKIMA    modified Akima piecewise cubic (end slopes extended linearly).
+ * map: device FP32 [H][W] row-major (read only). py, px: host int32 [n].
+ * out: host double [3 n]: y, x, interpolated value per peak. hip_stream:
+ * hipStream_t (NULL = legacy default stream) on the current device; the call
+ * returns when out is written. Arithmetic in FP64.
+ * Errors: E_INVAL (n < 0, H or W < 1, sub outside 1..64, unknown method, null
+ * pointers with n > 0, a peak outside the map), E_NOMEM, E_HIP. n = 0 does
+ * nothing. */
+#define FITRIG_INTERP_BILINEAR 0
+#define FITRIG_INTERP_BICUBIC 1
+#define FITRIG_INTERP_SPLINE 2
+#define FITRIG_INTERP_MAKIMA 3
+fitrig_status fitrig_interp_peaks(const float* map, int32_t H, int32_t W, const int32_t* py, const int32_t* px,
+                                  int32_t n, int32_t method, int32_t sub, double* out, void* hip_stream);
+
 /* ---- serving form ----------------------------------------------------------
  * A real-time trigger loop: requests are snapshot stacks of a field (a
  * fixed sky position and image size). The server keeps each field's last two

@@ -4,5 +4,6 @@ The Python side only marshals arguments; see ``fitrig.py``.
 """
 from .fitrig import (  # noqa: F401
     Context, FitrigError, Server, fitrig_abi_version, fitrig_config_default, fitrig_create, fitrig_destroy,
-    fitrig_detect, fitrig_last_hip_error, fitrig_phase_times, fitrig_status_string, load,
+    fitrig_detect, fitrig_interp_peaks, fitrig_last_hip_error, fitrig_phase_times, fitrig_status_string,
+    interp_peaks, load, INTERP_BILINEAR, INTERP_BICUBIC, INTERP_SPLINE, INTERP_MAKIMA,
 )

@@ -28,8 +28,10 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
-    # fitrig_api.hip includes the kernels; fitrig_server.hip is the serving loop
-    srcs = [os.path.join(CSRC, "fitrig_api.hip"), os.path.join(CSRC, "fitrig_server.hip")]
+    # fitrig_api.hip includes the kernels; fitrig_server.hip is the serving
+    # loop; fitrig_interp.hip the sub-cell localisation
+    srcs = [os.path.join(CSRC, "fitrig_api.hip"), os.path.join(CSRC, "fitrig_server.hip"),
+            os.path.join(CSRC, "fitrig_interp.hip")]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            *srcs, "-o", tmp, "-lpthread"]

@@ -125,6 +125,7 @@ EXPORTS = (
     "fitrig_poll",
     "fitrig_release",
     "fitrig_server_destroy",
+    "fitrig_interp_peaks",
 )
 N_PHASES = 5
 PHASES = ("index_pass", "spread", "image_select", "freq_branch", "host_copy")
@@ -170,6 +171,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fitrig_release.restype = i32
     L.fitrig_server_destroy.argtypes = [vp]
     L.fitrig_server_destroy.restype = i32
+    L.fitrig_interp_peaks.argtypes = [vp, i32, i32, vp, vp, i32, i32, i32, vp, vp]
+    L.fitrig_interp_peaks.restype = i32
     _lib = L
     return L
 
@@ -253,6 +256,39 @@ def fitrig_release(srv, ticket) -> int:
 
 def fitrig_server_destroy(srv) -> int:
     return load().fitrig_server_destroy(srv)
+
+
+INTERP_BILINEAR, INTERP_BICUBIC, INTERP_SPLINE, INTERP_MAKIMA = 0, 1, 2, 3
+
+
+def fitrig_interp_peaks(map_ptr, H: int, W: int, py, px, n: int, method: int, sub: int, out, stream) -> int:
+    return load().fitrig_interp_peaks(map_ptr, H, W, py, px, n, method, sub, out, stream)
+
+
+def interp_peaks(value_map, peaks, method: int = INTERP_SPLINE, sub: int = 16, stream=None):
+    """Sub-cell positions of peak cells of a 2-D FP32 device map.
+
+    peaks: sequence of (y, x) cells. Returns a float64 array [n, 3] of
+    (y, x, interpolated value)."""
+    import numpy as np
+
+    if not value_map.is_cuda or value_map.dim() != 2 or not value_map.is_contiguous():
+        raise ValueError("value_map must be a contiguous 2-D device tensor")
+    if str(value_map.dtype) != "torch.float32":
+        raise ValueError("value_map must be float32")
+    pk = np.ascontiguousarray(np.asarray(peaks, dtype=np.int32).reshape(-1, 2))
+    n = pk.shape[0]
+    py = np.ascontiguousarray(pk[:, 0])
+    px = np.ascontiguousarray(pk[:, 1])
+    out = np.zeros((n, 3), dtype=np.float64)
+    H, W = value_map.shape
+    st = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+    rc = fitrig_interp_peaks(ctypes.c_void_p(value_map.data_ptr()), H, W, py.ctypes.data_as(ctypes.c_void_p),
+                             px.ctypes.data_as(ctypes.c_void_p), n, int(method), int(sub),
+                             out.ctypes.data_as(ctypes.c_void_p), st)
+    if rc != OK:
+        raise FitrigError(rc, "fitrig_interp_peaks")
+    return out
 
 
 # ---- torch convenience layer --------------------------------------------------

@@ -101,3 +101,22 @@ def test_server_rejects_bad_config_on_cpu():
     assert F.fitrig_server_destroy(None) == F.E_INVAL
     c = F.fitrig_server_config_default()
     assert (c.n_slots, c.max_fields, c.mem_budget, c.cand_cap, c.freq_window, c.base.window) == (4, 64, 0, 65536, 0, 7)
+
+
+def test_interp_peaks_rejects_bad_arguments_on_cpu():
+    import numpy as np
+
+    py = np.array([1], np.int32)
+    px = np.array([5], np.int32)
+    out = np.zeros(3)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    dummy = ctypes.c_void_p(1)   # never dereferenced: arguments are checked first
+    call = lambda *a: F.fitrig_interp_peaks(*a)    # noqa: E731
+    assert call(dummy, 4, 4, p(py), p(px), 1, F.INTERP_SPLINE, 16, p(out), None) == F.E_INVAL   # x outside
+    assert call(dummy, 4, 8, p(py), p(px), -1, F.INTERP_SPLINE, 16, p(out), None) == F.E_INVAL
+    assert call(dummy, 4, 8, p(py), p(px), 1, 4, 16, p(out), None) == F.E_INVAL
+    assert call(dummy, 4, 8, p(py), p(px), 1, F.INTERP_SPLINE, 0, p(out), None) == F.E_INVAL
+    assert call(dummy, 4, 8, p(py), p(px), 1, F.INTERP_SPLINE, 65, p(out), None) == F.E_INVAL
+    assert call(None, 4, 8, p(py), p(px), 1, F.INTERP_SPLINE, 16, p(out), None) == F.E_INVAL
+    assert call(dummy, 0, 8, p(py), p(px), 1, F.INTERP_SPLINE, 16, p(out), None) == F.E_INVAL
+    assert call(dummy, 4, 8, None, None, 0, F.INTERP_SPLINE, 16, None, None) == F.OK   # nothing to do
