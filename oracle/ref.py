@@ -13,10 +13,12 @@ loops in the paper's order and arranges the results:
 * per-triple spread and selection z > tau with 8-connected components
   (Sec. 2.4.1 Eqs. (8)-(9));
 * the image-frequency branch: tile cube over s, spectrum eta (Eq. (10)),
-  z-score on eta and selection (Eqs. (11)-(12), Sec. 2.4.2).
+  z-score on eta and selection (Eqs. (11)-(12), Sec. 2.4.2);
+* the same spectrum, z-score and selection per cell of the sliding index maps
+  (the per-pixel form of Eq. (10); the paper transforms tiles).
 
 Candidate order: image branch first (by triple, then label), then the
-frequency branch (by label). Label = lowest row-major index of the component.
+frequency branch (by label), then the per-pixel frequency branch (by label). Label = lowest row-major index of the component.
 """
 from __future__ import annotations
 
@@ -32,6 +34,7 @@ _SRC = os.path.join(_HERE, "fitrig_ref.c")
 _LIB = os.path.join(_HERE, "libfitrig_ref.so")
 
 SLIDING, TILES = 0, 1
+FREQ_PIXEL = 4
 MEAN_STD, MEDIAN_MAD = 0, 1
 IMAGE, FREQ = 1, 2
 FLAG_SIGMA_ZERO = 1
@@ -240,5 +243,18 @@ def detect(stack, *, tau: float = 6.0, mode: int = SLIDING, window: int = 7,
         if sig > 0 and np.isfinite(sig):
             for c in components(e, mu, sig, tau):
                 c.update(branch=FREQ, triple=-1)
+                out["cands"].append(c)
+    # per-pixel form: the spectrum of every cell's series of sliding q
+    # (register-resident series on the GPU: 4 <= n' <= 64)
+    out["eta_px"] = None
+    out["eta_px_mu"] = out["eta_px_sigma"] = None
+    if (branches & FREQ_PIXEL) and mode == SLIDING and 4 <= n - 2 <= 64:
+        qp = q if q is not None else index_maps(X, mode=SLIDING, window=window, tile=tile, r_signed=r_signed, C=C)
+        e = eta(qp, harm)
+        mu, sig = spread(e, sigma_est)
+        out["eta_px"], out["eta_px_mu"], out["eta_px_sigma"] = e, mu, sig
+        if sig > 0 and np.isfinite(sig):
+            for c in components(e, mu, sig, tau):
+                c.update(branch=FREQ_PIXEL, triple=-1)
                 out["cands"].append(c)
     return out

@@ -335,3 +335,36 @@ def test_interp_peak_ties_and_edges():
     assert -1.0 <= y <= 1.0 and -1.0 <= x <= 1.0
     F = I.neighbourhood(m, 0, 0)
     assert F[0, 0] == F[2, 2] == 5.0 and F[4, 4] == 0.0
+
+
+def test_per_pixel_frequency_branch_equals_tile_one_with_window_one():
+    """With a 1 x 1 window the sliding maps are the 1 x 1 tile cube, so the
+    per-pixel spectrum, its spread and its components are the tile branch's."""
+    rng = np.random.default_rng(21)
+    X = rng.normal(size=(14, 20, 23)) + 5.0
+    X[::3, 8:11, 4:7] += 6.0
+    for sigma_est in (ref.MEAN_STD, ref.MEDIAN_MAD):
+        out = ref.detect(X, tau=3.0, window=1, tile=1, branches=ref.FREQ | ref.FREQ_PIXEL, sigma_est=sigma_est)
+        assert np.allclose(out["eta_px"], out["eta"], rtol=1e-12, atol=0.0)
+        assert out["eta_px_mu"] == pytest.approx(out["eta_mu"], rel=1e-12)
+        assert out["eta_px_sigma"] == pytest.approx(out["eta_sigma"], rel=1e-12)
+        a = [{k: v for k, v in c.items() if k != "branch"} for c in out["cands"] if c["branch"] == ref.FREQ]
+        b = [{k: v for k, v in c.items() if k != "branch"} for c in out["cands"] if c["branch"] == ref.FREQ_PIXEL]
+        assert a and len(a) == len(b)
+        for u, v in zip(a, b):
+            assert u.keys() == v.keys()
+            for k in u:
+                assert u[k] == pytest.approx(v[k], rel=1e-9, abs=1e-12), k
+
+
+def test_per_pixel_frequency_branch_finds_a_periodic_pixel_source():
+    rng = np.random.default_rng(22)
+    X = rng.normal(size=(34, 40, 48)) + 10.0
+    X[1::4, 20:23, 30:33] += 8.0    # period 4 snapshots
+    out = ref.detect(X, tau=6.0, window=3, branches=ref.FREQ_PIXEL)
+    c = [c for c in out["cands"] if c["branch"] == ref.FREQ_PIXEL]
+    assert c and all(c_["triple"] == -1 for c_ in c)
+    best = max(c, key=lambda c_: c_["peak_z"])
+    assert 18 <= best["peak_y"] <= 24 and 28 <= best["peak_x"] <= 34
+    # outside 4 <= n' <= 64 the branch does not run
+    assert ref.detect(X[:5], tau=6.0, window=3, branches=ref.FREQ_PIXEL)["eta_px"] is None
