@@ -360,6 +360,8 @@ def main() -> int:
                     help="sliding window (per pixel) or the paper's tiles")
     ap.add_argument("--tile", type=int, default=32, help="tile size (tile mode and frequency branch)")
     ap.add_argument("--no-fp16-form", action="store_true", help="skip the FP16-storage run of the same stack")
+    ap.add_argument("--freq-pixel", action="store_true",
+                    help="add the per-pixel frequency branch (spectrum of every pixel's q series)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving replay")
     ap.add_argument("--no-precision-report", action="store_true",
                     help="skip the crop error report of an FP16 / BF16 workload")
@@ -406,8 +408,9 @@ def main() -> int:
     n, H, W = spec.n, spec.H, spec.W
     est = {"mean_std": 0, "median_mad": 1}[args.sigma_est]
     mode = {"sliding": 0, "tiles": 1}[args.mode]
+    branches = 3 | (4 if args.freq_pixel else 0)
     ctx = Context(window=spec.window, profile=1, max_pixels=H * W, max_snap=n, sigma_est=est, mode=mode,
-                  tile=args.tile)
+                  tile=args.tile, branches=branches)
     stream = torch.cuda.current_stream(dev)
     print(f"[bench] timing {args.steps} steps after {args.warmup} warmup", file=sys.stderr, flush=True)
     ms_per_step, step_ms, phases, cands, stats = time_detect(ctx, stack, tau, args.steps, args.warmup, stream)
@@ -438,7 +441,7 @@ def main() -> int:
         "dtype": spec.dtype,
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "n_snap": n, "H": H, "W": W,
-                   "window": spec.window, "tau": tau, "branches": "image+freq", "sigma_est": args.sigma_est,
+                   "window": spec.window, "tau": tau, "branches": "image+freq" + ("+freq_pixel" if args.freq_pixel else ""), "sigma_est": args.sigma_est,
                    "mode": args.mode, "tile": args.tile},
         "hbm_peak_frac_whole_step": round(px * BYTES_IN[spec.dtype] / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "p50_ms": round(statistics.median(step_ms), 4),

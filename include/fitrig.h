@@ -54,6 +54,8 @@ typedef enum { FITRIG_F32 = 0, FITRIG_F16 = 1, FITRIG_BF16 = 2 } fitrig_dtype;
 /* branches (bitmask) */
 #define FITRIG_IMAGE 1        /* image-domain selection, Sec. 2.4.1 */
 #define FITRIG_FREQ 2         /* image-frequency selection, Sec. 2.4.2 (needs n_snap - 2 >= 4) */
+#define FITRIG_FREQ_PIXEL 4   /* the same transform and selection per cell of the sliding index maps
+                                 (sliding mode only; runs for 4 <= n_snap - 2 <= 64) */
 /* spread estimator */
 #define FITRIG_MEAN_STD 0     /* mean and population std (Eq. (8)) */
 #define FITRIG_MEDIAN_MAD 1   /* median and 1.482602218505602 * MAD */
@@ -69,7 +71,7 @@ typedef struct {
   int32_t mode;         /* FITRIG_SLIDING (default) or FITRIG_TILES */
   int32_t window;       /* sliding window, odd, 1..17 (default 7) */
   int32_t tile;         /* tile size for FITRIG_TILES and for the frequency branch (default 32) */
-  int32_t branches;     /* FITRIG_IMAGE | FITRIG_FREQ (default both) */
+  int32_t branches;     /* FITRIG_IMAGE | FITRIG_FREQ | FITRIG_FREQ_PIXEL (default IMAGE | FREQ) */
   int32_t sigma_est;    /* FITRIG_MEAN_STD (default) or FITRIG_MEDIAN_MAD */
   int32_t harm;         /* 0: eta = max magnitude (default); h >= 2: harmonic sum of h terms */
   int32_t r_signed;     /* 0: divide by |x_hat| (default); 1: by the signed x_hat (literal Eq. (4)) */
@@ -84,8 +86,8 @@ typedef struct {
 
 /* One candidate: an 8-connected component of selected cells. */
 typedef struct {
-  int32_t branch;       /* FITRIG_IMAGE or FITRIG_FREQ */
-  int32_t triple;       /* first snapshot s of the triple; -1 for FITRIG_FREQ */
+  int32_t branch;       /* FITRIG_IMAGE, FITRIG_FREQ or FITRIG_FREQ_PIXEL (in that order) */
+  int32_t triple;       /* first snapshot s of the triple; -1 for the frequency branches */
   int64_t label;        /* lowest row-major cell index y * width + x of the component */
   int32_t n_pix;        /* cells in the component (pixels, or tiles for tile mode / FREQ) */
   int32_t peak_y, peak_x; /* cell of the largest z (ties: lowest index) */
@@ -107,7 +109,7 @@ typedef struct {
   double eta_mu;        /* frequency branch: location of eta (0 if not run) */
   double eta_sigma;     /* frequency branch: spread of eta (0 if not run) */
   int64_t n_image_cand; /* candidates from the image branch */
-  int64_t n_freq_cand;  /* candidates from the frequency branch */
+  int64_t n_freq_cand;  /* candidates from the frequency branches (tile and per-pixel) */
 } fitrig_stats;
 
 typedef struct fitrig_ctx fitrig_ctx;

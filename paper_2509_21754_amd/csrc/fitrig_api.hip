@@ -53,6 +53,7 @@ struct fitrig_ctx {
   int32_t last_hip = 0;
   DevBuf stat_part, seg_max, seg_max2, tile_part, cube, cube_f, eta_d, eta_f, mu, sigma, flags, eta_st, M, qscratch;
   DevBuf fseries;  // frequency series over [history | call] (serving)
+  DevBuf etapx_d, etapx_f;  // per-pixel spectrum maxima
   DevBuf hist, rs_state, rs_med, rs_dev, rs_next, chunk_cnt, counters, mom_tmp, max_key;
   DevBuf rs_samp, rs_gbuf, rs_bkt, rs_cnt, rs_nvalid, rs_plan;
   DevBuf seg_entry, seg_mask, cell_q, parent, comp_of, c_root, c_npix, c_key, c_w, c_box, c_out;
@@ -661,6 +662,8 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   const int nfreq = ring ? (int)std::min<int64_t>(c.hist->cap, (int64_t)c.hist->n_in + np) : np;
   const bool freq = want_freq && nfreq >= 4 && nfreq <= 2048;
   const bool cube_needed = freq || ring;
+  // per-pixel frequency branch: series of sliding q held in registers
+  const bool fpx = (cfg.branches & FITRIG_FREQ_PIXEL) != 0 && cfg.mode == FITRIG_SLIDING && np >= 4 && np <= 64;
   const bool sliding = cfg.mode == FITRIG_SLIDING;
   const int tile = cfg.tile;
   const int Ty = (c.H + tile - 1) / tile, Tx = (c.W + tile - 1) / tile;
@@ -670,7 +673,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   if ((rc = ensure(ctx, ctx->mu, (size_t)np * 8)) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->sigma, (size_t)np * 8)) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->flags, (size_t)np * 4)) != FITRIG_OK) return rc;
-  if ((rc = ensure(ctx, ctx->eta_st, 32)) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->eta_st, 64)) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->M, 8)) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->max_key, 64)) != FITRIG_OK) return rc;
   int64_t* cnt = (int64_t*)ctx->counters.p;
@@ -700,7 +703,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   float* qmap = nullptr;
   const bool robust = cfg.sigma_est == FITRIG_MEDIAN_MAD;
 
-  if (img && sliding) {
+  if ((img || fpx) && sliding) {
     const int64_t nwg = (int64_t)ncol * nbands;
     if (nwg > INT32_MAX) return FITRIG_E_INVAL;
     const bool byprod = cube_needed && tile == 32;
@@ -709,7 +712,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     if (byprod && (rc = ensure(ctx, ctx->tile_part, (size_t)np * nbands * ncol * kPieces * 3 * 8)) != FITRIG_OK)
       return rc;
     qmap = c.index_map;
-    if (robust && !qmap) {
+    if ((robust || fpx) && !qmap) {
       if ((rc = ensure(ctx, ctx->qscratch, (size_t)np * plane * 4)) != FITRIG_OK) return rc;
       qmap = (float*)ctx->qscratch.p;
     }
@@ -757,11 +760,11 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
       have_cube = true;
     }
     // per-triple spread
-    if (!robust) {
+    if (img && !robust) {
       if ((rc = moments(ctx, st, (const double*)ctx->stat_part.p, np, nwg * 16, 0, plane, mu, sigma, flags)) !=
           FITRIG_OK)
         return rc;
-    } else {
+    } else if (img) {
       if ((rc = robust_spread(ctx, st, qmap, np, plane, !cfg.r_signed, mu, sigma, flags)) != FITRIG_OK) return rc;
     }
   }
@@ -937,6 +940,42 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
       HIP_TRY(ctx, hipMemcpyAsync(c.eta_map, ctx->eta_f.p, (size_t)ntiles * 4, hipMemcpyDeviceToDevice, st));
   }
 
+  // ---- per-pixel frequency branch -------------------------------------------
+  if (fpx) {
+    double* px_mu = (double*)ctx->eta_st.p + 4;
+    double* px_sig = px_mu + 1;
+    uint32_t* px_flag = (uint32_t*)(px_mu + 2);
+    if ((rc = ensure(ctx, ctx->etapx_d, (size_t)plane * 8)) != FITRIG_OK) return rc;
+    if ((rc = ensure(ctx, ctx->etapx_f, (size_t)plane * 4)) != FITRIG_OK) return rc;
+    double* ed = (double*)ctx->etapx_d.p;
+    float* ef = (float*)ctx->etapx_f.p;
+    const dim3 g(grid_for(plane, 256, 8192)), b(256);
+    const size_t lds = (size_t)2 * np * 8;
+    if (np <= 16)
+      hipLaunchKernelGGL(k_eta_px<16>, g, b, lds, st, (const float*)qmap, np, plane, cfg.harm, ed, ef);
+    else if (np <= 32)
+      hipLaunchKernelGGL(k_eta_px<32>, g, b, lds, st, (const float*)qmap, np, plane, cfg.harm, ed, ef);
+    else
+      hipLaunchKernelGGL(k_eta_px<64>, g, b, lds, st, (const float*)qmap, np, plane, cfg.harm, ed, ef);
+    LAUNCH_CHECK(ctx);
+    if (!robust) {
+      if ((rc = moments(ctx, st, (const double*)ed, 1, plane, 1, plane, px_mu, px_sig, px_flag)) != FITRIG_OK)
+        return rc;
+    } else {
+      if ((rc = robust_spread(ctx, st, (const float*)ef, 1, plane, true, px_mu, px_sig, px_flag)) != FITRIG_OK)
+        return rc;
+    }
+    SegLayout L{c.H, c.W, 1, 1, 64, (c.W + 63) / 64, 1, c.H};
+    const int64_t ne = (int64_t)c.H * L.nseg_row;
+    if ((rc = ensure(ctx, ctx->seg_max2, (size_t)ne * 4)) != FITRIG_OK) return rc;
+    float* smax = (float*)ctx->seg_max2.p;
+    hipLaunchKernelGGL(k_segmax_direct, dim3(grid_for(ne)), dim3(256), 0, st, (const float*)ef, L, smax);
+    if ((rc = ensure_selection(ctx, ne)) != FITRIG_OK) return rc;
+    if ((rc = select_run(ctx, c, L, smax, px_mu, px_sig, px_flag, FITRIG_FREQ_PIXEL, (const float*)ef, halo)) !=
+        FITRIG_OK)
+      return rc;
+  }
+
   if (c.index_map && sliding && img && cfg.map_kind == FITRIG_MAP_TLISI) {
     hipLaunchKernelGGL(k_to_tlisi, dim3(grid_for((int64_t)np * plane, 256, 8192)), dim3(256), 0, st, c.index_map,
                        (int64_t)np * plane, (const double*)ctx->M.p);
@@ -1008,7 +1047,8 @@ fitrig_status validate_cfg(const fitrig_config* c) {
   if (c->mode != FITRIG_SLIDING && c->mode != FITRIG_TILES) return FITRIG_E_INVAL;
   if (c->window < 1 || c->window % 2 == 0 || c->window > 2 * kMaxHalo + 1) return FITRIG_E_INVAL;
   if (c->tile < 1) return FITRIG_E_INVAL;
-  if (c->branches < 1 || c->branches > 3) return FITRIG_E_INVAL;
+  if (c->branches < 1 || c->branches > 7) return FITRIG_E_INVAL;
+  if ((c->branches & FITRIG_FREQ_PIXEL) && c->mode != FITRIG_SLIDING) return FITRIG_E_INVAL;
   if (c->sigma_est != FITRIG_MEAN_STD && c->sigma_est != FITRIG_MEDIAN_MAD) return FITRIG_E_INVAL;
   if (c->harm < 0 || c->harm == 1 || c->harm > 64) return FITRIG_E_INVAL;
   if (c->r_signed != 0 && c->r_signed != 1) return FITRIG_E_INVAL;
@@ -1108,7 +1148,7 @@ fitrig_status fitrig_destroy(fitrig_ctx* ctx) {
   if (!ctx) return FITRIG_E_INVAL;
   (void)hipSetDevice(ctx->cfg.device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&ctx->fseries, &ctx->mom_tmp, &ctx->max_key, &ctx->seg_max2, &ctx->stat_part, &ctx->seg_max,  &ctx->tile_part, &ctx->cube,    &ctx->cube_f,
+  DevBuf* bufs[] = {&ctx->etapx_d, &ctx->etapx_f, &ctx->fseries, &ctx->mom_tmp, &ctx->max_key, &ctx->seg_max2, &ctx->stat_part, &ctx->seg_max,  &ctx->tile_part, &ctx->cube,    &ctx->cube_f,
                     &ctx->eta_d,     &ctx->eta_f,    &ctx->mu,        &ctx->sigma,    &ctx->flags,   &ctx->eta_st,
                     &ctx->M,         &ctx->qscratch, &ctx->hist,      &ctx->rs_state, &ctx->rs_med,  &ctx->rs_dev,
                     &ctx->chunk_cnt, &ctx->counters, &ctx->seg_entry, &ctx->seg_mask, &ctx->cell_q,  &ctx->parent,
@@ -1208,6 +1248,8 @@ int64_t scratch_estimate(const fitrig_config& cfg, int n, int H, int W) {
   b += segcap * (8 + 8 + 64 * 12) + 2 * segcap * (4 + 4 + 8 + 48 + 16 + 2 * (int64_t)sizeof(fitrig_candidate));
   // median / MAD: the value map, plus the bracket gathers (about 4 % of it)
   if (cfg.sigma_est == FITRIG_MEDIAN_MAD) b += np * plane * 4 + np * plane / 2;
+  // per-pixel frequency branch: the q map and the per-pixel spectrum maxima
+  if (cfg.branches & FITRIG_FREQ_PIXEL) b += np * plane * 4 + plane * 12;
   return b;
 }
 

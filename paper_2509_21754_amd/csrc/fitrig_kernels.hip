@@ -2122,4 +2122,57 @@ __global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t
   }
 }
 
+// Per-pixel form of the frequency branch: the same transform of every
+// cell's series of sliding q over the triples (series held in registers,
+// n' <= NP), one-sided magnitudes, h = max or harmonic sum.
+template <int NP>
+__global__ __launch_bounds__(256) void k_eta_px(const float* q, int np, int64_t plane, int harm, double* eta,
+                                                float* eta_f) {
+  extern __shared__ double tw[];  // [2][np]: cos, sin of 2 pi m / np
+  for (int m = threadIdx.x; m < np; m += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)np, &sn, &cs);
+    tw[m] = cs;
+    tw[np + m] = sn;
+  }
+  __syncthreads();
+  const int K = np / 2;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < plane; p += (int64_t)gridDim.x * blockDim.x) {
+    double v[NP];
+    double mean = 0.0;
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      v[s] = s < np ? (double)q[(int64_t)s * plane + p] : 0.0;
+      if (s < np) mean += v[s];
+    }
+    mean /= (double)np;
+#pragma unroll
+    for (int s = 0; s < NP; ++s) v[s] -= mean;
+    double best = 0.0;
+    for (int k = 1; k <= K; ++k) {
+      double val = 0.0;
+      const int jmax = harm == 0 ? 1 : harm;
+      for (int j = 1; j <= jmax && j * k <= K; ++j) {
+        const int kk = j * k;
+        double re = 0.0, im = 0.0;
+        int ph = 0;
+#pragma unroll
+        for (int s = 0; s < NP; ++s) {
+          if (s < np) {
+            re = fma(v[s], tw[ph], re);
+            im = fma(-v[s], tw[np + ph], im);
+            ph += kk;
+            if (ph >= np) ph -= np;
+          }
+        }
+        val += sqrt(re * re + im * im);
+      }
+      if (k == 1 || val > best) best = val;
+    }
+    if (K < 1) best = 0.0;
+    eta[p] = best;
+    eta_f[p] = (float)best;
+  }
+}
+
 }  // namespace fitrig

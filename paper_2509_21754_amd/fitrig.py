@@ -19,7 +19,7 @@ ABI_VERSION = 2
 OK, E_INVAL, E_NOMEM, E_HIP, E_TRUNC, E_BUSY, E_NOTREADY = 0, -1, -2, -3, -4, -5, -6
 F32, F16, BF16 = 0, 1, 2
 SLIDING, TILES = 0, 1
-IMAGE, FREQ = 1, 2
+IMAGE, FREQ, FREQ_PIXEL = 1, 2, 4
 MEAN_STD, MEDIAN_MAD = 0, 1
 MAP_QTILDE, MAP_TLISI = 0, 1
 FLAG_SIGMA_ZERO, FLAG_TRUNC = 1, 2

@@ -108,6 +108,13 @@ def check_candidates(cands: list, out: dict, tau: float, *, image_values=None):
         g = [c for c in cands if c["branch"] == ref.FREQ]
         r = [c for c in out["cands"] if c["branch"] == ref.FREQ]
         nchk += check_components(g, r, out["eta"], out["eta_mu"], out["eta_sigma"], tau, where="freq")
+    if out.get("eta_px") is not None and out["eta_px_sigma"] and out["eta_px_sigma"] > 0:
+        g = [c for c in cands if c["branch"] == ref.FREQ_PIXEL]
+        r = [c for c in out["cands"] if c["branch"] == ref.FREQ_PIXEL]
+        nchk += check_components(g, r, out["eta_px"], out["eta_px_mu"], out["eta_px_sigma"], tau,
+                                 where="freq per pixel")
+    else:
+        assert not [c for c in cands if c["branch"] == ref.FREQ_PIXEL]
     return nchk
 
 

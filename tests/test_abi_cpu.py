@@ -73,7 +73,7 @@ def test_defaults():
 
 @pytest.mark.parametrize("bad", [
     dict(abi_version=F.ABI_VERSION + 1), dict(abi_version=1), dict(mode=2), dict(window=4), dict(window=0), dict(window=19), dict(tile=0),
-    dict(branches=0), dict(branches=4), dict(sigma_est=2), dict(harm=1), dict(harm=-1), dict(r_signed=2),
+    dict(branches=0), dict(branches=8), dict(branches=4, mode=1), dict(sigma_est=2), dict(harm=1), dict(harm=-1), dict(r_signed=2),
     dict(map_kind=3), dict(profile=2), dict(C=0.0), dict(C=-1.0), dict(C=float("nan")), dict(max_pixels=-1),
 ])
 def test_create_rejects_bad_config(bad):

@@ -309,3 +309,31 @@ def test_crop_interior_bitwise(w, dt):
         a = q_crop[:, h:-h, h:-h]
         b = q_full[:, oy + h:oy + 200 - h, ox + h:ox + 208 - h]
         assert a.tobytes() == b.tobytes(), (oy, ox)
+
+
+@pytest.mark.parametrize("n,H,W,window,branches,dtype,sigma_est,harm,with_maps", [
+    (12, 48, 300, 5, 7, "f32", 0, 0, True),     # n' = 10, all three branches
+    (34, 40, 260, 3, 4, "f32", 0, 0, False),    # n' = 32, per-pixel branch alone
+    (66, 30, 130, 5, 5, "f32", 1, 3, False),    # n' = 64, median/MAD, harmonic sum
+    (22, 37, 250, 7, 6, "f16", 0, 0, True),     # FP16 storage
+    (67, 20, 70, 3, 5, "f32", 0, 0, False),     # n' = 65: the per-pixel branch does not run
+])
+def test_per_pixel_frequency_branch(n, H, W, window, branches, dtype, sigma_est, harm, with_maps):
+    rng = np.random.default_rng(n * 7 + H)
+    X = structured_stack(n + H, n, H, W)
+    y0, x0 = int(rng.integers(5, H - 8)), int(rng.integers(5, W - 8))
+    X[1::5, y0:y0 + 3, x0:x0 + 3] += 9.0
+    tau = 4.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, dtype=dtype, with_maps=with_maps, window=window,
+                                             branches=branches, sigma_est=sigma_est, harm=harm, tile=16)
+    assert rc == 0
+    out = ref.detect(used, tau=tau, window=window, branches=branches, sigma_est=sigma_est, harm=harm, tile=16,
+                     keep_maps=True)
+    if with_maps and branches & ref.IMAGE:
+        check_maps(q, out["q"])
+    check_candidates(cands, out, tau)
+    px = [c for c in cands if c["branch"] == ref.FREQ_PIXEL]
+    if out["eta_px"] is None:
+        assert not px
+    else:
+        assert px and all(c["triple"] == -1 for c in px)
