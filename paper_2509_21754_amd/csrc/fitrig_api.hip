@@ -950,7 +950,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
     double* ed = (double*)ctx->etapx_d.p;
     float* ef = (float*)ctx->etapx_f.p;
     const dim3 g(grid_for(plane, 256, 8192)), b(256);
-    const size_t lds = (size_t)2 * np * 8;
+    const size_t lds = (size_t)(np / 2) * np * 16;  // at most 32 KB (n' <= 64)
     if (np <= 16)
       hipLaunchKernelGGL(k_eta_px<16>, g, b, lds, st, (const float*)qmap, np, plane, cfg.harm, ed, ef);
     else if (np <= 32)

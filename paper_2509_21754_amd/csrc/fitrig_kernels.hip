@@ -2124,19 +2124,22 @@ __global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t
 
 // Per-pixel form of the frequency branch: the same transform of every
 // cell's series of sliding q over the triples (series held in registers,
-// n' <= NP), one-sided magnitudes, h = max or harmonic sum.
+// n' <= NP), one-sided magnitudes, h = max or harmonic sum. The twiddles of
+// each frequency are tabulated in LDS in the order the sum runs (k, s), so
+// one 16-byte broadcast read serves the two multiply-adds of a term.
 template <int NP>
 __global__ __launch_bounds__(256) void k_eta_px(const float* q, int np, int64_t plane, int harm, double* eta,
                                                 float* eta_f) {
-  extern __shared__ double tw[];  // [2][np]: cos, sin of 2 pi m / np
-  for (int m = threadIdx.x; m < np; m += blockDim.x) {
+  extern __shared__ double2 tw2[];  // [K][np]: (cos, sin) of 2 pi k s / np, k = 1..K
+  const int K = np / 2;
+  for (int i = threadIdx.x; i < K * np; i += blockDim.x) {
+    const int k = i / np + 1, s = i - (k - 1) * np;
+    const int m = (int)(((int64_t)k * s) % np);
     double sn, cs;
     sincospi(2.0 * (double)m / (double)np, &sn, &cs);
-    tw[m] = cs;
-    tw[np + m] = sn;
+    tw2[i] = make_double2(cs, sn);
   }
   __syncthreads();
-  const int K = np / 2;
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < plane; p += (int64_t)gridDim.x * blockDim.x) {
     double v[NP];
     double mean = 0.0;
@@ -2153,16 +2156,14 @@ __global__ __launch_bounds__(256) void k_eta_px(const float* q, int np, int64_t 
       double val = 0.0;
       const int jmax = harm == 0 ? 1 : harm;
       for (int j = 1; j <= jmax && j * k <= K; ++j) {
-        const int kk = j * k;
+        const double2* t = tw2 + (j * k - 1) * np;
         double re = 0.0, im = 0.0;
-        int ph = 0;
 #pragma unroll
         for (int s = 0; s < NP; ++s) {
           if (s < np) {
-            re = fma(v[s], tw[ph], re);
-            im = fma(-v[s], tw[np + ph], im);
-            ph += kk;
-            if (ph >= np) ph -= np;
+            const double2 w = t[s];
+            re = fma(v[s], w.x, re);
+            im = fma(-v[s], w.y, im);
           }
         }
         val += sqrt(re * re + im * im);
