@@ -2152,7 +2152,29 @@ __global__ __launch_bounds__(256) void k_eta_px(const float* q, int np, int64_t 
 #pragma unroll
     for (int s = 0; s < NP; ++s) v[s] -= mean;
     double best = 0.0;
-    for (int k = 1; k <= K; ++k) {
+    int k0 = 1;
+    if (harm == 0) {
+      // h = max: two frequencies per pass over s (four independent chains)
+      for (; k0 + 1 <= K; k0 += 2) {
+        const double2* t0 = tw2 + (k0 - 1) * np;
+        const double2* t1 = t0 + np;
+        double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+#pragma unroll
+        for (int s = 0; s < NP; ++s) {
+          if (s < np) {
+            const double2 w0 = t0[s], w1 = t1[s];
+            re0 = fma(v[s], w0.x, re0);
+            im0 = fma(-v[s], w0.y, im0);
+            re1 = fma(v[s], w1.x, re1);
+            im1 = fma(-v[s], w1.y, im1);
+          }
+        }
+        const double a0 = sqrt(re0 * re0 + im0 * im0), a1 = sqrt(re1 * re1 + im1 * im1);
+        if (k0 == 1 || a0 > best) best = a0;
+        if (a1 > best) best = a1;
+      }
+    }
+    for (int k = k0; k <= K; ++k) {
       double val = 0.0;
       const int jmax = harm == 0 ? 1 : harm;
       for (int j = 1; j <= jmax && j * k <= K; ++j) {
