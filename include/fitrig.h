@@ -240,7 +240,9 @@ typedef struct {
                            freq_window triples (FP64 tile cube kept per field,
                            freq_window * ceil(H/tile) * ceil(W/tile) * 8 bytes,
                            counted in mem_budget). The branch runs once the
-                           covered series has at least 4 triples. */
+                           covered series has at least 4 triples. The
+                           per-pixel branch (FITRIG_FREQ_PIXEL) always covers
+                           the request's own triples. */
 } fitrig_server_config;
 
 typedef struct {
