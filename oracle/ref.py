@@ -244,11 +244,11 @@ def detect(stack, *, tau: float = 6.0, mode: int = SLIDING, window: int = 7,
             for c in components(e, mu, sig, tau):
                 c.update(branch=FREQ, triple=-1)
                 out["cands"].append(c)
-    # per-pixel form: the spectrum of every cell's series of sliding q
-    # (register-resident series on the GPU: 4 <= n' <= 64)
+    # per-pixel form: the spectrum of every cell's series of sliding q, for
+    # every series length the tile branch accepts (n' >= 4)
     out["eta_px"] = None
     out["eta_px_mu"] = out["eta_px_sigma"] = None
-    if (branches & FREQ_PIXEL) and mode == SLIDING and 4 <= n - 2 <= 64:
+    if (branches & FREQ_PIXEL) and mode == SLIDING and n - 2 >= 4:
         qp = q if q is not None else index_maps(X, mode=SLIDING, window=window, tile=tile, r_signed=r_signed, C=C)
         e = eta(qp, harm)
         mu, sig = spread(e, sigma_est)

@@ -184,7 +184,7 @@ def test_tile_mode_matches_block_reduction(shape, t):
 
 def test_eta_matches_numpy_rfft():
     rng = np.random.default_rng(3)
-    for npr in (4, 5, 14, 30, 31, 62):
+    for npr in (4, 5, 14, 30, 31, 62, 65, 126, 127, 130):
         cube = rng.normal(size=(npr, 3, 4)) + 5.0
         e = ref.eta(cube, 0)
         v = cube - cube.mean(0, keepdims=True)
@@ -366,5 +366,24 @@ def test_per_pixel_frequency_branch_finds_a_periodic_pixel_source():
     assert c and all(c_["triple"] == -1 for c_ in c)
     best = max(c, key=lambda c_: c_["peak_z"])
     assert 18 <= best["peak_y"] <= 24 and 28 <= best["peak_x"] <= 34
-    # outside 4 <= n' <= 64 the branch does not run
+    # fewer than four triples: the branch does not run (as the tile branch)
     assert ref.detect(X[:5], tau=6.0, window=3, branches=ref.FREQ_PIXEL)["eta_px"] is None
+
+
+@pytest.mark.parametrize("n", [6, 67, 128])
+def test_per_pixel_spectrum_matches_numpy_rfft_any_length(n):
+    """The per-pixel eta is the one-sided magnitude maximum of the DFT of each
+    cell's mean-removed q series (Eq. (10) applied per cell), for every series
+    length, including lengths past 64 and odd ones: pinned to numpy's FFT of
+    the oracle's own q maps."""
+    rng = np.random.default_rng(n)
+    X = rng.normal(size=(n, 9, 13)) + 4.0
+    X[2::5, 3:6, 4:8] += 5.0
+    out = ref.detect(X, tau=3.0, window=3, branches=ref.IMAGE | ref.FREQ_PIXEL)
+    q = out["q"]
+    v = q - q.mean(0, keepdims=True)
+    A = np.abs(np.fft.rfft(v, axis=0))[1:(n - 2) // 2 + 1]
+    np.testing.assert_allclose(out["eta_px"], A.max(0), rtol=1e-10)
+    mu, sig = A.max(0).mean(), A.max(0).std()
+    assert out["eta_px_mu"] == pytest.approx(mu, rel=1e-10)
+    assert out["eta_px_sigma"] == pytest.approx(sig, rel=1e-10)
