@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define FITRIG_ABI_VERSION 2
+#define FITRIG_ABI_VERSION 3
 
 typedef int32_t fitrig_status;
 #define FITRIG_OK 0
@@ -55,7 +55,8 @@ typedef enum { FITRIG_F32 = 0, FITRIG_F16 = 1, FITRIG_BF16 = 2 } fitrig_dtype;
 #define FITRIG_IMAGE 1        /* image-domain selection, Sec. 2.4.1 */
 #define FITRIG_FREQ 2         /* image-frequency selection, Sec. 2.4.2 (needs n_snap - 2 >= 4) */
 #define FITRIG_FREQ_PIXEL 4   /* the same transform and selection per cell of the sliding index maps
-                                 (sliding mode only; runs for 4 <= n_snap - 2 <= 64) */
+                                 (sliding mode only; needs n_snap - 2 >= 4; n_snap - 2 <= 4096,
+                                 or <= 448 with a harmonic sum) */
 /* spread estimator */
 #define FITRIG_MEAN_STD 0     /* mean and population std (Eq. (8)) */
 #define FITRIG_MEDIAN_MAD 1   /* median and 1.482602218505602 * MAD */
@@ -102,14 +103,22 @@ typedef struct {
 typedef struct {
   double M;             /* max(max over the stack, C) */
   int32_t n_triples;    /* out: n_snap - 2 */
-  int32_t pad0;
+  int32_t status;       /* out: the call's result, FITRIG_OK or FITRIG_E_TRUNC (for an
+                           asynchronous call this is where truncation shows) */
   double* mu;           /* in: array of >= n_snap - 2, out: per-triple location of q (nullable) */
   double* sigma;        /* in: array of >= n_snap - 2, out: per-triple spread of q (nullable) */
   uint32_t* flags;      /* in: array of >= n_snap - 2, out: FITRIG_FLAG_* (nullable) */
-  double eta_mu;        /* frequency branch: location of eta (0 if not run) */
-  double eta_sigma;     /* frequency branch: spread of eta (0 if not run) */
+  double eta_mu;        /* tile frequency branch: location of eta (0 if not run) */
+  double eta_sigma;     /* tile frequency branch: spread of eta (0 if not run) */
   int64_t n_image_cand; /* candidates from the image branch */
-  int64_t n_freq_cand;  /* candidates from the frequency branches (tile and per-pixel) */
+  int64_t n_freq_cand;  /* candidates from the tile frequency branch */
+  int64_t n_freq_px_cand; /* candidates from the per-pixel frequency branch */
+  double eta_px_mu;     /* per-pixel frequency branch: location of eta (0 if not run) */
+  double eta_px_sigma;  /* per-pixel frequency branch: spread of eta (0 if not run) */
+  uint32_t ran;         /* out: the branches that ran (FITRIG_IMAGE | FITRIG_FREQ | FITRIG_FREQ_PIXEL);
+                           a requested frequency branch does not run when n_snap - 2 < 4 */
+  uint32_t eta_flags;   /* out: FITRIG_FLAG_SIGMA_ZERO of the tile branch (bit 0) and of the
+                           per-pixel branch (bit 8) */
 } fitrig_stats;
 
 typedef struct fitrig_ctx fitrig_ctx;
@@ -128,33 +137,52 @@ fitrig_status fitrig_create(const fitrig_config* cfg, fitrig_ctx** out);
 /*
  * Runs the whole path on one stack.
  *   stack      device, [n_snap][H][W] row-major, dtype as given, read only
- *   n_snap     >= 3 (the frequency branch runs only when n_snap - 2 >= 4)
- *   H, W       >= 1, H * W < 2^32
+ *   n_snap     >= 3 (the frequency branches run only when n_snap - 2 >= 4)
+ *   H, W       >= 1, H * W < 2^32, W * (bytes per pixel) * (17 + window) < 2^30
  *   sigma      the threshold tau of Eqs. (9), (12); finite and > 0
  *   cand       host, cand_cap records (nullable when cand_cap == 0)
  *   n_cand     host, out: total number of candidates (always written)
  *   index_map  device, nullable: [n_snap-2][H][W] floats (sliding) or
- *              [n_snap-2][ceil(H/tile)][ceil(W/tile)] (tiles)
- *   eta_map    device, nullable: [ceil(H/tile)][ceil(W/tile)] floats
+ *              [n_snap-2][ceil(H/tile)][ceil(W/tile)] (tiles); written
+ *              whenever given, whichever branches run
+ *   eta_map    device, nullable: [ceil(H/tile)][ceil(W/tile)] floats (tile
+ *              frequency branch)
+ *   eta_px_map device, nullable: [H][W] floats, the per-pixel spectrum
+ *              eta of every cell (FITRIG_FREQ_PIXEL)
  *   stats      host, nullable
- *   hip_stream hipStream_t to run on; NULL = the context's stream, which
- *              is a blocking stream: it starts after work queued earlier on
- *              the legacy default stream (where the stack may have been
- *              written) without further synchronisation by the caller
+ *   hip_stream NULL: the call runs on the context's stream (a blocking
+ *              stream: it starts after work queued earlier on the legacy
+ *              default stream, where the stack may have been written) and
+ *              returns when every output is written.
+ *              Non-NULL, a hipStream_t: the call is asynchronous. It
+ *              enqueues the whole path on that stream and returns; the
+ *              device maps, cand, *n_cand and *stats (and the arrays stats
+ *              points to) are written when the stream reaches the end of
+ *              the call (the host outputs by a host function the call
+ *              enqueues), so the caller keeps them alive and reads them
+ *              after synchronising the stream. Such a call may be captured
+ *              into a HIP graph; every replay rewrites the same outputs.
  * Candidates come in canonical order: image branch by (triple, label), then
- * the frequency branch by label. The call returns when every output is
- * written. Scratch grows (hipMalloc) when a stack exceeds the capacity
- * hints; with adequate hints a call allocates nothing.
- * Errors: E_INVAL (argument outside the ranges above, unknown dtype),
- * E_TRUNC (more candidates than cand_cap: the first cand_cap are written
- * and *n_cand holds the total; or the internal selection capacity was
- * exceeded, flagged FITRIG_FLAG_TRUNC), E_NOMEM, E_HIP.
+ * the tile frequency branch by label, then the per-pixel frequency branch by
+ * label. Scratch is sized from the capacity hints at create; a call that
+ * needs more grows it before enqueueing anything (a device-wide
+ * synchronisation), except on a capturing stream, where it returns E_INVAL
+ * instead. With adequate hints a call allocates nothing. Calls on one
+ * context must be ordered: one stream per context, or the caller orders them.
+ * Returns (synchronous call): OK, or E_TRUNC (more candidates than cand_cap:
+ * the first cand_cap are written and *n_cand holds the total; or the
+ * internal selection capacity was exceeded, flagged FITRIG_FLAG_TRUNC).
+ * An asynchronous call returns OK once enqueued; the result status then
+ * appears in stats->status (and *n_cand > cand_cap shows truncation).
+ * Errors: E_INVAL (argument outside the ranges above, unknown dtype, a
+ * per-pixel series longer than the FITRIG_FREQ_PIXEL limits, scratch growth
+ * while capturing), E_NOMEM, E_HIP.
  */
 fitrig_status fitrig_detect(fitrig_ctx* ctx, const void* stack, fitrig_dtype dtype,
                             int32_t n_snap, int32_t H, int32_t W, double sigma,
                             fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand,
-                            float* index_map, float* eta_map, fitrig_stats* stats,
-                            void* hip_stream);
+                            float* index_map, float* eta_map, float* eta_px_map,
+                            fitrig_stats* stats, void* hip_stream);
 
 /* Releases the context and its device memory. Errors: E_INVAL (null). */
 fitrig_status fitrig_destroy(fitrig_ctx* ctx);
@@ -167,14 +195,16 @@ int32_t fitrig_last_hip_error(const fitrig_ctx* ctx);
 
 /*
  * Phase durations of the last fitrig_detect on ctx, in milliseconds, measured
- * with HIP events recorded on the call's stream (config profile = 1):
+ * with HIP events recorded on the call's stream (config profile = 1; not
+ * recorded while the stream is capturing):
  *   [0] pass over the stack (streaming index kernel or tile kernel)
  *   [1] per-triple spread
  *   [2] image-branch selection and components
  *   [3] frequency branch
  *   [4] result copies to the host
  * Writes min(cap, FITRIG_N_PHASES) values; returns the number written, or
- * 0 when profiling is off or no call has completed, -1 on a null pointer.
+ * 0 when profiling is off or the last call has not completed, -1 on a null
+ * pointer.
  */
 #define FITRIG_N_PHASES 5
 int32_t fitrig_phase_times(const fitrig_ctx* ctx, double* ms, int32_t cap);

@@ -19,11 +19,22 @@ constexpr int kHistBins = 2048;      // radix-select digit bins (11 bits)
 // also cover the halo of up to 8 columns on each side).
 inline int out_width(int /*halo*/) { return kLanes - 16; }
 
-// Streaming index kernel arguments (one launch covers every triple).
-struct StreamArgs {
+// Values of one call that change between calls of the same shape. The
+// kernels read them from device memory (written by a one-thread kernel at the
+// start of each call), so a recorded launch sequence (a HIP graph) serves
+// every call of its shape once this record is rewritten.
+struct CallDev {
   const void* base;      // first frame of the new stack
   const void* carry0;    // frames carried in front of the stack (serving), nullable
   const void* carry1;
+  const double* hist_in; // serving: frequency history [n_in][Ty][Tx] (nullable)
+  double* hist_out;      // serving: receives the covered slices (nullable)
+  double tau;            // threshold of Eqs. (9), (12)
+};
+
+// Streaming index kernel arguments (one launch covers every triple).
+struct StreamArgs {
+  const CallDev* cd;     // frame pointers
   int32_t ncarry;
   int32_t n;             // total frames seen by the kernel = ncarry + new frames
   int64_t plane;         // H * W
@@ -41,9 +52,7 @@ struct StreamArgs {
 
 // Generic tile-mode kernel arguments (re-reads the three frames of a triple).
 struct TileArgs {
-  const void* base;
-  const void* carry0;
-  const void* carry1;
+  const CallDev* cd;
   int32_t ncarry;
   int32_t n;
   int64_t plane;
@@ -61,9 +70,7 @@ struct TileArgs {
 // workgroup per band of whole tile rows and chunk of 256 columns, every frame
 // read once.
 struct TileStreamArgs {
-  const void* base;
-  const void* carry0;
-  const void* carry1;
+  const CallDev* cd;
   int32_t ncarry;
   int32_t n;
   int64_t plane;
@@ -103,26 +110,75 @@ __host__ __device__ inline int seg_of_x(const SegLayout& L, int x) {
   return (x / L.gw) * L.spg + (x % L.gw) / 64;
 }
 
-// Device-side scratch used by a selection pipeline run.
-struct SelBuffers {
-  int64_t seg_cap;       // capacity in segments
-  int64_t comp_cap;      // capacity in components
-  int64_t* seg_entry;    // [seg_cap] entry index (set * Ho * nseg_row + y * nseg_row + g)
-  uint64_t* seg_mask;    // [seg_cap]
-  float* cell_q;         // [seg_cap * 64]
-  int32_t* parent;       // [seg_cap * 64]
-  int32_t* comp_of;      // [seg_cap * 64]
-  uint32_t* chunk_cnt;   // scan workspace
-  int64_t chunk_cap;
-  int64_t* counters;     // [0]=segments selected, [1]=components, [2]=trunc flag, [3]=comps written
-  // component accumulators [comp_cap]
-  int32_t* c_root;
-  int32_t* c_npix;
-  unsigned long long* c_key;
-  unsigned long long* c_w;     // 128-bit pairs: w, w*y, w*x -> 6 per component
-  int32_t* c_box;              // 4 per component
-  void* c_out;                 // fitrig_candidate[comp_cap]
+// Arguments of the exact recompute of selected segments (sliding mode).
+struct RecomputeArgs {
+  const CallDev* cd;
+  int32_t ncarry;
+  int64_t plane;
+  int32_t H, W;
+  float Cf;
+  SegLayout L;
+  const int64_t* seg_entry;
+  const int64_t* nsel;   // segments selected (device)
+  int64_t cap;
+  const double* mu;
+  const double* sigma;
+  uint64_t* mask;
+  float* cell_q;
 };
+
+// Device counters of one call.
+enum {
+  CNT_NSEL = 0,    // segments selected in the current selection run
+  CNT_NCOMP = 1,   // components of the current run
+  CNT_OUTBASE = 3, // candidates written so far
+  CNT_TRUNC = 5,   // internal capacity exceeded
+  CNT_IMG = 6,     // image-branch candidates
+  CNT_FREQ = 7,    // tile frequency-branch candidates
+  CNT_NBLK = 8,    // selection blocks flagged in the current run
+  CNT_FPX = 9,     // per-pixel frequency-branch candidates
+  CNT_N = 10
+};
+
+// Frequency-branch statistics of one call (doubles; the last one holds two
+// uint32 flag words: tile branch, per-pixel branch).
+enum { ES_MU = 0, ES_SIG = 1, ES_PXMU = 2, ES_PXSIG = 3, ES_FLAGS = 4, ES_N = 5 };
+
+// Byte offsets of a call's results in host-visible memory.
+struct ResultLayout {
+  int64_t off_cnt;      // int64[CNT_N]
+  int64_t off_scalars;  // double M, then the ES_N words of the frequency statistics
+  int64_t off_mu;       // double[n']
+  int64_t off_sigma;    // double[n']
+  int64_t off_flags;    // uint32[n']
+  int64_t off_cand;     // fitrig_candidate[cap]
+  int64_t bytes;
+};
+
+// Host launchers of the kernels templated on the storage type, one
+// translation unit per type (dtype: 0 FP32, 1 FP16, 2 BF16). Each returns
+// false, launching nothing, when no instantiation covers the arguments.
+bool launch_stream(int dtype, int halo, bool r_signed, dim3 grid, hipStream_t st, const StreamArgs& A);
+bool launch_tile_stream(int dtype, int tile, bool r_signed, dim3 grid, hipStream_t st, const TileStreamArgs& A);
+bool launch_tile(int dtype, bool r_signed, dim3 grid, hipStream_t st, const TileArgs& A);
+bool launch_recompute(int dtype, int halo, bool r_signed, dim3 grid, hipStream_t st, const RecomputeArgs& R);
+bool launch_stack_max(int dtype, dim3 grid, hipStream_t st, const CallDev* cd, int64_t n, uint32_t* max_key);
+bool launch_stream_f32(int halo, bool r_signed, dim3 grid, hipStream_t st, const StreamArgs& A);
+bool launch_stream_f16(int halo, bool r_signed, dim3 grid, hipStream_t st, const StreamArgs& A);
+bool launch_stream_bf16(int halo, bool r_signed, dim3 grid, hipStream_t st, const StreamArgs& A);
+bool launch_tile_stream_f32(int tile, bool r_signed, dim3 grid, hipStream_t st, const TileStreamArgs& A);
+bool launch_tile_stream_f16(int tile, bool r_signed, dim3 grid, hipStream_t st, const TileStreamArgs& A);
+bool launch_tile_stream_bf16(int tile, bool r_signed, dim3 grid, hipStream_t st, const TileStreamArgs& A);
+bool launch_tile_f32(bool r_signed, dim3 grid, hipStream_t st, const TileArgs& A);
+bool launch_tile_f16(bool r_signed, dim3 grid, hipStream_t st, const TileArgs& A);
+bool launch_tile_bf16(bool r_signed, dim3 grid, hipStream_t st, const TileArgs& A);
+bool launch_recompute_f32(int halo, bool r_signed, dim3 grid, hipStream_t st, const RecomputeArgs& R);
+bool launch_recompute_f16(int halo, bool r_signed, dim3 grid, hipStream_t st, const RecomputeArgs& R);
+bool launch_recompute_bf16(int halo, bool r_signed, dim3 grid, hipStream_t st, const RecomputeArgs& R);
+bool launch_stack_max_f32(dim3 grid, hipStream_t st, const CallDev* cd, int64_t n, uint32_t* max_key);
+bool launch_stack_max_f16(dim3 grid, hipStream_t st, const CallDev* cd, int64_t n, uint32_t* max_key);
+bool launch_stack_max_bf16(dim3 grid, hipStream_t st, const CallDev* cd, int64_t n, uint32_t* max_key);
+
 
 }  // namespace fitrig
 

@@ -1,829 +1,15 @@
-// FITrig device code for CDNA4 (gfx950): streaming index kernel, tile-mode
-// kernel, statistics, exact selection by recompute, union-find components,
-// image-frequency transform and radix selection for the robust spread.
+// FITrig device code that does not depend on the storage type: tile-cube
+// merge, statistics, radix selection for the robust spread, the selection
+// pipeline (segment flags, compaction, union-find components), the
+// image-frequency transforms and result delivery. Included by the host
+// runtime (fitrig_api.hip), which launches these kernels.
 //
 // Method (Li, Adamek & Armour, arXiv 2509.21754):
-//   Delta = ||x(s+2)-x(s+1)| - |x(s+1)-x(s)||, reference x(s+1)  Sec. 2.2.4, Eqs. (3)-(5)
-//   r = min(Delta / |x_hat|, 1), x_hat = C where x(s+1) == 0       Eqs. (4)-(5)
-//   q = mean(Delta) max(Delta) mean(r) over the window / tile       Eq. (2), Eq. (6)
 //   z = (q - mean q) / std q per triple, select z > tau             Sec. 2.4.1, Eqs. (8)-(9)
-//   eta = h(|DFT_s[q(s) - mean q]|) per tile, z on eta               Sec. 2.4.2, Eqs. (10)-(12)
-//
-// Window sums use 8-row / 8-column blocks aligned to absolute multiples of
-// 8: a window [L, R] is suffix(block of L) + totals of whole blocks +
-// prefix(block of R), with prefix / suffix defined by fixed left-to-right /
-// right-to-left recurrences. The value of a cell therefore depends only on
-// its absolute position, so the exact selection kernel recomputes it to the
-// same bits as the streaming kernel.
-#include <hip/hip_fp16.h>
-#include <math.h>
-#include <stdint.h>
-
-#include "fitrig.h"
-#include "fitrig_internal.h"
+//   eta = h(|DFT_s[q(s) - mean q]|) per tile or pixel, z on eta      Sec. 2.4.2, Eqs. (10)-(12)
+#include "fitrig_device.h"
 
 namespace fitrig {
-
-struct bf16_t {
-  uint16_t v;
-};
-
-template <typename T>
-__device__ __forceinline__ float to_f(T v);
-template <>
-__device__ __forceinline__ float to_f<float>(float v) {
-  return v;
-}
-template <>
-__device__ __forceinline__ float to_f<__half>(__half v) {
-  return __half2float(v);
-}
-template <>
-__device__ __forceinline__ float to_f<bf16_t>(bf16_t v) {
-  return __uint_as_float(((uint32_t)v.v) << 16);
-}
-
-template <typename T>
-__device__ __forceinline__ const T* frame_ptr(const void* base, const void* c0, const void* c1,
-                                              int ncarry, int64_t plane, int k) {
-  if (k < ncarry) return (const T*)(k == 0 ? c0 : c1);
-  return (const T*)base + (int64_t)(k - ncarry) * plane;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous run of logical tiles so neighbours share halo lines in its L2.
-__device__ __forceinline__ int xcd_remap(int bid, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int xcd = bid & 7, k = bid >> 3;
-  return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
-}
-
-// Order of the streaming kernel's (band, group) tiles along one XCD's run of
-// workgroups: blocks of bb bands, group by group. With bb = 8 the workgroups
-// resident on an XCD at a time cover about 8 bands x 8 groups, so the halo
-// rows they share are fetched once into its L2; bb = 1 is row order.
-__device__ __forceinline__ void tile_of(int t, int nbands, int ncol, int bb_size, int& band, int& grp) {
-  const int per = bb_size * ncol;
-  const int bb = t / per;
-  const int rem = nbands - bb * bb_size;
-  const int hb = rem < bb_size ? rem : bb_size;
-  const int u = t - bb * per;
-  grp = u / hb;
-  band = bb * bb_size + (u - grp * hb);
-}
-
-// Order-preserving map of a float to uint32 (and back).
-__device__ __forceinline__ uint32_t ord_key(float v) {
-  const uint32_t u = __float_as_uint(v);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float ord_val(uint32_t k) {
-  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
-}
-
-constexpr int fdiv8(int a) { return a >= 0 ? a / 8 : -((-a + 7) / 8); }
-
-// Window reduction over a register array.
-//   a[i] holds the value at relative position P = i - H (P in [-H, NOUT+H-1]),
-//   the base position (P = 0) being a multiple of 8 in absolute coordinates.
-//   o[c] = op over positions [c-H, c+H]; tot[j] = prefix of block j at 7
-//   (sum / max of the 8 positions [8j, 8j+7]).
-template <int H, int NOUT, bool MAXOP>
-struct Win {
-  static constexpr int NIN = NOUT + 2 * H;
-  static constexpr int MLO = -1;
-  static constexpr int MHI = fdiv8(NOUT - 1 + H);
-  static constexpr int NB = MHI - MLO + 1;
-  __device__ static __forceinline__ float op(float x, float y) { return MAXOP ? fmaxf(x, y) : x + y; }
-
-  __device__ static __forceinline__ void run(const float* a, float* o, float* tot) {
-    if constexpr (H <= 2) {
-#pragma unroll
-      for (int c = 0; c < NOUT; ++c) {
-        float s = a[c];
-#pragma unroll
-        for (int j = 1; j <= 2 * H; ++j) s = op(s, a[c + j]);
-        o[c] = s;
-      }
-      if (tot) {
-#pragma unroll
-        for (int j = 0; j < NOUT / 8; ++j) {
-          float s = a[H + 8 * j];
-#pragma unroll
-          for (int p = 1; p < 8; ++p) s = op(s, a[H + 8 * j + p]);
-          tot[j] = s;
-        }
-      }
-    } else {
-      float pre[NB][8] = {};
-      float suf[NB][8] = {};
-#pragma unroll
-      for (int mi = 0; mi < NB; ++mi) {
-        const int m = mi + MLO;
-        const int st = H + 8 * m;
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-          const int idx = st + p;
-          if (st >= 0 && idx < NIN) pre[mi][p] = (p == 0) ? a[idx] : op(pre[mi][p - 1], a[idx]);
-        }
-#pragma unroll
-        for (int p = 7; p >= 0; --p) {
-          const int idx = st + p;
-          if (st + 7 < NIN && idx >= 0) suf[mi][p] = (p == 7) ? a[idx] : op(a[idx], suf[mi][p + 1]);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < NOUT; ++c) {
-        const int L = c - H, R = c + H;
-        const int bs = fdiv8(L), be = fdiv8(R);
-        const int ps = L - 8 * bs, pe = R - 8 * be;
-        if (bs == be) {
-          o[c] = (ps == 0) ? pre[bs - MLO][pe] : suf[bs - MLO][ps];
-        } else {
-          float s = suf[bs - MLO][ps];
-#pragma unroll
-          for (int m = bs + 1; m < be; ++m) s = op(s, pre[m - MLO][7]);
-          o[c] = op(s, pre[be - MLO][pe]);
-        }
-      }
-      if (tot) {
-#pragma unroll
-        for (int j = 0; j < NOUT / 8; ++j) tot[j] = pre[j - MLO][7];
-      }
-    }
-  }
-};
-
-// Maximum over each aligned group of 8 lanes (DPP quad xor 1, xor 2, half-row mirror).
-__device__ __forceinline__ float group8_max(float v) {
-  float t = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-  v = fmaxf(v, t);
-  t = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
-  v = fmaxf(v, t);
-  t = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
-  return fmaxf(v, t);
-}
-
-// Sum over the 64 lanes of a wave with DPP (quad swaps, half-row and row
-// mirrors, row broadcasts); the total ends in lane 63. Fixed order.
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const uint64_t u = __double_as_longlong(v);
-  int lo, hi;
-  if constexpr (ROWMASK == 0xF) {
-    lo = __builtin_amdgcn_mov_dpp((int)(u & 0xFFFFFFFFu), CTRL, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
-  } else {
-    lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xFFFFFFFFu), CTRL, ROWMASK, 0xF, false);
-    hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROWMASK, 0xF, false);
-  }
-  return __longlong_as_double(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-// Sum over each row of 16 lanes (every lane of the row ends with it).
-__device__ __forceinline__ double row_sum_f64(double v) {
-  v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
-  v += dpp_f64<0x140, 0xF>(v);  // row_mirror
-  return v;
-}
-__device__ __forceinline__ double wave_sum_f64(double v) {
-  v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
-  v += dpp_f64<0x140, 0xF>(v);  // row_mirror
-  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  return v;
-}
-
-// Pointwise terms of one pixel: Delta from the two frame differences, r from
-// the reference pixel (Eqs. (3)-(5)). RS selects the literal signed reading
-// of Eq. (4); otherwise the ratio uses |x_hat| and is clamped to [0, 1].
-template <bool RS>
-__device__ __forceinline__ void pix_ratio(float dl, float ref, float Cf, float& rl) {
-  const float den = (ref == 0.0f) ? Cf : ref;
-  if constexpr (RS) {
-    rl = fminf(dl * __builtin_amdgcn_rcpf(den), 1.0f);
-  } else {
-    // dl >= 0 and den != 0, so the product is finite and >= 0 and min(., 1)
-    // is the [0, 1] clamp, which folds into the multiply
-    rl = __builtin_amdgcn_fmed3f(dl * __builtin_amdgcn_rcpf(fabsf(den)), 0.0f, 1.0f);
-  }
-}
-
-template <bool RS>
-__device__ __forceinline__ void pix_terms(float d_new, float d_old, float ref, float Cf, float& dl, float& rl) {
-  dl = fabsf(fabsf(d_new) - fabsf(d_old));
-  pix_ratio<RS>(dl, ref, Cf, rl);
-}
-
-// Same terms, Delta returned signed: Delta = |dd| (the absolute value is
-// applied where it is consumed, as a source modifier).
-template <bool RS>
-__device__ __forceinline__ void pix_terms_signed(float d_new, float d_old, float ref, float Cf, float& dd,
-                                                 float& rl) {
-  dd = fabsf(d_new) - fabsf(d_old);
-  pix_ratio<RS>(fabsf(dd), ref, Cf, rl);
-}
-
-// 1 / n^2 for a window of n in-image cells (n = rows * cols).
-__device__ __forceinline__ float inv_count2(int y, int x, int H, int Hh, int Wh) {
-  const int cy = min(y + H, Hh - 1) - max(y - H, 0) + 1;
-  const int cx = min(x + H, Wh - 1) - max(x - H, 0) + 1;
-  const int nn = cy * cx;
-  return 1.0f / (float)(nn * nn);
-}
-
-// Window maximum by max3 tripling: t3[j] = max(a[j..j+2]), then each window
-// of 2H+1 values is the max3 of at most three t3 terms (plus singles). The
-// inputs are non-negative finite floats (Delta and its window maxima), whose
-// bit patterns order like unsigned integers, so the maxima run on the bits
-// (exact, no NaN canonicalisation) and agree with every other evaluation.
-__device__ __forceinline__ uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) {
-  // one v_max3_u32 (common-subexpression elimination would otherwise split
-  // overlapping triples back into two-operand maxima)
-  uint32_t r;
-  asm("v_max3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-  return r;
-}
-
-template <int H, int NOUT>
-struct WinMax {
-  static constexpr int L = 2 * H + 1;
-  static constexpr int NIN = NOUT + 2 * H;
-  __device__ static __forceinline__ void run(const float* af, float* o) {
-    if constexpr (L == 1) {
-#pragma unroll
-      for (int c = 0; c < NOUT; ++c) o[c] = af[c];
-    } else {
-      uint32_t a[NIN];
-#pragma unroll
-      for (int j = 0; j < NIN; ++j) a[j] = __float_as_uint(af[j]);
-      uint32_t t3[NIN > 2 ? NIN - 2 : 1];
-#pragma unroll
-      for (int j = 0; j + 2 < NIN; ++j) t3[j] = umax3(a[j], a[j + 1], a[j + 2]);
-#pragma unroll
-      for (int c = 0; c < NOUT; ++c) {
-        // terms: t3 at c, c+3, ... while they fit, then singles
-        uint32_t acc[8];
-        int nt = 0, p = c;
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
-          if (p + 2 <= c + L - 1) {
-            acc[nt++] = t3[p];
-            p += 3;
-          }
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-          if (p <= c + L - 1) acc[nt++] = a[p++];
-        uint32_t m = acc[0];
-        int i = 1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (i + 1 < nt) {
-            m = umax3(m, acc[i], acc[i + 1]);
-            i += 2;
-          } else if (i < nt) {
-            m = max(m, acc[i]);
-            i += 1;
-          }
-        }
-        o[c] = __uint_as_float(m);
-      }
-    }
-  }
-};
-
-// Window maximum of |a| for register values produced by arithmetic (so no
-// NaN canonicalisation is needed); the absolute value folds into the max3
-// source modifiers. Same tripling as WinMax; max is exact in any order.
-template <int H, int NOUT>
-struct WinMaxAbs {
-  static constexpr int L = 2 * H + 1;
-  static constexpr int NIN = NOUT + 2 * H;
-  __device__ static __forceinline__ float m3(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
-  __device__ static __forceinline__ void run(const float* a, float* o) {
-    if constexpr (L == 1) {
-#pragma unroll
-      for (int c = 0; c < NOUT; ++c) o[c] = fabsf(a[c]);
-    } else {
-      float t3[NIN > 2 ? NIN - 2 : 1];
-#pragma unroll
-      for (int j = 0; j + 2 < NIN; ++j) t3[j] = m3(fabsf(a[j]), fabsf(a[j + 1]), fabsf(a[j + 2]));
-#pragma unroll
-      for (int c = 0; c < NOUT; ++c) {
-        float acc[8];
-        int nt = 0, p = c;
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
-          if (p + 2 <= c + L - 1) {
-            acc[nt++] = t3[p];
-            p += 3;
-          }
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-          if (p <= c + L - 1) acc[nt++] = fabsf(a[p++]);
-        float m = acc[0];
-        int i = 1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (i + 1 < nt) {
-            m = m3(m, acc[i], acc[i + 1]);
-            i += 2;
-          } else if (i < nt) {
-            m = fmaxf(m, acc[i]);
-            i += 1;
-          }
-        }
-        o[c] = m;
-      }
-    }
-  }
-};
-
-template <typename T>
-__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, int voff, int soff);
-template <>
-__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-template <>
-__device__ __forceinline__ float buf_ld<__half>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
-}
-template <>
-__device__ __forceinline__ float buf_ld<bf16_t>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
-}
-
-// Buffer descriptor word 3 for gfx9 raw buffers; a lane offset at or beyond
-// the record count reads 0, which masks columns outside the image.
-constexpr int kRsrcWord3 = 0x00020000;
-constexpr int kRecords = 0x40000000;
-constexpr int kOffMasked = 0x40000000;
-
-// ---------------------------------------------------------------------------
-// Streaming index kernel (sliding window). One workgroup owns 16 output rows
-// x out_w output columns and walks every frame once, keeping the previous
-// frame and the previous difference of its (16 + 2H) x 256 input pixels in
-// registers; the next frame is loaded while the current one is reduced.
-// Per triple it writes FP64 moment partials (one per wave), the maximum q
-// of every 64-cell row segment, optional q map rows, and (tile == 32) the
-// per-column sums of the 32-row tiles for the frequency branch.
-// ---------------------------------------------------------------------------
-template <typename T, int H, bool RS>
-struct Stream {
-  static constexpr int NR = kBand + 2 * H;
-  static constexpr int NT = 16;            // outputs per horizontal task
-  static constexpr int NH = NT + 2 * H;
-  // LDS row layout for 32 banks (a half wave per cycle): column c at
-  // c + ((c >> 5) & 7), row stride 264 = 8 (mod 16). A half wave writes 32
-  // consecutive columns of one row (one 32-column run: 32 distinct banks); the
-  // horizontal tasks of a half wave (2 rows x 16 chunks of 16 columns) read
-  // 16 ch + i: run offsets 0..7 plus 8 per row and 16 per odd chunk give 32
-  // distinct banks for every i.
-  static constexpr int LDW = kLanes + 8;
-  __device__ static __forceinline__ int lcol(int c) { return c + ((c >> 5) & 7); }
-
-  // per-column tile sums of the group's columns, with 32 zero words on each
-  // side so a 32-column tile piece is always 32 in-range reads
-  static constexpr int CPAD = 32;
-  struct Shared {
-    float V[3][kBand][LDW];
-    float col[3][kLanes + 2 * CPAD];
-    int mx[kLanes / 64];
-  };
-
-  const StreamArgs& A;
-  Shared& sh;
-  int lane, wave, bid, band, grp, y0, x0, nseg_row, voff;
-  int64_t wg_off;
-  bool all_rows, interior;
-  float inv_full;
-  int mxi;
-
-  __device__ Stream(const StreamArgs& a, Shared& s) : A(a), sh(s) {}
-
-  template <bool ALLROWS>
-  __device__ __forceinline__ void load(int k, float* dst) {
-    const T* fr = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, k);
-    const __amdgpu_buffer_rsrc_t r =
-        __builtin_amdgcn_make_buffer_rsrc((void*)(fr + wg_off), (short)0, kRecords, kRsrcWord3);
-    int pitch = A.W * (int)sizeof(T);
-    // keep the row offsets in one running scalar instead of a hoisted table
-    asm volatile("" : "+s"(pitch));
-    int so = 0;
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const int y = y0 - H + i;
-      if (ALLROWS || (y >= 0 && y < A.H))
-        dst[i] = buf_ld<T>(r, voff, so);
-      else
-        dst[i] = 0.0f;
-      so += pitch;
-    }
-  }
-
-  // One frame: P holds frame k-1 (becomes the load target of frame k+1), C
-  // holds frame k; DI holds the difference of frames k-1, k-2 and DO receives
-  // the difference of frames k, k-1 (the two swap between calls).
-  template <bool ALLROWS>
-  __device__ __forceinline__ void step(int k, float* P, const float* C, const float* DI, float* DO) {
-    // running maximum on the signed-int view of the bits: it orders every
-    // positive float correctly and maps non-positive values below them, which
-    // is all max(., C) with C > 0 needs
-#pragma unroll
-    // (own rows only: halo rows belong to the neighbouring bands; halo
-    // columns repeat pixels of the neighbouring groups, harmless for a max)
-    for (int i = H; i + 1 < H + kBand; i += 2) mxi = max(mxi, max(__float_as_int(C[i]), __float_as_int(C[i + 1])));
-    float dl[NR], rl[NR];
-    if (k >= 2) {
-#pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        DO[i] = C[i] - P[i];
-        pix_terms_signed<RS>(DO[i], DI[i], P[i], A.Cf, dl[i], rl[i]);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < NR; ++i) DO[i] = C[i] - P[i];
-    }
-    // the next frame's loads go straight into P (after the last frame the
-    // same frame is re-read from cache: an unconditional load avoids copies)
-    load<ALLROWS>(k + 1 < A.n ? k + 1 : k, P);
-    if (k < 2) return;
-    const int s = k - 2;
-    {
-      float vs[kBand], vm[kBand], vr[kBand], ts[kBand / 8], tr[kBand / 8];
-      float al[NR];
-#pragma unroll
-      for (int i = 0; i < NR; ++i) al[i] = fabsf(dl[i]);
-      Win<H, kBand, false>::run(al, vs, ts);
-      WinMaxAbs<H, kBand>::run(dl, vm);
-      Win<H, kBand, false>::run(rl, vr, tr);
-#pragma unroll
-      for (int c = 0; c < kBand; ++c) {
-        sh.V[0][c][lcol(lane)] = vs[c];
-        sh.V[1][c][lcol(lane)] = vm[c];
-        sh.V[2][c][lcol(lane)] = vr[c];
-      }
-      if (A.tile_part) {
-        const int ox = lane - H;
-        if (ox >= 0 && ox < A.out_w) {
-          float m = fabsf(dl[H]);
-#pragma unroll
-          for (int i = 1; i < kBand; ++i) m = fmaxf(m, fabsf(dl[H + i]));
-          sh.col[0][CPAD + ox] = ts[0] + ts[1];
-          sh.col[1][CPAD + ox] = m;
-          sh.col[2][CPAD + ox] = tr[0] + tr[1];
-        }
-      }
-    }
-    __syncthreads();
-    // horizontal: lane -> (row r, 16-column chunk ch)
-    const int r = lane >> 4, ch = lane & 15;
-    const int y = y0 + r;
-    const int xc = x0 + NT * ch;
-    const bool chv = (NT * ch < A.out_w) && (xc < A.W) && (y < A.H);
-    // column 16 ch + i of the padded layout: cb + i for i < 16, cb2 + i past
-    // the chunk (the next run for odd ch). The last chunk's columns 256.. read
-    // words 256..263 of the row (bank-aligned with the rest; they only feed
-    // outputs outside the group).
-    const int cb = chv ? 16 * ch + (ch >> 1) : 0;
-    const int cb2 = chv ? cb + (ch & 1) - (ch == 15 ? 8 : 0) : 0;
-    float os[NT], om[NT], orr[NT];
-    {
-      // all three rows of inputs are requested before the windows run
-      float h0[NH], h1[NH], h2[NH];
-#pragma unroll
-      for (int i = 0; i < NH; ++i) {
-        const int ci = (i < 16 ? cb : cb2) + i;
-        h0[i] = sh.V[0][r][ci];
-        h1[i] = sh.V[1][r][ci];
-        h2[i] = sh.V[2][r][ci];
-      }
-      Win<H, NT, false>::run(h0, os, nullptr);
-      WinMax<H, NT>::run(h1, om);
-      Win<H, NT, false>::run(h2, orr, nullptr);
-    }
-    float qv[NT];
-    // FP64 moments: q^2 of a float is exact in double, so a constant map
-    // gives exactly zero variance
-    double s1 = 0.0, s2 = 0.0;
-    float gmax = -INFINITY;
-    if (interior) {
-      // every chunk but the 16th is fully inside the image: no per-cell masks,
-      // the idle chunk is dropped once per lane. The constant 1/n^2 is applied
-      // after the reductions: q = p * inv with p = (S max) R, and rounding
-      // p * inv is monotone, so max q = (max p) * inv exactly.
-      float pv[NT];
-#pragma unroll
-      for (int c = 0; c < NT; ++c) {
-        const float pq = (os[c] * om[c]) * orr[c];
-        pv[c] = pq;
-        const double pd = (double)pq;
-        s1 += pd;
-        s2 = fma(pd, pd, s2);
-        gmax = fmaxf(gmax, pq);
-      }
-      const double id = (double)inv_full;
-      s1 *= id;
-      s2 *= id * id;
-      gmax *= inv_full;
-      if (A.qmap) {
-#pragma unroll
-        for (int c = 0; c < NT; ++c) qv[c] = pv[c] * inv_full;
-      }
-      if (!chv) {
-        s1 = 0.0;
-        s2 = 0.0;
-        gmax = -INFINITY;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < NT; ++c) {
-        const int x = xc + c;
-        const bool v = chv && x < A.W;
-        const float q = ((os[c] * om[c]) * orr[c]) * inv_count2(y, x, H, A.H, A.W);
-        qv[c] = q;
-        const double qm = v ? (double)q : 0.0;
-        s1 += qm;
-        s2 = fma(qm, qm, s2);
-        gmax = v ? fmaxf(gmax, q) : gmax;
-      }
-    }
-    // 64-cell segments = 4 consecutive chunks = one lane quad
-    gmax = fmaxf(gmax, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(gmax), 0xB1, 0xF, 0xF, false)));
-    gmax = fmaxf(gmax, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(gmax), 0x4E, 0xF, 0xF, false)));
-    if ((ch & 3) == 0 && y < A.H && xc < A.W && NT * ch < A.out_w)
-      A.seg_max[((int64_t)s * A.H + y) * nseg_row + grp * kSegsPerGroup + (ch >> 2)] = gmax;
-    if (A.qmap && chv) {
-      float* dst = A.qmap + ((int64_t)s * A.H + y) * A.W + xc;
-      if (xc + NT <= A.W && ((uintptr_t)dst & 15) == 0) {
-        // whole chunk inside the row, 16-byte aligned: four 16-byte stores
-#pragma unroll
-        for (int c = 0; c < NT; c += 4)
-          *reinterpret_cast<float4*>(dst + c) = make_float4(qv[c], qv[c + 1], qv[c + 2], qv[c + 3]);
-      } else {
-#pragma unroll
-        for (int c = 0; c < NT; ++c)
-          if (xc + c < A.W) dst[c] = qv[c];
-      }
-    }
-    const double a1 = row_sum_f64(s1);
-    const double a2 = row_sum_f64(s2);
-    if ((lane & 15) == 15) {
-      double* sp = A.stat_part + (((int64_t)s * gridDim.x + bid) * 16 + (lane >> 4)) * 2;
-      sp[0] = a1;
-      sp[1] = a2;
-    }
-    if (A.tile_part) {
-      // job = (quantity qd, piece p) on 8 lanes; lane sub sums columns
-      // sub, sub + 8, sub + 16, sub + 24 of the 32 columns of tile x0/32 + p
-      // (zeros outside the group or the image), then the 8 lanes combine by
-      // DPP (fixed order). The four jobs of a half wave start at different
-      // 8-column segments, so each read touches 32 distinct banks.
-      const int job = lane >> 3, sub = lane & 7;
-      const int qd = job / kPieces, p = job - kPieces * (job / kPieces);
-      const int qs = qd < 3 ? qd : 0;
-      const int c0 = (x0 / 32 + p) * 32 - x0 + sub;  // >= -31
-      const float* cv = &sh.col[qs][CPAD + c0];
-      const int rot = job & 3;
-      const float v0 = cv[8 * (rot & 3)], v1 = cv[8 * ((rot + 1) & 3)];
-      const float v2 = cv[8 * ((rot + 2) & 3)], v3 = cv[8 * ((rot + 3) & 3)];
-      float sm = (v0 + v1) + (v2 + v3);
-      uint32_t mb = umax3(__float_as_uint(v0), __float_as_uint(v1), max(__float_as_uint(v2), __float_as_uint(v3)));
-      sm += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sm), 0xB1, 0xF, 0xF, false));
-      mb = max(mb, (uint32_t)__builtin_amdgcn_mov_dpp((int)mb, 0xB1, 0xF, 0xF, false));
-      sm += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sm), 0x4E, 0xF, 0xF, false));
-      mb = max(mb, (uint32_t)__builtin_amdgcn_mov_dpp((int)mb, 0x4E, 0xF, 0xF, false));
-      sm += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sm), 0x141, 0xF, 0xF, false));
-      mb = max(mb, (uint32_t)__builtin_amdgcn_mov_dpp((int)mb, 0x141, 0xF, 0xF, false));
-      if (sub == 0 && qd < 3)
-        A.tile_part[((((int64_t)s * A.nbands + band) * A.ncol + grp) * kPieces + p) * 3 + qd] =
-            (double)(qd == 1 ? __uint_as_float(mb) : sm);
-    }
-    __syncthreads();
-  }
-};
-
-template <typename T, int H, bool RS>
-__global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
-  using S = Stream<T, H, RS>;
-  __shared__ typename S::Shared sh;
-  S st(A, sh);
-  st.lane = threadIdx.x;
-  st.wave = st.lane >> 6;
-  tile_of(xcd_remap(blockIdx.x, gridDim.x), A.nbands, A.ncol, A.band_block, st.band, st.grp);
-  st.bid = st.band * A.ncol + st.grp;
-  st.y0 = st.band * kBand;
-  st.x0 = st.grp * A.out_w;
-  const int xin = st.x0 - H + st.lane;
-  const bool colv = (st.lane < A.out_w + 2 * H) && xin >= 0 && xin < A.W;
-  st.voff = colv ? st.lane * (int)sizeof(T) : kOffMasked;
-  st.wg_off = (int64_t)(st.y0 - H) * A.W + (st.x0 - H);
-  st.all_rows = (st.y0 - H >= 0) && (st.y0 + kBand + H <= A.H);
-  st.interior = st.all_rows && (st.x0 - H >= 0) && (st.x0 + A.out_w - 1 + H < A.W);
-  st.nseg_row = A.ncol * kSegsPerGroup;
-  constexpr int WN = (2 * H + 1) * (2 * H + 1);
-  st.inv_full = 1.0f / (float)(WN * WN);
-  st.mxi = INT32_MIN;
-  for (int i = st.lane; i < 3 * kBand * S::LDW; i += kLanes) (&sh.V[0][0][0])[i] = 0.0f;
-  for (int i = st.lane; i < 3 * (kLanes + 2 * S::CPAD); i += kLanes) (&sh.col[0][0])[i] = 0.0f;
-  __syncthreads();
-  float fa[S::NR], fb[S::NR], da[S::NR], db[S::NR];
-#pragma unroll
-  for (int i = 0; i < S::NR; ++i) {
-    fa[i] = 0.0f;
-    da[i] = 0.0f;
-  }
-  if (st.all_rows) {
-    st.template load<true>(0, fb);
-    for (int k = 0; k < A.n; k += 2) {
-      st.template step<true>(k, fa, fb, da, db);
-      if (k + 1 < A.n) st.template step<true>(k + 1, fb, fa, db, da);
-    }
-  } else {
-    st.template load<false>(0, fb);
-    for (int k = 0; k < A.n; k += 2) {
-      st.template step<false>(k, fa, fb, da, db);
-      if (k + 1 < A.n) st.template step<false>(k + 1, fb, fa, db, da);
-    }
-  }
-  int mx = st.mxi;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) mx = max(mx, __shfl_xor(mx, off));
-  if ((st.lane & 63) == 0) sh.mx[st.wave] = mx;
-  __syncthreads();
-  if (st.lane == 0) {
-    int m = sh.mx[0];
-    for (int w = 1; w < kLanes / 64; ++w) m = max(m, sh.mx[w]);
-    // m is the largest value when any is positive, else some value <= 0
-    atomicMax(A.max_key, ord_key(__int_as_float(m)));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Tile-mode kernel: one workgroup per (256-column chunk, tile row, triple).
-// Each lane owns a column, reads the three frames of the triple over the
-// tile row and accumulates sum Delta, max Delta and sum r in FP64; per tile
-// piece of the chunk the columns are summed in order.
-// ---------------------------------------------------------------------------
-template <typename T, bool RS>
-__global__ __launch_bounds__(kLanes) void k_tile(TileArgs A) {
-  __shared__ double sCol[3][kLanes];
-  __shared__ float sMax[kLanes / 64];
-  const int lane = threadIdx.x;
-  const int chunk = blockIdx.x, ty = blockIdx.y, s = blockIdx.z;
-  const int x = chunk * kLanes + lane;
-  const bool cv = x < A.W;
-  const T* f0 = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, s);
-  const T* f1 = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, s + 1);
-  const T* f2 = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, s + 2);
-  const int ya = ty * A.tile;
-  const int yb = min(ya + A.tile, A.H);
-  double sd = 0.0, md = 0.0, sr = 0.0;
-  float mx = -INFINITY;
-  if (cv) {
-    for (int y = ya; y < yb; ++y) {
-      const int64_t o = (int64_t)y * A.W + x;
-      const float a = to_f<T>(f0[o]), b = to_f<T>(f1[o]), c = to_f<T>(f2[o]);
-      mx = fmaxf(mx, fmaxf(a, fmaxf(b, c)));
-      float dl, rl;
-      pix_terms<RS>(c - b, b - a, b, A.Cf, dl, rl);
-      sd += (double)dl;
-      md = fmax(md, (double)dl);
-      sr += (double)rl;
-    }
-  }
-  sCol[0][lane] = sd;
-  sCol[1][lane] = md;
-  sCol[2][lane] = sr;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-  if ((lane & 63) == 0) sMax[lane >> 6] = mx;
-  __syncthreads();
-  const int x0 = chunk * kLanes;
-  for (int job = lane; job < A.pieces * 3; job += kLanes) {
-    const int p = job / 3, qd = job - 3 * (job / 3);
-    const int tx = x0 / A.tile + p;
-    const int ca = max(tx * A.tile, x0) - x0;
-    const int cb = min(min(tx * A.tile + A.tile, x0 + kLanes), A.W) - x0;
-    double acc = 0.0;
-    for (int c = ca; c < cb; ++c) acc = (qd == 1) ? fmax(acc, sCol[1][c]) : acc + sCol[qd][c];
-    A.tile_part[((((int64_t)s * gridDim.y + ty) * A.nchunk + chunk) * A.pieces + p) * 3 + qd] = acc;
-  }
-  if (lane == 0) {
-    float m = sMax[0];
-    for (int w = 1; w < kLanes / 64; ++w) m = fmaxf(m, sMax[w]);
-    atomicMax(A.max_key, ord_key(m));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Streaming tile-mode kernel (tile a power of two <= 32): one workgroup per (band of tpb
-// whole tile rows, chunk of whole tiles); each lane owns a column, keeps the
-// previous frame and the previous difference of the band's rows in
-// registers and walks every frame once. Per triple it accumulates, per tile
-// row of the band, the column's sum Delta, max Delta and sum r (FP32 over at
-// most 32 rows), then one job per tile sums its columns in FP64 and writes
-// the tile's q (Eq. (6) with the in-image count) to the cube.
-// ---------------------------------------------------------------------------
-constexpr int kTileTpbMax = 8;    // tile rows per band
-template <typename T, int TILE, bool RS>
-__global__ __launch_bounds__(kLanes) void k_tile_stream(TileStreamArgs A) {
-  constexpr int TPB = (32 / TILE) < kTileTpbMax ? (32 / TILE) : kTileTpbMax;
-  constexpr int ROWS = TPB * TILE;
-  constexpr int TPC = kLanes / TILE;        // whole tiles per chunk
-  __shared__ float col[TPB][3][kLanes];
-  __shared__ int mxs[kLanes / 64];
-  const int lane = threadIdx.x;
-  const int chunk = blockIdx.x % A.nchunk, band = blockIdx.x / A.nchunk;
-  const int x = chunk * kLanes + lane;
-  const bool cv = x < A.W;
-  const int y0 = band * ROWS;
-  float P[ROWS], D[ROWS];
-  int mxi = INT32_MIN;
-#pragma unroll
-  for (int i = 0; i < ROWS; ++i) {
-    P[i] = 0.0f;
-    D[i] = 0.0f;
-  }
-  for (int k = 0; k < A.n; ++k) {
-    const T* fr = frame_ptr<T>(A.base, A.carry0, A.carry1, A.ncarry, A.plane, k);
-    float sd[TPB], md[TPB], sr[TPB];
-#pragma unroll
-    for (int t = 0; t < TPB; ++t) {
-      sd[t] = 0.0f;
-      md[t] = 0.0f;
-      sr[t] = 0.0f;
-    }
-    // all rows of the frame are requested before any is used
-    float C[ROWS];
-#pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-      const int y = y0 + i;
-      C[i] = (cv && y < A.H) ? to_f<T>(fr[(int64_t)y * A.W + x]) : 0.0f;
-    }
-#pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-      const int y = y0 + i;
-      const bool in = cv && y < A.H;
-      const float c = C[i];
-      mxi = max(mxi, __float_as_int(c));
-      const float dn = c - P[i];
-      if (k >= 2 && in) {
-        float dl, rl;
-        pix_terms<RS>(dn, D[i], P[i], A.Cf, dl, rl);
-        sd[i / TILE] += dl;
-        md[i / TILE] = fmaxf(md[i / TILE], dl);
-        sr[i / TILE] += rl;
-      }
-      D[i] = dn;
-      P[i] = c;
-    }
-    if (k < 2) continue;
-    const int s = k - 2;
-    __syncthreads();  // the previous triple's jobs have read col
-#pragma unroll
-    for (int t = 0; t < TPB; ++t) {
-      col[t][0][lane] = sd[t];
-      col[t][1][lane] = md[t];
-      col[t][2][lane] = sr[t];
-    }
-    __syncthreads();
-    // one job per (tile row of the band, tile of the chunk)
-    for (int job = lane; job < TPB * TPC; job += kLanes) {
-      const int t = job / TPC, j = job - t * TPC;
-      const int ty = band * TPB + t;
-      const int tx = chunk * TPC + j;
-      if (ty >= A.Ty || tx >= A.Tx) continue;
-      const int ca = j * TILE;
-      const int cb = min(ca + TILE, A.W - chunk * kLanes);
-      double a0 = 0.0, a2 = 0.0;
-      float a1 = 0.0f;
-      for (int c = ca; c < cb; ++c) {
-        a0 += (double)col[t][0][c];
-        a1 = fmaxf(a1, col[t][1][c]);
-        a2 += (double)col[t][2][c];
-      }
-      const double n = (double)(min(ty * TILE + TILE, A.H) - ty * TILE) * (double)(cb - ca);
-      const double v = (a0 / n) * (double)a1 * (a2 / n);
-      const int64_t o = ((int64_t)s * A.Ty + ty) * A.Tx + tx;
-      A.cube[o] = v;
-      A.cube_f[o] = (float)v;
-    }
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) mxi = max(mxi, __shfl_xor(mxi, off));
-  if ((lane & 63) == 0) mxs[lane >> 6] = mxi;
-  __syncthreads();
-  if (lane == 0) {
-    int m = mxs[0];
-    for (int w = 1; w < kLanes / 64; ++w) m = max(m, mxs[w]);
-    atomicMax(A.max_key, ord_key(__int_as_float(m)));
-  }
-}
 
 // Tile q from pieces: (sum Delta / n) max Delta (sum r / n), n = cells of the
 // (possibly partial) tile in the image (Eq. (6) with the actual count).
@@ -940,11 +126,6 @@ __global__ void k_to_tlisi(float* map, int64_t n, const double* M) {
     map[i] = (float)(1.0 - (double)map[i] / m2);
 }
 
-__global__ void k_f64_to_f32(const double* src, float* dst, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = (float)src[i];
-}
-
 // ---------------------------------------------------------------------------
 // Radix selection (exact order statistics of a float array per set) for the
 // median / MAD spread. Keys: orderable bits of q (mode 0) or bits of
@@ -956,6 +137,19 @@ struct RsState {
   int64_t rank;
 };
 
+// Selection paths of a set (gate values): order statistics from the keys
+// gathered in a bracket, from a fallback bracket pass, or from the whole set.
+constexpr uint32_t kPathGathered = 1;
+constexpr uint32_t kPathFallback = 2;
+constexpr uint32_t kPathFull = 3;
+
+
+// Per-set gate: the kernels of one selection path run for a set only when
+// its entry equals `want` (null gate: every set). The path of each set is
+// decided on the device, so no host round trip sits inside the spread.
+__device__ __forceinline__ bool gated_off(const uint32_t* gate, int s, uint32_t want) {
+  return gate != nullptr && gate[s] != want;
+}
 
 // Selection key of a value: mode 0 -> order key of q, 1 -> bits of the
 // float |q - med| (non-negative, so the bits order like the values), 2 -> the
@@ -968,9 +162,10 @@ __device__ __forceinline__ uint32_t rs_key(float q, int mode, double m) {
 // far. nvalid (nullable): valid entries per set (arrays of per_set slots).
 __global__ __launch_bounds__(256) void k_rs_hist(const float* vals, int64_t per_set, int mode, const double* med,
                                                  const RsState* st, int shift, int nbits, uint32_t* hist,
-                                                 const unsigned long long* nvalid) {
+                                                 const unsigned long long* nvalid, const uint32_t* gate, uint32_t want) {
   __shared__ uint32_t h[kHistBins];
   const int s = blockIdx.y;
+  if (gated_off(gate, s, want)) return;
   for (int i = threadIdx.x; i < kHistBins; i += 256) h[i] = 0;
   __syncthreads();
   const RsState S = st[s];
@@ -1001,9 +196,11 @@ __global__ __launch_bounds__(256) void k_rs_hist(const float* vals, int64_t per_
 // Digit of the rank-th key: the first bin whose running count exceeds the
 // rank (the last bin when none does); the histogram is cleared for the next
 // digit. One workgroup of 256 per set, nbits 10 or 11.
-__global__ __launch_bounds__(256) void k_rs_pick(RsState* st, uint32_t* hist, int shift, int nbits) {
+__global__ __launch_bounds__(256) void k_rs_pick(RsState* st, uint32_t* hist, int shift, int nbits, const uint32_t* gate,
+                                                 uint32_t want) {
   __shared__ int64_t part[256];
   const int s = blockIdx.x, t = threadIdx.x;
+  if (gated_off(gate, s, want)) return;
   const RsState S = st[s];
   uint32_t* h = hist + (int64_t)s * kHistBins;
   const int nb = 1 << nbits, per = nb / 256;
@@ -1050,9 +247,9 @@ __global__ __launch_bounds__(256) void k_rs_pick(RsState* st, uint32_t* hist, in
 }
 
 // Every set searches the same rank.
-__global__ void k_rs_init_rank(RsState* st, int nsets, int64_t rank) {
+__global__ void k_rs_init_rank(RsState* st, int nsets, int64_t rank, const uint32_t* gate, uint32_t want) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsets) return;
+  if (s >= nsets || gated_off(gate, s, want)) return;
   RsState S;
   S.prefix = 0;
   S.known = 0;
@@ -1061,9 +258,10 @@ __global__ void k_rs_init_rank(RsState* st, int nsets, int64_t rank) {
 }
 
 // Rank within the gathered keys: global rank minus the keys below them.
-__global__ void k_rs_init_gathered(RsState* st, int nsets, int64_t rank, const unsigned long long* cnt) {
+__global__ void k_rs_init_gathered(RsState* st, int nsets, int64_t rank, const unsigned long long* cnt,
+                                   const uint32_t* gate, uint32_t want) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsets) return;
+  if (s >= nsets || gated_off(gate, s, want)) return;
   RsState S;
   S.prefix = 0;
   S.known = 0;
@@ -1075,8 +273,9 @@ __global__ void k_rs_init_gathered(RsState* st, int nsets, int64_t rank, const u
 // with mult odd and coprime to per_set, so the samples spread over the set
 // without following its rows or columns.
 __global__ void k_rs_sample(const float* vals, int64_t per_set, int mode, const double* med, int64_t S,
-                            uint64_t mult, uint32_t* samp) {
+                            uint64_t mult, uint32_t* samp, const uint32_t* gate, uint32_t want) {
   const int s = blockIdx.y;
+  if (gated_off(gate, s, want)) return;
   const double m = mode == 1 ? med[s] : 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x) {
     // i < 2^20 and mult < per_set < 2^32: the product fits in 64 bits
@@ -1086,9 +285,10 @@ __global__ void k_rs_sample(const float* vals, int64_t per_set, int mode, const 
 }
 
 // selected key of each set -> bkt[2 s + which]
-__global__ void k_rs_key_out(const RsState* st, int nsets, int which, uint32_t* bkt) {
+__global__ void k_rs_key_out(const RsState* st, int nsets, int which, uint32_t* bkt, const uint32_t* gate,
+                             uint32_t want) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < nsets) bkt[2 * s + which] = st[s].prefix;
+  if (s < nsets && !gated_off(gate, s, want)) bkt[2 * s + which] = st[s].prefix;
 }
 
 // One pass over a set: keys below bkt[2s] are counted (cnt[2s]); keys in
@@ -1115,7 +315,8 @@ constexpr int kGatherStage = 4096;  // one round of keys
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_rs_gather(const float* vals, int64_t per_set, int mode, const double* med,
                                                    const uint32_t* bkt, int64_t cap, unsigned long long* cnt,
-                                                   uint32_t* gbuf) {
+                                                   uint32_t* gbuf, const uint32_t* gate, uint32_t want) {
+  if (gated_off(gate, blockIdx.y, want)) return;
   constexpr int64_t kRound = 256 * 16;
   static_assert(kGatherStage >= kRound, "a stage holds one round");
   __shared__ uint32_t stage[kGatherStage];
@@ -1386,21 +587,36 @@ __global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t p
 // t_in + |med - mhat|, outer ones |q - med| > t_out - |med - mhat| (slack
 // 2^-40 covers the double roundings of these bounds). bad[s] = 1 otherwise.
 __global__ void k_rs_mad_verify(const double* pl, const double* med, const double* dev,
-                                const unsigned long long* cnt1, int nsets, uint32_t* bad) {
+                                const unsigned long long* cnt1, int nsets, uint32_t* gate_mad) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsets) return;
+  if (s >= nsets || gate_mad[s] != kPathGathered) return;
   const double e = fabs(med[s] - pl[4 * s + 0]);
   const double slack = 0x1p-40;
   const float in_max = (float)((pl[4 * s + 2] + e) * (1.0 + slack));
   const float out_min = (float)((pl[4 * s + 3] - e) * (1.0 - slack));
   const bool ok_in = cnt1[2 * s] == 0 || (double)in_max <= dev[2 * s];
   const bool ok_out = (double)out_min > dev[2 * s + 1];
-  bad[s] = (ok_in && ok_out && isfinite(med[s])) ? 0u : 1u;
+  // a failed check sends the set to the fallback pass around the exact median
+  if (!(ok_in && ok_out && isfinite(med[s]))) gate_mad[s] = kPathFallback;
+}
+
+// Path of each set after a bracket pass: the gathered keys when the bracket
+// holds both middle ranks and fitted its buffer, else `otherwise`. Also the
+// number of valid gathered keys (rank offsets stay in cnt[2 s]).
+__global__ void k_rs_plan(const unsigned long long* cnt, int nsets, int64_t cap, int64_t r_lo, int64_t r_hi,
+                          uint32_t* gate, uint32_t only, uint32_t take, uint32_t otherwise, unsigned long long* nvalid) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets || (only != 0u && gate[s] != only)) return;
+  const int64_t below = (int64_t)cnt[2 * s], in = (int64_t)cnt[2 * s + 1];
+  const bool ok = in <= cap && below <= r_lo && r_hi < below + in;
+  gate[s] = ok ? take : otherwise;
+  nvalid[s] = cnt[2 * s + 1];
 }
 
 // Dispersion keys of a sample of order keys: |q - med| of the sampled q.
-__global__ void k_rs_sample_dev(uint32_t* samp, int64_t S, const double* med) {
+__global__ void k_rs_sample_dev(uint32_t* samp, int64_t S, const double* med, const uint32_t* gate, uint32_t want) {
   const int s = blockIdx.y;
+  if (gated_off(gate, s, want)) return;
   const double m = med[s];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x) {
     uint32_t* p = samp + (int64_t)s * S + i;
@@ -1408,25 +624,17 @@ __global__ void k_rs_sample_dev(uint32_t* samp, int64_t S, const double* med) {
   }
 }
 
-__global__ void k_rs_init(RsState* st, int nsets, int64_t per_set, int which) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsets) return;
-  RsState S;
-  S.prefix = 0;
-  S.known = 0;
-  S.rank = which ? per_set / 2 : (per_set - 1) / 2;
-  st[s] = S;
-}
-
 // The order statistic just above the selected one (rank + 1): the selected
 // key itself when more than rank + 1 keys are <= it, else the smallest key
 // above it. One pass: count of keys <= the selected key, minimum key above.
 __global__ __launch_bounds__(256) void k_rs_next(const float* vals, int64_t per_set, int mode, const double* med,
                                                  const RsState* st, unsigned long long* cnt_le, uint32_t* min_gt,
-                                                 const unsigned long long* nvalid) {
+                                                 const unsigned long long* nvalid, const uint32_t* gate,
+                                                 uint32_t want) {
   __shared__ uint32_t sh_c[256];
   __shared__ uint32_t sh_m[256];
   const int s = blockIdx.y;
+  if (gated_off(gate, s, want)) return;
   const uint32_t sel = st[s].prefix;
   const float* v = vals + (int64_t)s * per_set;
   const double m = mode == 1 ? med[s] : 0.0;
@@ -1456,18 +664,19 @@ __global__ __launch_bounds__(256) void k_rs_next(const float* vals, int64_t per_
 // base (nullable): keys below the searched range, not in the counted array
 __global__ void k_rs_next_store(const RsState* st, int nsets, int64_t rank_hi, int mode,
                                 const unsigned long long* cnt_le, const uint32_t* min_gt,
-                                const unsigned long long* base, double* out) {
+                                const unsigned long long* base, double* out, const uint32_t* gate, uint32_t want) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsets) return;
+  if (s >= nsets || gated_off(gate, s, want)) return;
   const int64_t le = (int64_t)cnt_le[s] + (base ? (int64_t)base[2 * s] : 0);
   const uint32_t k = (le >= rank_hi + 1) ? st[s].prefix : min_gt[s];
   out[2 * s + 1] = mode ? (double)__uint_as_float(k) : (double)ord_val(k);
 }
 
 // value of the selected key: mode 0 -> q, mode 1 -> |q - med| (as float)
-__global__ void k_rs_store(const RsState* st, int nsets, int mode, int which, double* out) {
+__global__ void k_rs_store(const RsState* st, int nsets, int mode, int which, double* out, const uint32_t* gate,
+                           uint32_t want) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsets) return;
+  if (s >= nsets || gated_off(gate, s, want)) return;
   const uint32_t k = st[s].prefix;
   const double v = mode ? (double)__uint_as_float(k) : (double)ord_val(k);
   out[2 * s + which] = v;
@@ -1507,10 +716,6 @@ __global__ void k_segmax_direct(const float* vals, SegLayout L, float* seg_max) 
 constexpr int kPerThread = 16;
 constexpr int kChunk = 256 * kPerThread;
 
-__device__ __forceinline__ bool zsel(float q, double mu, double sg, double tau) {
-  return ((double)q - mu) / sg > tau;
-}
-
 // Two-level selection. A block is br rows of one 64-cell segment column
 // (block b = (set, yb, g) in raster order); a block is flagged when the
 // largest row-segment maximum in it passes the threshold. Flagged blocks are
@@ -1541,9 +746,10 @@ __device__ __forceinline__ BlkIdx blk_decode(const SegLayout& L, int64_t b) {
 // consecutive threads on consecutive segments (coalesced maxima reads), and
 // the number of flagged blocks per chunk of kChunk blocks.
 __global__ __launch_bounds__(256) void k_blk_count(const float* seg_max, const double* mu, const double* sigma,
-                                                   const uint32_t* flags, double tau, SegLayout L, uint8_t* bflag,
-                                                   uint32_t* cnt) {
+                                                   const uint32_t* flags, const CallDev* cd, SegLayout L,
+                                                   uint8_t* bflag, uint32_t* cnt) {
   __shared__ uint32_t sh[256];
+  const double tau = cd->tau;
   const int64_t NB = (int64_t)L.nsets * L.nbr * L.nseg_row;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   uint32_t c = 0;
@@ -1637,12 +843,12 @@ struct RowFlag {
   const float* seg_max;
   const double* mu;
   const double* sigma;
-  double tau;
+  const CallDev* cd;
   __device__ bool operator()(int64_t j) const {
     const int64_t e = ro.entry(j);
     if (e < 0) return false;
     const int s = (int)(e / ((int64_t)ro.L.Ho * ro.L.nseg_row));
-    return zsel(seg_max[e], mu[s], sigma[s], tau);
+    return zsel(seg_max[e], mu[s], sigma[s], cd->tau);
   }
 };
 
@@ -1772,91 +978,13 @@ __global__ __launch_bounds__(256) void k_compact_write(F f, E emit, int64_t ne_s
   }
 }
 
-// Exact q of the cells of each selected segment, recomputed with the same
-// arithmetic as k_stream; mask of z > tau.
-template <typename T, int H, bool RS>
-__global__ __launch_bounds__(64) void k_recompute(const void* base, const void* c0, const void* c1, int ncarry,
-                                                  int64_t plane, int Hh, int Wh, float Cf,
-                                                  SegLayout L, const int64_t* seg_entry, const int64_t* nsel_p,
-                                                  int64_t cap, const double* mu, const double* sigma, double tau,
-                                                  uint64_t* seg_mask, float* cell_q) {
-  constexpr int NV = 8 + 2 * H;
-  __shared__ float sv[3][64 + 32 + 2 * kMaxHalo];
-  const int lane = threadIdx.x;
-  int64_t nsel = nsel_p[0];
-  if (nsel > cap) nsel = cap;
-  for (int64_t i = blockIdx.x; i < nsel; i += gridDim.x) {
-    const int64_t e = seg_entry[i];
-    const int g = (int)(e % L.nseg_row);
-    const int64_t row = e / L.nseg_row;
-    const int y = (int)(row % L.Ho);
-    const int s = (int)(row / L.Ho);
-    const int xs = seg_x0(L, g), wd = seg_width(L, g);
-    const int cmin = 8 * (xs / 8) - H;
-    const int ncols = 8 * ((xs + wd - 1) / 8) + 7 + H - cmin + 1;
-    const int by = 8 * (y / 8);
-    const T* f0 = frame_ptr<T>(base, c0, c1, ncarry, plane, s);
-    const T* f1 = frame_ptr<T>(base, c0, c1, ncarry, plane, s + 1);
-    const T* f2 = frame_ptr<T>(base, c0, c1, ncarry, plane, s + 2);
-    for (int cc = lane; cc < ncols; cc += 64) {
-      const int col = cmin + cc;
-      float dl[NV], rl[NV];
-#pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        const int yy = by - H + j;
-        float a = 0.0f, b = 0.0f, c = 0.0f;
-        if (col >= 0 && col < Wh && yy >= 0 && yy < Hh) {
-          const int64_t o = (int64_t)yy * Wh + col;
-          a = to_f<T>(f0[o]);
-          b = to_f<T>(f1[o]);
-          c = to_f<T>(f2[o]);
-        }
-        pix_terms<RS>(c - b, b - a, b, Cf, dl[j], rl[j]);
-      }
-      float o8[8];
-      Win<H, 8, false>::run(dl, o8, nullptr);
-      sv[0][cc] = o8[y - by];
-      WinMax<H, 8>::run(dl, o8);
-      sv[1][cc] = o8[y - by];
-      Win<H, 8, false>::run(rl, o8, nullptr);
-      sv[2][cc] = o8[y - by];
-    }
-    __syncthreads();
-    bool sel = false;
-    float q = 0.0f;
-    if (lane < wd) {
-      const int x = xs + lane;
-      const int bx = 8 * (x / 8);
-      float hs[NV], hm[NV], hr[NV], os[8], om[8], orr[8];
-#pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        const int ci = bx - H + j - cmin;
-        hs[j] = sv[0][ci];
-        hm[j] = sv[1][ci];
-        hr[j] = sv[2][ci];
-      }
-      Win<H, 8, false>::run(hs, os, nullptr);
-      WinMax<H, 8>::run(hm, om);
-      Win<H, 8, false>::run(hr, orr, nullptr);
-      const int c = x - bx;
-      // same association as k_stream: ((sum * max) * sum_r) * 1/n^2
-      const float inv = inv_count2(y, x, H, Hh, Wh);
-      q = ((os[c] * om[c]) * orr[c]) * inv;
-      sel = zsel(q, mu[s], sigma[s], tau);
-    }
-    const uint64_t m = __ballot(sel);
-    cell_q[i * 64 + lane] = q;
-    if (lane == 0) seg_mask[i] = m;
-    __syncthreads();
-  }
-}
-
 // Cells of each selected segment taken from a value array (tiles / eta).
 __global__ __launch_bounds__(64) void k_fill_direct(const float* vals, SegLayout L, const int64_t* seg_entry,
                                                     const int64_t* nsel_p, int64_t cap, const double* mu,
-                                                    const double* sigma, double tau, uint64_t* seg_mask,
+                                                    const double* sigma, const CallDev* cd, uint64_t* seg_mask,
                                                     float* cell_q) {
   const int lane = threadIdx.x;
+  const double tau = cd->tau;
   int64_t nsel = nsel_p[0];
   if (nsel > cap) nsel = cap;
   for (int64_t i = blockIdx.x; i < nsel; i += gridDim.x) {
@@ -2073,25 +1201,26 @@ __global__ void k_comp_finalize(const int64_t* ncomp_p, int64_t cap, const int32
   }
 }
 
-__global__ void k_advance_base(int64_t* counters) {
-  // counters: [1] components of this run, [3] output base
-  if (threadIdx.x == 0 && blockIdx.x == 0) counters[3] += counters[1];
-}
+
 
 // ---------------------------------------------------------------------------
-// Image-frequency branch: per tile, DFT over s of the detrended tile series,
-// one-sided magnitudes k = 1..floor(n'/2), h = max or harmonic sum.
+// Image-frequency branch (Sec. 2.4.2, Eq. (10)): per series, DFT over s of
+// the mean-removed series, one-sided magnitudes k = 1..floor(n'/2),
+// h = max or harmonic sum.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t ntiles, int harm, double* eta,
-                                             float* eta_f) {
-  extern __shared__ double tw[];  // [2][np]: cos, sin of 2 pi m / np
-  for (int m = threadIdx.x; m < np; m += blockDim.x) {
+// tw[m] = (cos, sin)(2 pi m / n'), m = 0..n'-1 (the phase k s is reduced
+// modulo n' exactly before the table is read).
+__global__ void k_twiddle(int np, double2* tw) {
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < np; m += gridDim.x * blockDim.x) {
     double sn, cs;
     sincospi(2.0 * (double)m / (double)np, &sn, &cs);
-    tw[m] = cs;
-    tw[np + m] = sn;
+    tw[m] = make_double2(cs, sn);
   }
-  __syncthreads();
+}
+
+// Tile branch: one thread per tile, direct FP64 sums in the order of Eq. (10).
+__global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t ntiles, int harm, const double2* tw,
+                                             double* eta, float* eta_f) {
   const int K = np / 2;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
     double mean = 0.0;
@@ -2107,8 +1236,9 @@ __global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t
         int ph = 0;
         for (int s = 0; s < np; ++s) {
           const double v = cube[(int64_t)s * ntiles + t] - mean;
-          re = fma(v, tw[ph], re);
-          im = fma(-v, tw[np + ph], im);
+          const double2 w = tw[ph];
+          re = fma(v, w.x, re);
+          im = fma(-v, w.y, im);
           ph += kk;
           if (ph >= np) ph -= np;
         }
@@ -2122,80 +1252,222 @@ __global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t
   }
 }
 
-// Per-pixel form of the frequency branch: the same transform of every
-// cell's series of sliding q over the triples (series held in registers,
-// n' <= NP), one-sided magnitudes, h = max or harmonic sum. The twiddles of
-// each frequency are tabulated in LDS in the order the sum runs (k, s), so
-// one 16-byte broadcast read serves the two multiply-adds of a term.
-template <int NP>
-__global__ __launch_bounds__(256) void k_eta_px(const float* q, int np, int64_t plane, int harm, double* eta,
-                                                float* eta_f) {
-  extern __shared__ double2 tw2[];  // [K][np]: (cos, sin) of 2 pi k s / np, k = 1..K
+typedef double fitrig_v4d __attribute__((ext_vector_type(4)));
+
+// Per-pixel form of Eq. (10) on the matrix cores. For a tile of 64 pixels the
+// spectra are FP64 matrix products D = T Q: T[row][s] holds cos or sin of
+// 2 pi k s / n' for k = 1..K, Q[s][pixel] the pixel's q series. Each
+// v_mfma_f64_16x16x4 takes 16 rows x 4 series values (A: lane i + 16 kk
+// holds T[i][kk]) and 4 values x 16 pixels (B: lane n + 16 kk holds
+// Q[kk][n]) and accumulates D, whose register r of lane n + 16 c holds row
+// 4 r + c of pixel column n. Row i of a block of 16 therefore carries
+// frequency 2 (i mod 4) + floor(i / 8) + 1 (within the block's 8) and the
+// cosine for even floor(i / 4), the sine for odd: registers 0..3 of lane
+// n + 16 c then hold (re, im) of frequency 2 c + 1 and of 2 c + 2. A lane's
+// four pixel columns are the four pixels of one 16-byte load, so a block of
+// 16 columns is pixels p0 + 4 n + j. The series is not mean-removed: for k >= 1 a row of T sums
+// to zero, so the mean contributes only the FP64 rounding of that sum (the
+// products of FP32 q and FP64 twiddles are exact, accumulated in FP64).
+// MBG blocks of 16 rows are accumulated per pass over the series. Per
+// block of the grid (one wave) the FP64 sum and sum of squares of its
+// pixels' eta go to part[2 b], part[2 b + 1].
+template <int MBG, bool VEC>
+__global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t plane, int harm, const double2* twg,
+                                               float* eta_f, double* part) {
+  extern __shared__ double2 lds_tw[];         // [np] twiddles, then [K][64] float magnitudes (harmonic sums)
+  float* ak = (float*)(lds_tw + np);
+  const int lane = threadIdx.x;
+  const int n = lane & 15, kk = lane >> 4;
   const int K = np / 2;
-  for (int i = threadIdx.x; i < K * np; i += blockDim.x) {
-    const int k = i / np + 1, s = i - (k - 1) * np;
-    const int m = (int)(((int64_t)k * s) % np);
-    double sn, cs;
-    sincospi(2.0 * (double)m / (double)np, &sn, &cs);
-    tw2[i] = make_double2(cs, sn);
-  }
+  const int nmb = (2 * K + 15) / 16;
+  const int T = (np + 3) / 4;
+  for (int i = lane; i < np; i += 64) lds_tw[i] = twg[i];
   __syncthreads();
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < plane; p += (int64_t)gridDim.x * blockDim.x) {
-    double v[NP];
-    double mean = 0.0;
+  double s1 = 0.0, s2 = 0.0;
+  const int64_t ntile = (plane + 63) / 64;
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t p0 = tile * 64;
+    const bool full = p0 + 64 <= plane;
+    double best[4] = {0.0, 0.0, 0.0, 0.0};  // max over k of A_k^2 (pixel p0 + 4 n + j)
+    for (int g = 0; g < nmb; g += MBG) {
+      fitrig_v4d acc[MBG][4];
+      int idx[MBG], stp[MBG];
+      bool rv[MBG];
 #pragma unroll
-    for (int s = 0; s < NP; ++s) {
-      v[s] = s < np ? (double)q[(int64_t)s * plane + p] : 0.0;
-      if (s < np) mean += v[s];
+      for (int m = 0; m < MBG; ++m) {
+        const int f = 8 * (g + m) + 2 * (n & 3) + (n >> 3) + 1;  // frequency of this lane's A row
+        rv[m] = f <= K;
+        idx[m] = (int)(((int64_t)f * kk) % np);
+        stp[m] = (int)(((int64_t)f * 4) % np);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[m][j] = fitrig_v4d{0.0, 0.0, 0.0, 0.0};
+      }
+      for (int t = 0; t < T; ++t) {
+        const int s = 4 * t + kk;
+        double b[4] = {0.0, 0.0, 0.0, 0.0};
+        if (s < np) {
+          const float* row = q + (int64_t)s * plane + p0 + 4 * n;
+          if (VEC && full) {
+            const float4 v = *reinterpret_cast<const float4*>(row);
+            b[0] = v.x;
+            b[1] = v.y;
+            b[2] = v.z;
+            b[3] = v.w;
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (p0 + 4 * n + j < plane) b[j] = row[j];
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < MBG; ++m) {
+          double a = 0.0;
+          if (rv[m] && s < np) {
+            const double2 w = lds_tw[idx[m]];
+            a = ((n >> 2) & 1) ? w.y : w.x;
+          }
+          idx[m] += stp[m];
+          if (idx[m] >= np) idx[m] -= np;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[m][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[j], acc[m][j], 0, 0, 0);
+        }
+      }
+      // registers 0..3: (re, im) of f0 and of f0 + 1 (rows kk, kk + 4, kk + 8, kk + 12)
+#pragma unroll
+      for (int m = 0; m < MBG; ++m) {
+        const int f0 = 8 * (g + m) + 2 * kk + 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double a0 = acc[m][j][0] * acc[m][j][0] + acc[m][j][1] * acc[m][j][1];
+          const double a1 = acc[m][j][2] * acc[m][j][2] + acc[m][j][3] * acc[m][j][3];
+          if (harm == 0) {
+            if (f0 <= K) best[j] = fmax(best[j], a0);
+            if (f0 + 1 <= K) best[j] = fmax(best[j], a1);
+          } else {
+            if (f0 <= K) ak[(f0 - 1) * 64 + 4 * n + j] = (float)sqrt(a0);
+            if (f0 + 1 <= K) ak[f0 * 64 + 4 * n + j] = (float)sqrt(a1);
+          }
+        }
+      }
     }
-    mean /= (double)np;
-#pragma unroll
-    for (int s = 0; s < NP; ++s) v[s] -= mean;
-    double best = 0.0;
-    int k0 = 1;
     if (harm == 0) {
-      // h = max: two frequencies per pass over s (four independent chains)
-      for (; k0 + 1 <= K; k0 += 2) {
-        const double2* t0 = tw2 + (k0 - 1) * np;
-        const double2* t1 = t0 + np;
-        double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
 #pragma unroll
-        for (int s = 0; s < NP; ++s) {
-          if (s < np) {
-            const double2 w0 = t0[s], w1 = t1[s];
-            re0 = fma(v[s], w0.x, re0);
-            im0 = fma(-v[s], w0.y, im0);
-            re1 = fma(v[s], w1.x, re1);
-            im1 = fma(-v[s], w1.y, im1);
+      for (int j = 0; j < 4; ++j) {
+        best[j] = fmax(best[j], __shfl_xor(best[j], 16));
+        best[j] = fmax(best[j], __shfl_xor(best[j], 32));
+      }
+      if (kk == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t p = p0 + 4 * n + j;
+          if (p < plane) {
+            const double e = sqrt(best[j]);
+            eta_f[p] = (float)e;
+            s1 += e;
+            s2 = fma(e, e, s2);
           }
         }
-        const double a0 = sqrt(re0 * re0 + im0 * im0), a1 = sqrt(re1 * re1 + im1 * im1);
-        if (k0 == 1 || a0 > best) best = a0;
-        if (a1 > best) best = a1;
       }
+    } else {
+      __syncthreads();
+      const int64_t p = p0 + lane;
+      double bv = 0.0;
+      for (int k = 1; k <= K; ++k) {
+        double val = 0.0;
+        for (int j = 1; j <= harm && j * k <= K; ++j) val += (double)ak[(j * k - 1) * 64 + lane];
+        if (k == 1 || val > bv) bv = val;
+      }
+      if (p < plane) {
+        eta_f[p] = (float)bv;
+        s1 += bv;
+        s2 = fma(bv, bv, s2);
+      }
+      __syncthreads();
     }
-    for (int k = k0; k <= K; ++k) {
-      double val = 0.0;
-      const int jmax = harm == 0 ? 1 : harm;
-      for (int j = 1; j <= jmax && j * k <= K; ++j) {
-        const double2* t = tw2 + (j * k - 1) * np;
-        double re = 0.0, im = 0.0;
+  }
+  // fixed-order wave sums
 #pragma unroll
-        for (int s = 0; s < NP; ++s) {
-          if (s < np) {
-            const double2 w = t[s];
-            re = fma(v[s], w.x, re);
-            im = fma(-v[s], w.y, im);
-          }
-        }
-        val += sqrt(re * re + im * im);
-      }
-      if (k == 1 || val > best) best = val;
-    }
-    if (K < 1) best = 0.0;
-    eta[p] = best;
-    eta_f[p] = (float)best;
+  for (int off = 32; off >= 1; off >>= 1) {
+    s1 += __shfl_xor(s1, off);
+    s2 += __shfl_xor(s2, off);
+  }
+  if (lane == 0) {
+    part[2 * (int64_t)blockIdx.x] = s1;
+    part[2 * (int64_t)blockIdx.x + 1] = s2;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Call record, result delivery, small fills and copies.
+// ---------------------------------------------------------------------------
+__global__ void k_set_call(CallDev* d, CallDev v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *d = v;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// counters[CNT_TRUNC] |= overflow of this run; per-branch count; output base.
+__global__ void k_run_done(int64_t* c, int64_t seg_cap, int64_t blk_cap, int64_t comp_cap, int branch) {
+  if (threadIdx.x || blockIdx.x) return;
+  if (c[CNT_NSEL] > seg_cap || c[CNT_NBLK] > blk_cap || c[CNT_NCOMP] > comp_cap) c[CNT_TRUNC] |= 1;
+  const int64_t nc = c[CNT_NCOMP] < comp_cap ? c[CNT_NCOMP] : comp_cap;
+  c[branch == FITRIG_IMAGE ? CNT_IMG : branch == FITRIG_FREQ ? CNT_FREQ : CNT_FPX] += nc;
+  c[CNT_OUTBASE] += nc;
+}
+
+// Frequency series over [history | this call] (serving): slices
+// n_in - from_hist .. n_in - 1 of the history, then the call's last
+// from_call slices of the cube, into fs; afterwards (k_hist_out) fs becomes
+// the field's history.
+__global__ void k_hist_in(const CallDev* cd, int64_t hist_off, int64_t n_hist, const double* cube, int64_t cube_off,
+                          int64_t n_call, double* fs) {
+  const double* h = cd->hist_in;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_hist + n_call;
+       i += (int64_t)gridDim.x * blockDim.x)
+    fs[i] = i < n_hist ? h[hist_off + i] : cube[cube_off + (i - n_hist)];
+}
+__global__ void k_hist_out(const CallDev* cd, const double* fs, int64_t n) {
+  double* h = cd->hist_out;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    h[i] = fs[i];
+}
+
+// Results of a call into host-visible memory: counters, M, the frequency
+// statistics, per-triple mu / sigma / flags and min(total, cap) candidates
+// (layout in ResultLayout). Only the records that exist cross the bus.
+__global__ void k_pack_results(const int64_t* cnt, const double* M, const double* eta_st, const double* mu,
+                               const double* sigma, const uint32_t* flags, int np, const fitrig_candidate* cand,
+                               int64_t cap, ResultLayout R, char* dst) {
+  int64_t ncand = cnt[CNT_OUTBASE];
+  if (ncand > cap) ncand = cap;
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
+  int64_t* hc = (int64_t*)(dst + R.off_cnt);
+  for (int64_t i = tid; i < CNT_N; i += nth) hc[i] = cnt[i];
+  uint64_t* hd = (uint64_t*)(dst + R.off_scalars);
+  if (tid == 0) {
+    hd[0] = __double_as_longlong(M[0]);
+    for (int i = 0; i < ES_N; ++i) hd[1 + i] = ((const uint64_t*)eta_st)[i];
+  }
+  double* hmu = (double*)(dst + R.off_mu);
+  double* hsg = (double*)(dst + R.off_sigma);
+  uint32_t* hfl = (uint32_t*)(dst + R.off_flags);
+  for (int64_t i = tid; i < np; i += nth) {
+    hmu[i] = mu[i];
+    hsg[i] = sigma[i];
+    hfl[i] = flags[i];
+  }
+  const uint64_t* src = (const uint64_t*)cand;
+  uint64_t* out = (uint64_t*)(dst + R.off_cand);
+  const int64_t words = ncand * (int64_t)(sizeof(fitrig_candidate) / 8);
+  for (int64_t i = tid; i < words; i += nth) out[i] = src[i];
+}
+
 
 }  // namespace fitrig

@@ -173,8 +173,7 @@ void worker_main(fitrig_server* S, int slot) {
         f.nring = ok ? (int)std::min<int64_t>(S->cfg.freq_window, (int64_t)f.nring + r->n_triples) : 0;
         r->freq_triples = (ok && (S->cfg.base.branches & FITRIG_FREQ) && f.nring >= 4) ? f.nring : 0;
       } else {
-        r->freq_triples =
-            ((S->cfg.base.branches & FITRIG_FREQ) && r->n_triples >= 4 && r->n_triples <= 2048) ? r->n_triples : 0;
+        r->freq_triples = ((S->cfg.base.branches & FITRIG_FREQ) && r->n_triples >= 4) ? r->n_triples : 0;
       }
       f.M = fmax(f.M, st.M);
       r->M = f.M;

@@ -14,7 +14,7 @@ import ctypes
 import os
 from typing import Optional
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_TRUNC, E_BUSY, E_NOTREADY = 0, -1, -2, -3, -4, -5, -6
 F32, F16, BF16 = 0, 1, 2
@@ -71,7 +71,7 @@ class fitrig_stats(ctypes.Structure):
     _fields_ = [
         ("M", ctypes.c_double),
         ("n_triples", ctypes.c_int32),
-        ("pad0", ctypes.c_int32),
+        ("status", ctypes.c_int32),
         ("mu", ctypes.POINTER(ctypes.c_double)),
         ("sigma", ctypes.POINTER(ctypes.c_double)),
         ("flags", ctypes.POINTER(ctypes.c_uint32)),
@@ -79,6 +79,11 @@ class fitrig_stats(ctypes.Structure):
         ("eta_sigma", ctypes.c_double),
         ("n_image_cand", ctypes.c_int64),
         ("n_freq_cand", ctypes.c_int64),
+        ("n_freq_px_cand", ctypes.c_int64),
+        ("eta_px_mu", ctypes.c_double),
+        ("eta_px_sigma", ctypes.c_double),
+        ("ran", ctypes.c_uint32),
+        ("eta_flags", ctypes.c_uint32),
     ]
 
 
@@ -147,7 +152,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fitrig_create.argtypes = [ctypes.POINTER(fitrig_config), ctypes.POINTER(vp)]
     L.fitrig_create.restype = i32
     L.fitrig_detect.argtypes = [vp, vp, i32, i32, i32, i32, dbl, ctypes.POINTER(fitrig_candidate), i64,
-                                ctypes.POINTER(i64), vp, vp, ctypes.POINTER(fitrig_stats), vp]
+                                ctypes.POINTER(i64), vp, vp, vp, ctypes.POINTER(fitrig_stats), vp]
     L.fitrig_detect.restype = i32
     L.fitrig_destroy.argtypes = [vp]
     L.fitrig_destroy.restype = i32
@@ -196,9 +201,9 @@ def fitrig_create(cfg: fitrig_config) -> tuple[int, Optional[int]]:
 
 
 def fitrig_detect(ctx, stack_ptr, dtype, n_snap, H, W, sigma, cand, cand_cap, n_cand, index_map, eta_map,
-                  stats, hip_stream) -> int:
+                  eta_px_map, stats, hip_stream) -> int:
     return load().fitrig_detect(ctx, stack_ptr, dtype, n_snap, H, W, sigma, cand, cand_cap, n_cand, index_map,
-                                eta_map, stats, hip_stream)
+                                eta_map, eta_px_map, stats, hip_stream)
 
 
 def fitrig_destroy(ctx) -> int:
@@ -386,12 +391,14 @@ class Context:
         return b
 
     def detect(self, stack, sigma: float, *, cand_cap: int = 1 << 16, index_map=None, eta_map=None,
-               stream=None, raise_on_trunc: bool = False, as_dicts: bool = True):
+               eta_px_map=None, stream=None, raise_on_trunc: bool = False, as_dicts: bool = True):
         """Run the path on ``stack`` ([n][H][W] device tensor, f32/f16/bf16).
 
-        Returns (candidates, stats (dict), status). Candidates are a list of
-        dicts, or with ``as_dicts=False`` a numpy structured array (a copy of
-        the records the library wrote)."""
+        Synchronous: the library runs on torch's current stream (or ``stream``)
+        as an asynchronous call and this method synchronises that stream
+        before reading the results. Returns (candidates, stats (dict),
+        status). Candidates are a list of dicts, or with ``as_dicts=False`` a
+        numpy structured array (a copy of the records the library wrote)."""
         import numpy as np
         import torch
 
@@ -400,18 +407,21 @@ class Context:
         n, H, W = stack.shape
         np_ = max(n - 2, 0)
         b = self._buffers(cand_cap, np_)
-        for m in (index_map, eta_map):
+        for m in (index_map, eta_map, eta_px_map):
             if m is not None and (not m.is_cuda or m.dtype != torch.float32 or not m.is_contiguous()):
                 raise ValueError("maps must be contiguous float32 device tensors")
         if stream is None:
             stream = torch.cuda.current_stream(stack.device)
-        rc = fitrig_detect(self.handle, ctypes.c_void_p(stack.data_ptr()), _dtype_code(stack), n, H, W,
-                           float(sigma), b["cand"], cand_cap, ctypes.byref(b["n"]),
-                           ctypes.c_void_p(index_map.data_ptr()) if index_map is not None else None,
-                           ctypes.c_void_p(eta_map.data_ptr()) if eta_map is not None else None,
-                           ctypes.byref(b["st"]), ctypes.c_void_p(stream.cuda_stream))
-        if rc not in (OK, E_TRUNC) or (rc == E_TRUNC and raise_on_trunc):
+        # a null stream handle (the legacy default stream) makes the call
+        # synchronous on the context's stream; any other stream makes it
+        # asynchronous on that stream
+        rc = self.enqueue(stack, sigma, b, cand_cap, index_map, eta_map, eta_px_map, stream)
+        if rc not in (OK, E_TRUNC):
             raise FitrigError(rc, "fitrig_detect", fitrig_last_hip_error(self.handle))
+        stream.synchronize()
+        rc = b["st"].status
+        if rc == E_TRUNC and raise_on_trunc:
+            raise FitrigError(rc, "fitrig_detect")
         ncand = b["n"].value
         k = min(ncand, cand_cap)
         arr = _cand_array(ctypes.addressof(b["cand"]), k)
@@ -419,8 +429,19 @@ class Context:
         st = b["st"]
         stats = dict(M=st.M, n_triples=st.n_triples, mu=list(b["mu"][:np_]), sigma=list(b["sg"][:np_]),
                      flags=list(b["fl"][:np_]), eta_mu=st.eta_mu, eta_sigma=st.eta_sigma,
-                     n_image_cand=st.n_image_cand, n_freq_cand=st.n_freq_cand, n_cand=ncand)
+                     eta_px_mu=st.eta_px_mu, eta_px_sigma=st.eta_px_sigma, ran=st.ran, eta_flags=st.eta_flags,
+                     n_image_cand=st.n_image_cand, n_freq_cand=st.n_freq_cand,
+                     n_freq_px_cand=st.n_freq_px_cand, n_cand=ncand, status=st.status)
         return cands, stats, rc
+
+    def enqueue(self, stack, sigma, b, cand_cap, index_map, eta_map, eta_px_map, stream) -> int:
+        """The asynchronous C call on ``stream`` with the host buffers ``b``
+        (from ``_buffers``), which must stay alive until the stream has run it."""
+        n, H, W = stack.shape
+        ptr = lambda m: ctypes.c_void_p(m.data_ptr()) if m is not None else None  # noqa: E731
+        return fitrig_detect(self.handle, ctypes.c_void_p(stack.data_ptr()), _dtype_code(stack), n, H, W,
+                             float(sigma), b["cand"], cand_cap, ctypes.byref(b["n"]), ptr(index_map), ptr(eta_map),
+                             ptr(eta_px_map), ctypes.byref(b["st"]), ctypes.c_void_p(stream.cuda_stream))
 
 
 class Server:

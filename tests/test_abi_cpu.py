@@ -83,7 +83,7 @@ def test_create_rejects_bad_config(bad):
 
 def test_detect_rejects_null_context():
     n = ctypes.c_int64(5)
-    rc = F.fitrig_detect(None, ctypes.c_void_p(1), F.F32, 4, 8, 8, 6.0, None, 0, ctypes.byref(n), None, None,
+    rc = F.fitrig_detect(None, ctypes.c_void_p(1), F.F32, 4, 8, 8, 6.0, None, 0, ctypes.byref(n), None, None, None,
                          None, None)
     assert rc == F.E_INVAL
     assert F.fitrig_destroy(None) == F.E_INVAL

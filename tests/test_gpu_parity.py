@@ -19,8 +19,9 @@ def _ctx(**cfg):
     return Context(**cfg)
 
 
-def run_gpu(X, tau, dtype="f32", with_maps=True, cand_cap=1 << 16, **cfg):
-    """X: float32/float64 numpy stack -> (cands, stats, qmap, eta, stack used)."""
+def run_gpu(X, tau, dtype="f32", with_maps=True, cand_cap=1 << 16, eta_px=False, **cfg):
+    """X: float32/float64 numpy stack -> (cands, stats, qmap, eta, stack used, status); with
+    eta_px=True the per-pixel eta map is returned in stats["eta_px_map"]."""
     t = torch.from_numpy(np.ascontiguousarray(X)).to(DT[dtype]).cuda()
     n, H, W = t.shape
     mode = cfg.get("mode", 0)
@@ -31,10 +32,13 @@ def run_gpu(X, tau, dtype="f32", with_maps=True, cand_cap=1 << 16, **cfg):
         qshape = (n - 2, -(-H // tile), -(-W // tile))
     qmap = torch.full(qshape, float("nan"), device="cuda") if with_maps else None
     eta = torch.full((-(-H // tile), -(-W // tile)), float("nan"), device="cuda") if with_maps else None
+    epx = torch.full((H, W), float("nan"), device="cuda") if eta_px else None
     with _ctx(**cfg) as ctx:
-        cands, stats, rc = ctx.detect(t, tau, index_map=qmap, eta_map=eta, cand_cap=cand_cap)
+        cands, stats, rc = ctx.detect(t, tau, index_map=qmap, eta_map=eta, eta_px_map=epx, cand_cap=cand_cap)
     torch.cuda.synchronize()
     used = t.float().cpu().numpy()
+    if eta_px:
+        stats["eta_px_map"] = epx.cpu().numpy()
     return cands, stats, (qmap.cpu().numpy() if with_maps else None), (eta.cpu().numpy() if with_maps else None), used, rc
 
 
@@ -311,29 +315,134 @@ def test_crop_interior_bitwise(w, dt):
         assert a.tobytes() == b.tobytes(), (oy, ox)
 
 
-@pytest.mark.parametrize("n,H,W,window,branches,dtype,sigma_est,harm,with_maps", [
-    (12, 48, 300, 5, 7, "f32", 0, 0, True),     # n' = 10, all three branches
-    (34, 40, 260, 3, 4, "f32", 0, 0, False),    # n' = 32, per-pixel branch alone
-    (66, 30, 130, 5, 5, "f32", 1, 3, False),    # n' = 64, median/MAD, harmonic sum
-    (22, 37, 250, 7, 6, "f16", 0, 0, True),     # FP16 storage
-    (67, 20, 70, 3, 5, "f32", 0, 0, False),     # n' = 65: the per-pixel branch does not run
+@pytest.mark.parametrize("n,H,W,window,branches,dtype,sigma_est,harm", [
+    (12, 48, 300, 5, 7, "f32", 0, 0),     # n' = 10, all three branches
+    (34, 40, 260, 3, 4, "f32", 0, 0),     # n' = 32, per-pixel branch alone
+    (66, 30, 130, 5, 5, "f32", 1, 3),     # n' = 64, median/MAD, harmonic sum
+    (22, 37, 250, 7, 6, "f16", 0, 0),     # FP16 storage
+    (67, 20, 70, 3, 5, "f32", 0, 0),      # n' = 65
+    (128, 16, 90, 3, 4, "f32", 0, 0),     # n' = 126, the longest serving request
+    (129, 13, 37, 1, 4, "f32", 0, 2),     # n' = 127 (odd), harmonic sum, H*W not a multiple of 4
+    (34, 300, 700, 9, 5, "f32", 0, 0),    # 3282 tiles of 64 pixels
+    (34, 300, 700, 9, 5, "bf16", 1, 0),   # median/MAD of eta on a large map
 ])
-def test_per_pixel_frequency_branch(n, H, W, window, branches, dtype, sigma_est, harm, with_maps):
+def test_per_pixel_frequency_branch(n, H, W, window, branches, dtype, sigma_est, harm):
+    """Per-pixel spectra (Eq. (10) per cell) against the oracle element by
+    element: eta within 1e-5 eta, its mean and spread within 1e-6, the
+    candidates by component."""
     rng = np.random.default_rng(n * 7 + H)
     X = structured_stack(n + H, n, H, W)
-    y0, x0 = int(rng.integers(5, H - 8)), int(rng.integers(5, W - 8))
+    y0, x0 = int(rng.integers(min(5, H - 4), H - 3)), int(rng.integers(5, W - 8))
     X[1::5, y0:y0 + 3, x0:x0 + 3] += 9.0
     tau = 4.0
-    cands, stats, q, eta, used, rc = run_gpu(X, tau, dtype=dtype, with_maps=with_maps, window=window,
-                                             branches=branches, sigma_est=sigma_est, harm=harm, tile=16)
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, dtype=dtype, window=window, branches=branches,
+                                             sigma_est=sigma_est, harm=harm, tile=16, eta_px=True)
     assert rc == 0
     out = ref.detect(used, tau=tau, window=window, branches=branches, sigma_est=sigma_est, harm=harm, tile=16,
                      keep_maps=True)
-    if with_maps and branches & ref.IMAGE:
+    assert stats["ran"] & ref.FREQ_PIXEL
+    if branches & ref.IMAGE:
         check_maps(q, out["q"])
+    check_eta(stats["eta_px_map"], out["eta_px"])
+    assert stats["eta_px_mu"] == pytest.approx(out["eta_px_mu"], rel=1e-6)
+    assert stats["eta_px_sigma"] == pytest.approx(out["eta_px_sigma"], rel=1e-6)
     check_candidates(cands, out, tau)
     px = [c for c in cands if c["branch"] == ref.FREQ_PIXEL]
-    if out["eta_px"] is None:
-        assert not px
-    else:
-        assert px and all(c["triple"] == -1 for c in px)
+    assert px and all(c["triple"] == -1 for c in px)
+    assert stats["n_freq_px_cand"] == len(px)
+
+
+def test_per_pixel_branch_needs_four_triples():
+    """With n' = 3 the frequency branches do not run, and say so."""
+    X = structured_stack(5, 5, 20, 30)
+    cands, stats, q, eta, used, rc = run_gpu(X, 3.0, window=3, branches=7, eta_px=True)
+    assert rc == 0
+    assert stats["ran"] == ref.IMAGE
+    assert not [c for c in cands if c["branch"] != ref.IMAGE]
+
+
+def test_per_pixel_series_limit_is_an_error():
+    """A harmonic sum over a per-pixel series longer than the kernel's LDS
+    table allows is refused, never skipped."""
+    from paper_2509_21754_amd import FitrigError
+
+    X = np.random.default_rng(7).normal(size=(452, 4, 8)).astype(np.float32)
+    with pytest.raises(FitrigError):
+        run_gpu(X, 3.0, window=3, branches=4, harm=2, with_maps=False)
+    # the same length with h = max runs
+    cands, stats, *_ = run_gpu(X, 3.0, window=3, branches=4, harm=0, with_maps=False)
+    assert stats["ran"] == ref.FREQ_PIXEL
+
+
+@pytest.mark.parametrize("mode,branches", [(0, 2), (1, 2), (0, 4)])
+def test_index_map_written_without_image_branch(mode, branches):
+    """The index map is written whenever it is requested."""
+    X = structured_stack(17, 8, 40, 96)
+    cands, stats, q, eta, used, rc = run_gpu(X, 3.0, window=5, mode=mode, tile=8, branches=branches)
+    want = ref.index_maps(used, mode=mode, window=5, tile=8)
+    check_maps(q, want)
+
+
+def test_async_call_on_a_stream():
+    """A call on a non-null stream returns at once; after the stream is
+    synchronised its outputs equal the synchronous call's."""
+    import ctypes
+
+    from paper_2509_21754_amd import Context
+
+    X = structured_stack(23, 12, 96, 400)
+    t = torch.from_numpy(X).cuda()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with Context(window=7) as ctx:
+        sync = ctx.detect(t, 4.0, as_dicts=False)
+        b = ctx._buffers(1 << 16, 10)
+        rc = ctx.enqueue(t, 4.0, b, 1 << 16, None, None, None, s)
+        assert rc == 0
+        s.synchronize()
+        n = b["n"].value
+        got = np.ctypeslib.as_array((ctypes.c_uint8 * (n * 72)).from_address(ctypes.addressof(b["cand"]))).copy()
+        assert n == len(sync[0]) and got.tobytes() == sync[0].tobytes()
+        assert list(b["mu"][:10]) == sync[1]["mu"] and b["st"].status == 0
+
+
+def test_graph_capture_replays_bitwise():
+    """The MEAN_STD image + frequency path captured into a HIP graph: three
+    replays, with eager work and synchronisations between them, each equal
+    byte for byte to the eager call."""
+    import ctypes
+
+    from paper_2509_21754_amd import Context
+
+    X = structured_stack(29, 14, 150, 700)
+    for k in range(2, 14, 4):
+        X[k, 60:67, 300:307] += 30.0
+    t = torch.from_numpy(X).cuda()
+    qmap = torch.zeros((12, 150, 700), device="cuda")
+    torch.cuda.synchronize()
+    with Context(window=7, max_pixels=150 * 700, max_snap=14) as ctx:
+        ref_c, ref_st, _ = ctx.detect(t, 4.0, index_map=qmap, as_dicts=False)
+        q_ref = qmap.clone()
+        assert len(ref_c) > 0
+        s = torch.cuda.Stream()
+        b = ctx._buffers(1 << 16, 12)
+        with torch.cuda.stream(s):
+            assert ctx.enqueue(t, 4.0, b, 1 << 16, qmap, None, None, s) == 0   # warm, outside the graph
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            assert ctx.enqueue(t, 4.0, b, 1 << 16, qmap, None, None, s) == 0
+        for rep in range(3):
+            qmap.fill_(float("nan"))
+            b["n"].value = -1
+            junk = (t[:3] * 2.0).sum()          # eager work between replays
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            n = b["n"].value
+            got = np.ctypeslib.as_array((ctypes.c_uint8 * (n * 72)).from_address(ctypes.addressof(b["cand"]))).copy()
+            assert n == len(ref_c) and got.tobytes() == ref_c.tobytes(), rep
+            assert torch.equal(qmap, q_ref), rep
+            assert list(b["mu"][:12]) == ref_st["mu"] and list(b["sg"][:12]) == ref_st["sigma"], rep
+            del junk
+        del g
