@@ -500,11 +500,15 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
   return FITRIG_OK;
 }
 
-// Deterministic compaction: count, scan, write.
+// Deterministic compaction: count, scan, write. The element count is read on
+// the device (ne_dyn, at most cap * mult entries); the grid and the chunk
+// counts are sized from that bound. The bound, not the pointer, decides the
+// size: in the sizing pass of a fresh context the counters are not allocated
+// yet and ne_dyn may be a null offset.
 template <class F, class E>
 fitrig_status compact(fitrig_ctx* ctx, hipStream_t st, F f, E e, int64_t ne_static, const int64_t* ne_dyn,
                       int64_t cap, int mult, int64_t* total) {
-  const int64_t ne_max = ne_dyn ? cap * mult : ne_static;
+  const int64_t ne_max = cap > 0 ? cap * mult : ne_static;
   const int64_t nch = std::max<int64_t>(1, (ne_max + kChunk - 1) / kChunk);
   fitrig_status rc;
   if ((rc = ensure(ctx, ctx->chunk_cnt, (size_t)nch * 4)) != FITRIG_OK) return rc;
