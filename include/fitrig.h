@@ -45,6 +45,7 @@ typedef int32_t fitrig_status;
 #define FITRIG_E_TRUNC (-4)   /* more results than the given or internal capacity */
 #define FITRIG_E_BUSY (-5)    /* serving: admission refused on a non-blocking submit */
 #define FITRIG_E_NOTREADY (-6)/* serving: result not ready on a non-blocking poll */
+#define FITRIG_E_SCRATCH (-7) /* fitrig_detect_noalloc: the call needs more than FITRIG_NOALLOC_SCRATCH_BYTES */
 
 typedef enum { FITRIG_F32 = 0, FITRIG_F16 = 1, FITRIG_BF16 = 2 } fitrig_dtype;
 
@@ -183,6 +184,39 @@ fitrig_status fitrig_detect(fitrig_ctx* ctx, const void* stack, fitrig_dtype dty
                             fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand,
                             float* index_map, float* eta_map, float* eta_px_map,
                             fitrig_stats* stats, void* hip_stream);
+
+/*
+ * Allocation-free variant of fitrig_detect, for callers that cannot allocate
+ * device memory during a call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). It runs the same kernels on the
+ * same arguments and writes the same outputs as fitrig_detect, but its
+ * scratch, including the packed device results, is carved from one static
+ * device array of FITRIG_NOALLOC_SCRATCH_BYTES per GPU that the library
+ * holds until the process ends (its address on ctx's device is taken once,
+ * at fitrig_create). The call allocates nothing: no hipMalloc, hipFree or
+ * pinned host memory, and none of the context's own buffers are used or
+ * grown.
+ *   Arguments as fitrig_detect. The call is always synchronous: it runs on
+ *   hip_stream (NULL = the context's stream) and returns when every output
+ *   is written (host outputs are copied from the device results).
+ *   Limit: everything one call needs beyond its inputs and outputs must fit
+ *   in FITRIG_NOALLOC_SCRATCH_BYTES (the default selection capacity alone
+ *   takes about 90 MB; the median/MAD spread and per-pixel spectra also
+ *   need an [n_snap-2][H][W] float map unless index_map is given). A larger
+ *   call returns E_SCRATCH and enqueues nothing.
+ *   Sharing: every call on a GPU uses that GPU's one array, which keeps the
+ *   last call's contents; each call clears what it needs zeroed. Calls that
+ *   overlap on one GPU would race on the array, so the library serialises
+ *   them per device with a lock held for the whole call.
+ * Returns OK or E_TRUNC as fitrig_detect. Errors: E_INVAL (as fitrig_detect),
+ * E_SCRATCH, E_HIP (including a failed lookup of the array's address).
+ */
+#define FITRIG_NOALLOC_SCRATCH_BYTES (256ull << 20)
+fitrig_status fitrig_detect_noalloc(fitrig_ctx* ctx, const void* stack, fitrig_dtype dtype,
+                                    int32_t n_snap, int32_t H, int32_t W, double sigma,
+                                    fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand,
+                                    float* index_map, float* eta_map, float* eta_px_map,
+                                    fitrig_stats* stats, void* hip_stream);
 
 /* Releases the context and its device memory. Errors: E_INVAL (null). */
 fitrig_status fitrig_destroy(fitrig_ctx* ctx);

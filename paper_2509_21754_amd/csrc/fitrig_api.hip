@@ -32,9 +32,40 @@
 #include "fitrig_internal.h"
 #include "fitrig_kernels.hip"
 
+// Scratch of the allocation-free entry (fitrig_detect_noalloc): one array in
+// the library's device code, so each GPU the library runs on holds its own
+// copy until the process ends. Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): it uses the
+// per-device address taken with hipGetSymbolAddress at fitrig_create.
+static __device__ __align__(256) char scratch[FITRIG_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 using namespace fitrig;
+
+// Device address of `scratch` on each device (null until set up), the HIP
+// error of a failed lookup, and a lock per device that serialises the
+// allocation-free calls sharing that device's array.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_setup_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+int32_t g_scratch_err[kMaxDevices] = {};
+std::mutex g_scratch_call_mu[kMaxDevices];
+
+// Once per device, with that device current.
+void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_setup_mu);
+  if (g_scratch_ptr[dev]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) {
+    g_scratch_ptr[dev] = p;
+    g_scratch_err[dev] = 0;
+  } else {
+    g_scratch_err[dev] = e != hipSuccess ? (int32_t)e : (int32_t)hipErrorInvalidSymbol;
+  }
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -155,7 +186,7 @@ fitrig_status provision(fitrig_ctx* ctx, hipStream_t st) {
       b.cap = b.want;
       off += b.want;
     }
-    return off <= ctx->arena_cap ? FITRIG_OK : FITRIG_E_INVAL;
+    return off <= ctx->arena_cap ? FITRIG_OK : FITRIG_E_SCRATCH;
   }
   bool grow = ctx->h_want > ctx->h_stage_cap;
   for (DevBuf fitrig_ctx::* m : kBufs) grow = grow || (ctx->*m).want > (ctx->*m).cap;
@@ -998,23 +1029,22 @@ fitrig_status enqueue_results(fitrig_ctx* ctx, const Call& c, char* dst, const R
   return FITRIG_OK;
 }
 
-// Host outputs from the packed results (after the stream reached them).
-fitrig_status unpack_results(const char* h, const ResultLayout& R, int np, uint32_t ran, fitrig_candidate* cand,
-                             int64_t cand_cap, int64_t* n_cand, fitrig_stats* stats, double* mu_o, double* sg_o,
-                             uint32_t* fl_o) {
-  const int64_t* cnt = (const int64_t*)(h + R.off_cnt);
-  const double* sc = (const double*)(h + R.off_scalars);
+// Host outputs from the results (after the stream reached them): counters
+// cnt, scalars sc (M, then the frequency statistics), per-triple hmu, hsg,
+// hfl and the candidate records hcand. A piece may already be the caller's
+// array (the allocation-free entry copies into them directly).
+fitrig_status unpack_pieces(const int64_t* cnt, const double* sc, const double* hmu, const double* hsg,
+                            const uint32_t* hfl, const fitrig_candidate* hcand, int np, uint32_t ran,
+                            fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand, fitrig_stats* stats,
+                            double* mu_o, double* sg_o, uint32_t* fl_o) {
   const int64_t total = cnt[CNT_OUTBASE];
   const bool trunc_internal = cnt[CNT_TRUNC] != 0;
   const int64_t ncopy = std::min<int64_t>(total, cand_cap);
-  if (ncopy > 0 && cand) memcpy(cand, h + R.off_cand, (size_t)ncopy * sizeof(fitrig_candidate));
+  if (ncopy > 0 && cand && cand != hcand) memcpy(cand, hcand, (size_t)ncopy * sizeof(fitrig_candidate));
   *n_cand = total;
   const fitrig_status status = (trunc_internal || total > cand_cap) ? FITRIG_E_TRUNC : FITRIG_OK;
   if (stats) {
     const bool img = (ran & FITRIG_IMAGE) != 0;
-    const double* hmu = (const double*)(h + R.off_mu);
-    const double* hsg = (const double*)(h + R.off_sigma);
-    const uint32_t* hfl = (const uint32_t*)(h + R.off_flags);
     const uint32_t* ef = (const uint32_t*)(sc + 1 + ES_FLAGS);
     stats->M = sc[0];
     stats->n_triples = np;
@@ -1036,6 +1066,16 @@ fitrig_status unpack_results(const char* h, const ResultLayout& R, int np, uint3
     }
   }
   return status;
+}
+
+// Host outputs from the packed results in host-visible memory h.
+fitrig_status unpack_results(const char* h, const ResultLayout& R, int np, uint32_t ran, fitrig_candidate* cand,
+                             int64_t cand_cap, int64_t* n_cand, fitrig_stats* stats, double* mu_o, double* sg_o,
+                             uint32_t* fl_o) {
+  return unpack_pieces((const int64_t*)(h + R.off_cnt), (const double*)(h + R.off_scalars),
+                       (const double*)(h + R.off_mu), (const double*)(h + R.off_sigma),
+                       (const uint32_t*)(h + R.off_flags), (const fitrig_candidate*)(h + R.off_cand), np, ran, cand,
+                       cand_cap, n_cand, stats, mu_o, sg_o, fl_o);
 }
 
 void async_done(void* p) {
@@ -1070,7 +1110,8 @@ fitrig_status sizing_pass(fitrig_ctx* ctx, const Call& c, size_t result_bytes) {
   clear_wants(ctx);
   ctx->sizing = true;
   fitrig_status rc = enqueue(ctx, c, true);
-  if (rc == FITRIG_OK) rc = ensure_host(ctx, result_bytes);
+  // results: host-visible memory, or (allocation-free entry) device scratch
+  if (rc == FITRIG_OK) rc = ctx->in_arena ? ensure(ctx, ctx->res_dev, result_bytes) : ensure_host(ctx, result_bytes);
   ctx->sizing = false;
   ctx->seg_cap = seg_cap;
   ctx->comp_cap = comp_cap;
@@ -1174,6 +1215,78 @@ fitrig_status presize(fitrig_ctx* ctx) {
   return provision(ctx, ctx->stream);
 }
 
+// The allocation-free call: the context's own buffers are set aside, the
+// call's scratch (and its device results) is carved from this device's
+// static array, and the results are copied into the caller's host memory.
+fitrig_status detect_noalloc_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand, int64_t* n_cand,
+                                  fitrig_stats* stats) {
+  const int dev = ctx->cfg.device;
+  if (dev < 0 || dev >= kMaxDevices) return FITRIG_E_INVAL;
+  void* base = g_scratch_ptr[dev];
+  if (!base) {
+    ctx->last_hip = g_scratch_err[dev];
+    return FITRIG_E_HIP;
+  }
+  fitrig_status rc = check_shape(ctx->cfg, c);
+  if (rc != FITRIG_OK) return rc;
+  const int np = c.n - 2;
+  const int64_t cap = c.cand_cap;
+  const ResultLayout R = result_layout(np, cap);
+  std::lock_guard<std::mutex> lk(g_scratch_call_mu[dev]);
+  DevBuf saved[kNBufs];
+  for (size_t i = 0; i < kNBufs; ++i) saved[i] = ctx->*kBufs[i];
+  const int64_t seg_cap = ctx->seg_cap, comp_cap = ctx->comp_cap;
+  ctx->seg_cap = ctx->comp_cap = 0;
+  ctx->in_arena = true;
+  ctx->arena = (char*)base;
+  ctx->arena_cap = FITRIG_NOALLOC_SCRATCH_BYTES;
+  int64_t hcnt[CNT_N] = {};
+  double hsc[1 + ES_N] = {};
+  const uint32_t ran = branches_ran(ctx->cfg, c);
+  auto run = [&]() -> fitrig_status {
+    fitrig_status r = sizing_pass(ctx, c, (size_t)R.bytes);
+    if (r != FITRIG_OK) return r;
+    if ((r = provision(ctx, c.st)) != FITRIG_OK) return r;
+    if ((r = enqueue(ctx, c, true)) != FITRIG_OK) return r;
+    const char* res = (const char*)ctx->res_dev.p;
+    if ((r = enqueue_results(ctx, c, (char*)ctx->res_dev.p, R, cap)) != FITRIG_OK) return r;
+    HIP_TRY(ctx, hipMemcpyAsync(hcnt, res + R.off_cnt, sizeof(hcnt), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(ctx, hipMemcpyAsync(hsc, res + R.off_scalars, sizeof(hsc), hipMemcpyDeviceToHost, c.st));
+    if (stats && np > 0) {
+      if (stats->mu)
+        HIP_TRY(ctx, hipMemcpyAsync(stats->mu, res + R.off_mu, (size_t)np * 8, hipMemcpyDeviceToHost, c.st));
+      if (stats->sigma)
+        HIP_TRY(ctx, hipMemcpyAsync(stats->sigma, res + R.off_sigma, (size_t)np * 8, hipMemcpyDeviceToHost, c.st));
+      if (stats->flags)
+        HIP_TRY(ctx, hipMemcpyAsync(stats->flags, res + R.off_flags, (size_t)np * 4, hipMemcpyDeviceToHost, c.st));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(c.st));
+    const int64_t ncopy = std::min<int64_t>(hcnt[CNT_OUTBASE], cap);
+    if (ncopy > 0 && cand) {
+      HIP_TRY(ctx, hipMemcpyAsync(cand, res + R.off_cand, (size_t)ncopy * sizeof(fitrig_candidate),
+                                  hipMemcpyDeviceToHost, c.st));
+      HIP_TRY(ctx, hipStreamSynchronize(c.st));
+    }
+    return FITRIG_OK;
+  };
+  rc = run();
+  if (rc != FITRIG_OK) {
+    // nothing of a failed call may still use the array when it is released
+    // to the next call (and the caller's buffers must be settled)
+    (void)hipStreamSynchronize(c.st);
+  }
+  for (size_t i = 0; i < kNBufs; ++i) ctx->*kBufs[i] = saved[i];
+  ctx->seg_cap = seg_cap;
+  ctx->comp_cap = comp_cap;
+  ctx->in_arena = false;
+  ctx->arena = nullptr;
+  ctx->arena_cap = 0;
+  if (rc != FITRIG_OK) return rc;
+  return unpack_pieces(hcnt, hsc, stats ? stats->mu : nullptr, stats ? stats->sigma : nullptr,
+                       stats ? stats->flags : nullptr, cand, np, ran, cand, cap, n_cand, stats,
+                       stats ? stats->mu : nullptr, stats ? stats->sigma : nullptr, stats ? stats->flags : nullptr);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1217,6 +1330,7 @@ const char* fitrig_status_string(fitrig_status s) {
     case FITRIG_E_TRUNC: return "results truncated (capacity exceeded)";
     case FITRIG_E_BUSY: return "admission refused (busy)";
     case FITRIG_E_NOTREADY: return "result not ready";
+    case FITRIG_E_SCRATCH: return "the call needs more scratch than the allocation-free entry's static array holds";
     default: return "unknown status";
   }
 }
@@ -1242,6 +1356,9 @@ fitrig_status fitrig_create(const fitrig_config* cfg, fitrig_ctx** out) {
     fitrig_destroy(ctx);
     return FITRIG_E_HIP;
   }
+  // address of the allocation-free entry's array on this device (once per
+  // device; a failed lookup shows only in that entry, as E_HIP)
+  scratch_setup(cfg->device);
   // scratch sized from the capacity hints, so warm calls allocate nothing
   if ((rc = presize(ctx)) != FITRIG_OK) {
     fitrig_destroy(ctx);
@@ -1293,6 +1410,34 @@ fitrig_status fitrig_detect(fitrig_ctx* ctx, const void* stack, fitrig_dtype dty
   c.hist = nullptr;
   c.cand_cap = cand_cap;
   return detect_impl(ctx, c, cand, n_cand, stats, hip_stream != nullptr);
+}
+
+fitrig_status fitrig_detect_noalloc(fitrig_ctx* ctx, const void* stack, fitrig_dtype dtype, int32_t n_snap,
+                                    int32_t H, int32_t W, double sigma, fitrig_candidate* cand, int64_t cand_cap,
+                                    int64_t* n_cand, float* index_map, float* eta_map, float* eta_px_map,
+                                    fitrig_stats* stats, void* hip_stream) {
+  if (!ctx) return FITRIG_E_INVAL;
+  fitrig_status rc = check_args(stack, dtype, H, W, sigma, cand, cand_cap, n_cand);
+  if (rc != FITRIG_OK) return rc;
+  if (n_snap < 3) return FITRIG_E_INVAL;
+  *n_cand = 0;
+  if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FITRIG_E_HIP;
+  Call c;
+  c.stack = stack;
+  c.carry0 = c.carry1 = nullptr;
+  c.ncarry = 0;
+  c.dtype = dtype;
+  c.n = n_snap;
+  c.H = H;
+  c.W = W;
+  c.tau = sigma;
+  c.index_map = index_map;
+  c.eta_map = eta_map;
+  c.eta_px_map = eta_px_map;
+  c.st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+  c.hist = nullptr;
+  c.cand_cap = cand_cap;
+  return detect_noalloc_impl(ctx, c, cand, n_cand, stats);
 }
 
 }  // extern "C"

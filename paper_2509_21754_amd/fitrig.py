@@ -16,7 +16,8 @@ from typing import Optional
 
 ABI_VERSION = 3
 
-OK, E_INVAL, E_NOMEM, E_HIP, E_TRUNC, E_BUSY, E_NOTREADY = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVAL, E_NOMEM, E_HIP, E_TRUNC, E_BUSY, E_NOTREADY, E_SCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
+NOALLOC_SCRATCH_BYTES = 256 << 20
 F32, F16, BF16 = 0, 1, 2
 SLIDING, TILES = 0, 1
 IMAGE, FREQ, FREQ_PIXEL = 1, 2, 4
@@ -119,6 +120,7 @@ EXPORTS = (
     "fitrig_config_default",
     "fitrig_create",
     "fitrig_detect",
+    "fitrig_detect_noalloc",
     "fitrig_destroy",
     "fitrig_status_string",
     "fitrig_last_hip_error",
@@ -154,6 +156,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fitrig_detect.argtypes = [vp, vp, i32, i32, i32, i32, dbl, ctypes.POINTER(fitrig_candidate), i64,
                                 ctypes.POINTER(i64), vp, vp, vp, ctypes.POINTER(fitrig_stats), vp]
     L.fitrig_detect.restype = i32
+    L.fitrig_detect_noalloc.argtypes = L.fitrig_detect.argtypes
+    L.fitrig_detect_noalloc.restype = i32
     L.fitrig_destroy.argtypes = [vp]
     L.fitrig_destroy.restype = i32
     L.fitrig_status_string.argtypes = [i32]
@@ -204,6 +208,12 @@ def fitrig_detect(ctx, stack_ptr, dtype, n_snap, H, W, sigma, cand, cand_cap, n_
                   eta_px_map, stats, hip_stream) -> int:
     return load().fitrig_detect(ctx, stack_ptr, dtype, n_snap, H, W, sigma, cand, cand_cap, n_cand, index_map,
                                 eta_map, eta_px_map, stats, hip_stream)
+
+
+def fitrig_detect_noalloc(ctx, stack_ptr, dtype, n_snap, H, W, sigma, cand, cand_cap, n_cand, index_map, eta_map,
+                          eta_px_map, stats, hip_stream) -> int:
+    return load().fitrig_detect_noalloc(ctx, stack_ptr, dtype, n_snap, H, W, sigma, cand, cand_cap, n_cand,
+                                        index_map, eta_map, eta_px_map, stats, hip_stream)
 
 
 def fitrig_destroy(ctx) -> int:

@@ -60,7 +60,7 @@ def test_struct_layout_matches_header(tmp_path):
 def test_status_strings_and_version():
     assert F.fitrig_abi_version() == F.ABI_VERSION
     assert F.fitrig_status_string(F.OK) == "ok"
-    for code in (F.E_INVAL, F.E_NOMEM, F.E_HIP, F.E_TRUNC, F.E_BUSY, F.E_NOTREADY):
+    for code in (F.E_INVAL, F.E_NOMEM, F.E_HIP, F.E_TRUNC, F.E_BUSY, F.E_NOTREADY, F.E_SCRATCH):
         assert F.fitrig_status_string(code) not in ("ok", "unknown status")
     assert F.fitrig_status_string(-99) == "unknown status"
 
@@ -120,3 +120,11 @@ def test_interp_peaks_rejects_bad_arguments_on_cpu():
     assert call(None, 4, 8, p(py), p(px), 1, F.INTERP_SPLINE, 16, p(out), None) == F.E_INVAL
     assert call(dummy, 0, 8, p(py), p(px), 1, F.INTERP_SPLINE, 16, p(out), None) == F.E_INVAL
     assert call(dummy, 4, 8, None, None, 0, F.INTERP_SPLINE, 16, None, None) == F.OK   # nothing to do
+
+
+def test_noalloc_scratch_limit_matches_header():
+    txt = open(HEADER).read()
+    m = re.search(r"#define FITRIG_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == F.NOALLOC_SCRATCH_BYTES
+    m = re.search(r"#define FITRIG_E_SCRATCH \((-\d+)\)", txt)
+    assert m and int(m.group(1)) == F.E_SCRATCH
