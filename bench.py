@@ -57,22 +57,59 @@ def stored_traffic(workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    """CPU model name of this host (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(spec_name: str) -> dict:
-    """The oracle as it stands on a bounded sample of the same recipe."""
+    """The oracle as it stands, timed on bounded samples of the same recipe:
+    on every host thread the process may use (the reported value) and on one
+    thread (a smaller sample, scaled to the same unit)."""
     import synth
     from oracle import ref
 
     base = synth.WORKLOADS[spec_name]
-    H, W, n = (4096, 2048, 12) if base.H >= 4096 else (base.H, base.W, base.n)
-    spec = synth.spec(spec_name, H=H, W=W, n=n) if (H, W) != (base.H, base.W) else base
-    X = synth.make_stack(spec).float().numpy()
-    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-    t0 = time.perf_counter()
-    ref.detect(X, tau=spec.taus[0], window=spec.window, keep_maps=False)
-    dt = time.perf_counter() - t0
-    return {"value": round(n * H * W / dt / 1e6, 3), "unit": "Mpix/s", "cores": threads, "kind": "oracle",
-            "sample": f"{H}x{W} px x {n} snapshots of the {spec_name} recipe (window {spec.window}), "
-                      f"full detect incl. frequency branch, {dt:.2f} s"}
+
+    def run(H, W, n, threads):
+        spec = synth.spec(spec_name, H=H, W=W, n=n) if (H, W, n) != (base.H, base.W, base.n) else base
+        X = synth.make_stack(spec).float().numpy()
+        used = ref.set_threads(threads)
+        t0 = time.perf_counter()
+        ref.detect(X, tau=spec.taus[0], window=spec.window, keep_maps=False)
+        dt = time.perf_counter() - t0
+        return n * H * W / dt / 1e6, dt, used, spec
+
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = int(os.environ.get("OMP_NUM_THREADS") or threads)
+    big = (4096, 2048, 12) if base.H >= 4096 else (base.H, base.W, base.n)
+    small = (1024, 1024, 12) if base.H >= 4096 else (base.H, base.W, base.n)
+    v_all, dt_all, used_all, spec = run(*big, threads)
+    v_one, dt_one, _, _ = run(*small, 1)
+    ref.set_threads(threads)
+    return {"value": round(v_all, 3), "unit": "Mpix/s", "cores": used_all, "kind": "oracle",
+            "sample": f"{big[0]}x{big[1]} px x {big[2]} snapshots of the {spec_name} recipe (window {spec.window}), "
+                      f"full detect incl. frequency branch, {dt_all:.2f} s on {used_all} threads",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": round(v_one, 3), "unit": "Mpix/s", "cores": 1,
+                              "sample": f"{small[0]}x{small[1]} px x {small[2]} snapshots, same recipe, "
+                                        f"{dt_one:.2f} s on 1 thread"}}
 
 
 def pulsar_recall(cands, spec) -> dict:
@@ -304,7 +341,8 @@ def serving_replay(n_req: int, slots: int, rate_hz: float, budget_gib: float, de
         d = {"mpix_s": round(px / ((last - first) / 1e9) / 1e6, 1), "wall_s": round(wall, 3),
              "p50_ms": round(pctl(lat, 0.5), 3), "p99_ms": round(pctl(lat, 0.99), 3),
              "queue_wait_p50_ms": round(pctl(wait, 0.5), 3), "errors": len(bad),
-             "freq_branch_runs": sum(1 for o, _ in res if o["freq_triples"] > 0)}
+             "freq_branch_runs": sum(1 for o, _ in res if o["freq_triples"] > 0),
+             "graph_replays": sum(1 for o, _ in res if o.get("replayed"))}
         for dt in ("f16", "f32"):
             l2 = [x for x, (_, r) in zip(lat, res) if r["dtype"] == dt]
             pxd = [r["n"] * r["size"] ** 2 for _, r in res if r["dtype"] == dt]

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define FITRIG_ABI_VERSION 3
+#define FITRIG_ABI_VERSION 4
 
 typedef int32_t fitrig_status;
 #define FITRIG_OK 0
@@ -292,12 +292,23 @@ fitrig_status fitrig_interp_peaks(const float* map, int32_t H, int32_t W, const 
 typedef struct fitrig_server fitrig_server;
 
 typedef struct {
-  fitrig_config base;   /* index / selection settings of every request; its
-                           capacity hints size each slot's scratch up front */
+  fitrig_config base;   /* index / selection settings of every request. With
+                           capacity hints (max_pixels > 0, max_snap >= 3) every
+                           slot's scratch is sized at create for a square image
+                           of max_pixels with max_snap new frames and the
+                           longest history, so such requests run without
+                           allocating. A slot that meets a larger request grows
+                           (waiting for its own stream only) and keeps that
+                           scratch. */
   int32_t n_slots;      /* requests on the device at once (default 4) */
   int32_t max_fields;   /* fields with resident state (default 64); a new field
                            beyond it evicts the least recently used idle field */
-  int64_t mem_budget;   /* device bytes for slot scratch plus field state; 0 = no limit */
+  int64_t mem_budget;   /* device bytes for slot scratch plus field state; 0 = no limit.
+                           Admission bounds the device use: resident field state
+                           plus, per slot, the larger of the scratch it holds
+                           (sized from the base capacity hints at create, grown
+                           to the largest request it ran) and the exact scratch
+                           of the largest queued or running request */
   int64_t cand_cap;     /* candidates kept per result (default 65536) */
   int32_t freq_window;  /* 0 (default): a request's frequency branch covers its
                            own triples; 1..2048: it covers the field's last
@@ -307,6 +318,10 @@ typedef struct {
                            covered series has at least 4 triples. The
                            per-pixel branch (FITRIG_FREQ_PIXEL) always covers
                            the request's own triples. */
+  int32_t graphs;       /* 1 (default): each slot captures its launch sequence
+                           into a HIP graph per request shape (frames, size,
+                           dtype, carried frames, history length) and replays
+                           it; 0: direct launches */
 } fitrig_server_config;
 
 typedef struct {
@@ -322,6 +337,7 @@ typedef struct {
   int32_t freq_triples;     /* triples the frequency branch covered: the field's
                                triples first_triple + n_triples - freq_triples ..
                                first_triple + n_triples - 1 (0 = it did not run) */
+  int32_t replayed;         /* 1: the request ran as a replay of a captured graph */
 } fitrig_result;
 
 /* Fills cfg with the defaults above. */
@@ -329,11 +345,15 @@ void fitrig_server_config_default(fitrig_server_config* cfg);
 
 /* Creates the server: one context and stream per slot, worker threads.
  * Errors: E_INVAL (null, bad base config, n_slots < 1, max_fields < 1,
- * cand_cap < 0, mem_budget < 0, freq_window outside 0..2048), E_NOMEM, E_HIP. */
+ * cand_cap < 0, mem_budget < 0, freq_window outside 0..2048, graphs not 0 or
+ * 1), E_NOMEM (also: the slots' scratch sized from the capacity hints alone
+ * exceeds mem_budget), E_HIP. */
 fitrig_status fitrig_server_create(const fitrig_server_config* cfg, fitrig_server** out);
 
 /* Submits a stack (device, [n_snap][H][W], must stay valid and unchanged
- * until the request is done). A field keeps its size and dtype; a request of
+ * until the request is done; work queued on the legacy default stream before
+ * the submit, where the stack may have been written, completes before the
+ * request reads it). A field keeps its size and dtype; a request of
  * another size or dtype resets the field's state. blocking = 1 waits for
  * admission; blocking = 0 returns E_BUSY when the request does not fit now.
  * *ticket identifies the request.

@@ -47,6 +47,9 @@
  *     with terms beyond floor(n'/2) dropped.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -387,3 +390,21 @@ int ref_eta(const double* cube, int nprime, int64_t ntiles, int harm,
 }
 
 int ref_abi_version(void) { return 1; }
+
+/* Threads of the OpenMP loops (for timing the oracle at a given core count;
+ * the arithmetic does not depend on it). */
+void ref_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int ref_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -78,6 +78,10 @@ def lib():
         L = ctypes.CDLL(_LIB)
         vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
         L.ref_pixel_terms.argtypes = [vp, i32, i32, i64, i64, i32, i32, dbl, vp, vp]
+        L.ref_set_threads.argtypes = [i32]
+        L.ref_set_threads.restype = None
+        L.ref_max_threads.argtypes = []
+        L.ref_max_threads.restype = i32
         L.ref_normaliser.argtypes = [vp, i32, i64, dbl]
         L.ref_normaliser.restype = dbl
         L.ref_index_maps.argtypes = [vp, i32, i32, i64, i64, i32, i32, i32, i32, dbl, vp]
@@ -258,3 +262,10 @@ def detect(stack, *, tau: float = 6.0, mode: int = SLIDING, window: int = 7,
                 c.update(branch=FREQ_PIXEL, triple=-1)
                 out["cands"].append(c)
     return out
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops from now on; returns the count in effect."""
+    L = lib()
+    L.ref_set_threads(int(n))
+    return int(L.ref_max_threads())

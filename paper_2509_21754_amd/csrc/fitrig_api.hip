@@ -26,6 +26,8 @@
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "fitrig.h"
@@ -90,6 +92,23 @@ struct AsyncOut {
   bool captured;  // recorded into a graph: replays reuse it, freed with the context
 };
 
+// A launch sequence captured for one call shape (serving slots).
+struct GraphKey {
+  int n, H, W, ncarry, dtype, hist_cap, hist_n_in, hist_out;
+  int64_t cand_cap;
+  bool operator==(const GraphKey& o) const {
+    return n == o.n && H == o.H && W == o.W && ncarry == o.ncarry && dtype == o.dtype && hist_cap == o.hist_cap &&
+           hist_n_in == o.hist_n_in && hist_out == o.hist_out && cand_cap == o.cand_cap;
+  }
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+  uint64_t gen;
+  int64_t last_use;
+};
+constexpr size_t kMaxGraphs = 64;
+
 }  // namespace
 
 struct fitrig_ctx {
@@ -115,7 +134,18 @@ struct fitrig_ctx {
   hipEvent_t ev[FITRIG_N_PHASES + 1] = {};
   bool ev_recorded = false;
   std::vector<AsyncOut*> captured_outs;
-
+  // serving slot: calls are synchronous on the context's own stream, so
+  // scratch growth waits for that stream only; launch sequences are captured
+  // into HIP graphs per call shape and replayed
+  bool serving = false;
+  bool use_graphs = false;
+  hipGraph_t rec_graph = nullptr;       // set while a launch sequence is built as a graph
+  hipGraphNode_t rec_last = nullptr;    // its last node (nodes form one chain)
+  hipError_t launch_err = hipSuccess;   // first launch error since the last check
+  uint64_t gen = 0;  // bumps whenever scratch moves (graphs hold its addresses)
+  std::vector<GraphEntry> graphs;
+  int64_t graph_clock = 0;
+  int64_t graph_replays = 0;
 };
 
 namespace {
@@ -149,14 +179,71 @@ namespace {
     }                                           \
   } while (0)
 
-// Launch / copy only in the launch pass.
-#define KL(...)                          \
-  do {                                   \
-    if (!ctx->sizing) hipLaunchKernelGGL(__VA_ARGS__); \
+// Launches a kernel (args: pointers to its argument values), or, while a
+// graph is being built (ctx->rec_graph), appends it as a kernel node after
+// the previous node. Graphs are built node by node rather than by stream
+// capture, which would forbid device-wide synchronisation in every other
+// thread of the process while it lasts.
+hipError_t launch_raw(fitrig_ctx* ctx, const void* fn, dim3 g, dim3 b, size_t sh, hipStream_t st, void** args) {
+  if (!fn) return hipErrorInvalidDeviceFunction;
+  if (!ctx->rec_graph) return hipLaunchKernel(fn, g, b, args, sh, st);
+  hipKernelNodeParams p;
+  memset(&p, 0, sizeof(p));
+  p.func = const_cast<void*>(fn);
+  p.gridDim = g;
+  p.blockDim = b;
+  p.sharedMemBytes = (unsigned int)sh;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  hipGraphNode_t n = nullptr;
+  const hipError_t e =
+      hipGraphAddKernelNode(&n, ctx->rec_graph, ctx->rec_last ? &ctx->rec_last : nullptr, ctx->rec_last ? 1 : 0, &p);
+  if (e == hipSuccess) ctx->rec_last = n;
+  return e;
+}
+
+// Device-to-device copy on the stream, or a copy node while building a graph.
+hipError_t copy_d2d(fitrig_ctx* ctx, void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (!ctx->rec_graph) return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+  hipGraphNode_t n = nullptr;
+  const hipError_t e = hipGraphAddMemcpyNode1D(&n, ctx->rec_graph, ctx->rec_last ? &ctx->rec_last : nullptr,
+                                               ctx->rec_last ? 1 : 0, dst, src, bytes, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) ctx->rec_last = n;
+  return e;
+}
+
+// Typed front end of launch_raw: the arguments are converted to the kernel's
+// parameter types and passed by address.
+template <typename... P, typename... A, size_t... I>
+hipError_t launch_k_impl(fitrig_ctx* ctx, void (*k)(P...), dim3 g, dim3 b, size_t sh, hipStream_t st,
+                         std::index_sequence<I...>, A&&... a) {
+  std::tuple<std::decay_t<P>...> vals(static_cast<std::decay_t<P>>(std::forward<A>(a))...);
+  void* ptrs[sizeof...(P) + 1] = {(void*)&std::get<I>(vals)...};
+  return launch_raw(ctx, (const void*)k, g, b, sh, st, ptrs);
+}
+template <typename... P, typename... A>
+hipError_t launch_k(fitrig_ctx* ctx, void (*k)(P...), dim3 g, dim3 b, size_t sh, hipStream_t st, A&&... a) {
+  static_assert(sizeof...(P) == sizeof...(A), "kernel argument count");
+  return launch_k_impl(ctx, k, g, b, sh, st, std::index_sequence_for<P...>{}, std::forward<A>(a)...);
+}
+
+void note_launch(fitrig_ctx* ctx, hipError_t e) {
+  if (e != hipSuccess && ctx->launch_err == hipSuccess) ctx->launch_err = e;
+}
+
+// Launch only in the launch pass.
+#define KL(k, g, b, sh, st, ...)                                        \
+  do {                                                                  \
+    if (!ctx->sizing) note_launch(ctx, launch_k(ctx, k, g, b, sh, st, __VA_ARGS__)); \
   } while (0)
-#define LAUNCH_CHECK(ctx)                                   \
-  do {                                                      \
-    if (!(ctx)->sizing) HIP_TRY(ctx, hipGetLastError());    \
+#define LAUNCH_CHECK(ctx)                                               \
+  do {                                                                  \
+    if (!(ctx)->sizing) {                                               \
+      hipError_t le_ = (ctx)->launch_err;                               \
+      (ctx)->launch_err = hipSuccess;                                   \
+      if (le_ == hipSuccess && !(ctx)->rec_graph) le_ = hipGetLastError(); \
+      HIP_TRY(ctx, le_);                                                \
+    }                                                                   \
   } while (0)
 
 // Records (sizing pass) or checks (launch pass) a scratch buffer's size.
@@ -194,7 +281,12 @@ fitrig_status provision(fitrig_ctx* ctx, hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_TRY(ctx, hipStreamIsCapturing(st, &cs));
   if (cs != hipStreamCaptureStatusNone) return FITRIG_E_INVAL;
-  HIP_TRY(ctx, hipDeviceSynchronize());
+  // a serving slot's calls all ran synchronously on its own stream
+  if (ctx->serving)
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  else
+    HIP_TRY(ctx, hipDeviceSynchronize());
+  ++ctx->gen;
   for (DevBuf fitrig_ctx::* m : kBufs) {
     DevBuf& b = ctx->*m;
     if (b.want <= b.cap) continue;
@@ -228,30 +320,51 @@ int grid_for(int64_t n, int per = 256, int maxg = 8192) {
   return (int)g;
 }
 
-bool dispatch_stream(int dt, int halo, bool rs, dim3 g, hipStream_t st, const StreamArgs& A) {
-  return dt == FITRIG_F32 ? launch_stream_f32(halo, rs, g, st, A)
-         : dt == FITRIG_F16 ? launch_stream_f16(halo, rs, g, st, A)
-                            : launch_stream_bf16(halo, rs, g, st, A);
+// Kernels templated on the storage type: one argument struct by value (the
+// stack maximum: three arguments).
+bool dispatch_stream(fitrig_ctx* ctx, int dt, int halo, bool rs, dim3 g, hipStream_t st, const StreamArgs& A) {
+  const void* fn = dt == FITRIG_F32 ? kernel_stream_f32(halo, rs)
+                   : dt == FITRIG_F16 ? kernel_stream_f16(halo, rs)
+                                      : kernel_stream_bf16(halo, rs);
+  if (!fn) return false;
+  void* a[] = {(void*)&A};
+  note_launch(ctx, launch_raw(ctx, fn, g, dim3(kLanes), 0, st, a));
+  return true;
 }
-bool dispatch_tile_stream(int dt, int tile, bool rs, dim3 g, hipStream_t st, const TileStreamArgs& A) {
-  return dt == FITRIG_F32 ? launch_tile_stream_f32(tile, rs, g, st, A)
-         : dt == FITRIG_F16 ? launch_tile_stream_f16(tile, rs, g, st, A)
-                            : launch_tile_stream_bf16(tile, rs, g, st, A);
+bool dispatch_tile_stream(fitrig_ctx* ctx, int dt, int tile, bool rs, dim3 g, hipStream_t st,
+                          const TileStreamArgs& A) {
+  const void* fn = dt == FITRIG_F32 ? kernel_tile_stream_f32(tile, rs)
+                   : dt == FITRIG_F16 ? kernel_tile_stream_f16(tile, rs)
+                                      : kernel_tile_stream_bf16(tile, rs);
+  if (!fn) return false;
+  void* a[] = {(void*)&A};
+  note_launch(ctx, launch_raw(ctx, fn, g, dim3(kLanes), 0, st, a));
+  return true;
 }
-bool dispatch_tile(int dt, bool rs, dim3 g, hipStream_t st, const TileArgs& A) {
-  return dt == FITRIG_F32 ? launch_tile_f32(rs, g, st, A)
-         : dt == FITRIG_F16 ? launch_tile_f16(rs, g, st, A)
-                            : launch_tile_bf16(rs, g, st, A);
+bool dispatch_tile(fitrig_ctx* ctx, int dt, bool rs, dim3 g, hipStream_t st, const TileArgs& A) {
+  const void* fn = dt == FITRIG_F32 ? kernel_tile_f32(rs) : dt == FITRIG_F16 ? kernel_tile_f16(rs) : kernel_tile_bf16(rs);
+  if (!fn) return false;
+  void* a[] = {(void*)&A};
+  note_launch(ctx, launch_raw(ctx, fn, g, dim3(kLanes), 0, st, a));
+  return true;
 }
-bool dispatch_recompute(int dt, int halo, bool rs, dim3 g, hipStream_t st, const RecomputeArgs& R) {
-  return dt == FITRIG_F32 ? launch_recompute_f32(halo, rs, g, st, R)
-         : dt == FITRIG_F16 ? launch_recompute_f16(halo, rs, g, st, R)
-                            : launch_recompute_bf16(halo, rs, g, st, R);
+bool dispatch_recompute(fitrig_ctx* ctx, int dt, int halo, bool rs, dim3 g, hipStream_t st, const RecomputeArgs& R) {
+  const void* fn = dt == FITRIG_F32 ? kernel_recompute_f32(halo, rs)
+                   : dt == FITRIG_F16 ? kernel_recompute_f16(halo, rs)
+                                      : kernel_recompute_bf16(halo, rs);
+  if (!fn) return false;
+  void* a[] = {(void*)&R};
+  note_launch(ctx, launch_raw(ctx, fn, g, dim3(64), 0, st, a));
+  return true;
 }
-bool dispatch_stack_max(int dt, dim3 g, hipStream_t st, const CallDev* cd, int64_t n, uint32_t* mk) {
-  return dt == FITRIG_F32 ? launch_stack_max_f32(g, st, cd, n, mk)
-         : dt == FITRIG_F16 ? launch_stack_max_f16(g, st, cd, n, mk)
-                            : launch_stack_max_bf16(g, st, cd, n, mk);
+bool dispatch_stack_max(fitrig_ctx* ctx, int dt, dim3 g, hipStream_t st, const CallDev* cd, int64_t n,
+                        uint32_t* mk) {
+  const void* fn = dt == FITRIG_F32 ? kernel_stack_max_f32() : dt == FITRIG_F16 ? kernel_stack_max_f16()
+                                                                                 : kernel_stack_max_bf16();
+  if (!fn) return false;
+  void* a[] = {(void*)&cd, (void*)&n, (void*)&mk};
+  note_launch(ctx, launch_raw(ctx, fn, g, dim3(256), 0, st, a));
+  return true;
 }
 
 struct Call {
@@ -620,7 +733,7 @@ fitrig_status select_run(fitrig_ctx* ctx, const Call& c, const SegLayout& L, flo
     R.sigma = sigma;
     R.mask = mask;
     R.cell_q = cq;
-    if (!dispatch_recompute(c.dtype, halo, ctx->cfg.r_signed != 0, dim3(gsel), st, R)) return FITRIG_E_INVAL;
+    if (!dispatch_recompute(ctx, c.dtype, halo, ctx->cfg.r_signed != 0, dim3(gsel), st, R)) return FITRIG_E_INVAL;
   }
   LAUNCH_CHECK(ctx);
   const int gcell = grid_for(cap * 64, 256, 4096);
@@ -678,6 +791,18 @@ fitrig_status ensure_selection(fitrig_ctx* ctx, int64_t ne_total) {
   return FITRIG_OK;
 }
 
+// The call record (stack pointers, tau, history pointers) the kernels read.
+void write_call(fitrig_ctx* ctx, const Call& c) {
+  CallDev v;
+  v.base = c.stack;
+  v.carry0 = c.carry0;
+  v.carry1 = c.carry1;
+  v.hist_in = c.hist ? c.hist->in : nullptr;
+  v.hist_out = c.hist ? c.hist->out : nullptr;
+  v.tau = c.tau;
+  KL(k_set_call, dim3(1), dim3(64), 0, c.st, (CallDev*)ctx->call.p, v);
+}
+
 // Enqueues the whole path of one call (or, in the sizing pass, records the
 // scratch it needs). with_call: also write the call record first.
 fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
@@ -701,21 +826,12 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
   if ((rc = ensure(ctx, ctx->max_key, 64)) != FITRIG_OK) return rc;
   CallDev* cd = (CallDev*)ctx->call.p;
   int64_t* cnt = (int64_t*)ctx->counters.p;
-  if (with_call) {
-    CallDev v;
-    v.base = c.stack;
-    v.carry0 = c.carry0;
-    v.carry1 = c.carry1;
-    v.hist_in = c.hist ? c.hist->in : nullptr;
-    v.hist_out = c.hist ? c.hist->out : nullptr;
-    v.tau = c.tau;
-    KL(k_set_call, dim3(1), dim3(64), 0, st, cd, v);
-  }
+  if (with_call) write_call(ctx, c);
   KL(k_fill_i64, dim3(1), dim3(64), 0, st, cnt, (int64_t)CNT_N, (int64_t)0);
   KL(k_fill_i64, dim3(1), dim3(64), 0, st, (int64_t*)ctx->eta_st.p, (int64_t)ES_N, (int64_t)0);
   KL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)ctx->max_key.p, (int64_t)1, 0u);
   KL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)ctx->flags.p, (int64_t)np, 0u);
-  bool prof = cfg.profile != 0 && !ctx->sizing;
+  bool prof = cfg.profile != 0 && !ctx->sizing && !ctx->rec_graph;
   if (prof) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIP_TRY(ctx, hipStreamIsCapturing(st, &cs));
@@ -776,7 +892,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
       A.seg_max = (float*)ctx->seg_max.p;
       A.tile_part = byprod ? (double*)ctx->tile_part.p : nullptr;
       A.max_key = (uint32_t*)ctx->max_key.p;
-      if (!dispatch_stream(c.dtype, halo, cfg.r_signed != 0, dim3((unsigned)nwg), st, A)) return FITRIG_E_INVAL;
+      if (!dispatch_stream(ctx, c.dtype, halo, cfg.r_signed != 0, dim3((unsigned)nwg), st, A)) return FITRIG_E_INVAL;
     }
     LAUNCH_CHECK(ctx);
     have_max = true;
@@ -825,7 +941,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     A.max_key = (uint32_t*)ctx->max_key.p;
     const int64_t nwg = (int64_t)A.nchunk * A.nbands;
     if (nwg > INT32_MAX) return FITRIG_E_INVAL;
-    if (!ctx->sizing && !dispatch_tile_stream(c.dtype, tile, cfg.r_signed != 0, dim3((unsigned)nwg), st, A))
+    if (!ctx->sizing && !dispatch_tile_stream(ctx, c.dtype, tile, cfg.r_signed != 0, dim3((unsigned)nwg), st, A))
       return FITRIG_E_INVAL;
     LAUNCH_CHECK(ctx);
     if (!have_max) {
@@ -854,7 +970,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     A.Cf = (float)cfg.C;
     A.tile_part = (double*)ctx->tile_part.p;
     A.max_key = (uint32_t*)ctx->max_key.p;
-    if (!ctx->sizing && !dispatch_tile(c.dtype, cfg.r_signed != 0, dim3(nchunk, Ty, np), st, A))
+    if (!ctx->sizing && !dispatch_tile(ctx, c.dtype, cfg.r_signed != 0, dim3(nchunk, Ty, np), st, A))
       return FITRIG_E_INVAL;
     LAUNCH_CHECK(ctx);
     if (!have_max) {
@@ -869,7 +985,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
   if (!have_max) {
     // no pass produced the maximum (frequency branch only with too few triples)
     if (!ctx->sizing &&
-        !dispatch_stack_max(c.dtype, dim3(1024), st, cd, (int64_t)(c.n - c.ncarry) * plane, (uint32_t*)ctx->max_key.p))
+        !dispatch_stack_max(ctx, c.dtype, dim3(1024), st, cd, (int64_t)(c.n - c.ncarry) * plane, (uint32_t*)ctx->max_key.p))
       return FITRIG_E_INVAL;
     if ((rc = mark(1)) != FITRIG_OK) return rc;
   }
@@ -906,7 +1022,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     }
   }
   if (c.index_map && !P.sliding && !ctx->sizing)
-    HIP_TRY(ctx, hipMemcpyAsync(c.index_map, ctx->cube_f.p, (size_t)np * Ty * Tx * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, copy_d2d(ctx, c.index_map, ctx->cube_f.p, (size_t)np * Ty * Tx * 4, st));
 
   if ((rc = mark(3)) != FITRIG_OK) return rc;
   // ---- frequency branch ----------------------------------------------------
@@ -955,7 +1071,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
                          halo)) != FITRIG_OK)
       return rc;
     if (c.eta_map && !ctx->sizing)
-      HIP_TRY(ctx, hipMemcpyAsync(c.eta_map, ctx->eta_f.p, (size_t)ntiles * 4, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(ctx, copy_d2d(ctx, c.eta_map, ctx->eta_f.p, (size_t)ntiles * 4, st));
   }
 
   // ---- per-pixel frequency branch -------------------------------------------
@@ -1165,6 +1281,81 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   return FITRIG_OK;
 }
 
+void drop_graph(GraphEntry& e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  e.exec = nullptr;
+}
+
+// The whole call as a replay of the launch sequence built as a graph for its
+// shape (synchronous on c.st). The sequence reads the per-call values from
+// the call record, which is written before each replay; scratch addresses
+// are built in, so a graph is valid for the context's current generation of
+// scratch only. When building or instantiation fails the context goes back
+// to direct launches for good.
+fitrig_status detect_graph(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand, int64_t* n_cand,
+                           fitrig_stats* stats) {
+  fitrig_status rc = check_shape(ctx->cfg, c);
+  if (rc != FITRIG_OK) return rc;
+  const int np = c.n - 2;
+  const int64_t cap = c.cand_cap;
+  const ResultLayout R = result_layout(np, cap);
+  if ((rc = sizing_pass(ctx, c, (size_t)R.bytes)) != FITRIG_OK) return rc;
+  if ((rc = provision(ctx, c.st)) != FITRIG_OK) return rc;
+  for (size_t i = 0; i < ctx->graphs.size();) {
+    if (ctx->graphs[i].gen != ctx->gen) {
+      drop_graph(ctx->graphs[i]);
+      ctx->graphs.erase(ctx->graphs.begin() + (std::ptrdiff_t)i);
+    } else {
+      ++i;
+    }
+  }
+  const GraphKey key{c.n, c.H, c.W, c.ncarry, (int)c.dtype, c.hist ? c.hist->cap : 0, c.hist ? c.hist->n_in : 0,
+                     (c.hist && c.hist->out) ? 1 : 0, cap};
+  GraphEntry* e = nullptr;
+  for (GraphEntry& g : ctx->graphs)
+    if (g.key == key) e = &g;
+  if (!e) {
+    hipGraph_t g = nullptr;
+    hipError_t he = hipGraphCreate(&g, 0);
+    if (he == hipSuccess) {
+      ctx->rec_graph = g;
+      ctx->rec_last = nullptr;
+      ctx->launch_err = hipSuccess;
+      rc = enqueue(ctx, c, false);
+      if (rc == FITRIG_OK) rc = enqueue_results(ctx, c, ctx->h_stage_dev, R, cap);
+      ctx->rec_graph = nullptr;
+      ctx->rec_last = nullptr;
+      ctx->launch_err = hipSuccess;
+    }
+    hipGraphExec_t x = nullptr;
+    if (he == hipSuccess && rc == FITRIG_OK) he = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (he != hipSuccess || rc != FITRIG_OK || !x) {
+      if (x) (void)hipGraphExecDestroy(x);
+      (void)hipGetLastError();
+      ctx->use_graphs = false;
+      return detect_impl(ctx, c, cand, n_cand, stats, false);
+    }
+    if (ctx->graphs.size() >= kMaxGraphs) {
+      size_t lru = 0;
+      for (size_t i = 1; i < ctx->graphs.size(); ++i)
+        if (ctx->graphs[i].last_use < ctx->graphs[lru].last_use) lru = i;
+      drop_graph(ctx->graphs[lru]);
+      ctx->graphs.erase(ctx->graphs.begin() + (std::ptrdiff_t)lru);
+    }
+    ctx->graphs.push_back(GraphEntry{key, x, ctx->gen, 0});
+    e = &ctx->graphs.back();
+  }
+  e->last_use = ++ctx->graph_clock;
+  write_call(ctx, c);
+  LAUNCH_CHECK(ctx);
+  HIP_TRY(ctx, hipGraphLaunch(e->exec, c.st));
+  HIP_TRY(ctx, hipStreamSynchronize(c.st));
+  ++ctx->graph_replays;
+  return unpack_results(ctx->h_stage, R, np, branches_ran(ctx->cfg, c), cand, cap, n_cand, stats,
+                        stats ? stats->mu : nullptr, stats ? stats->sigma : nullptr, stats ? stats->flags : nullptr);
+}
+
 fitrig_status validate_cfg(const fitrig_config* c) {
   if (!c || c->abi_version != FITRIG_ABI_VERSION) return FITRIG_E_INVAL;
   if (c->mode != FITRIG_SLIDING && c->mode != FITRIG_TILES) return FITRIG_E_INVAL;
@@ -1372,6 +1563,7 @@ fitrig_status fitrig_destroy(fitrig_ctx* ctx) {
   if (!ctx) return FITRIG_E_INVAL;
   (void)hipSetDevice(ctx->cfg.device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (GraphEntry& g : ctx->graphs) drop_graph(g);
   if (!ctx->in_arena)
     for (DevBuf fitrig_ctx::* m : kBufs)
       if ((ctx->*m).p) (void)hipFree((ctx->*m).p);
@@ -1476,28 +1668,91 @@ fitrig_status detect_frames(fitrig_ctx* ctx, const void* carry0, const void* car
   c.st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
   c.hist = hist;
   c.cand_cap = cand_cap;
+  if (ctx->use_graphs) return detect_graph(ctx, c, cand, n_cand, stats);
   return detect_impl(ctx, c, cand, n_cand, stats, false);
+}
+
+// A serving slot runs on a non-blocking stream of its own (captures must not
+// be joined by work on the legacy default stream; the server orders each
+// request after that stream with an event recorded at submit).
+fitrig_status ctx_set_serving(fitrig_ctx* ctx, bool graphs) {
+  if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FITRIG_E_HIP;
+  hipStream_t s = nullptr;
+  HIP_TRY(ctx, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  if (ctx->stream) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamDestroy(ctx->stream);
+  }
+  ctx->stream = s;
+  ctx->serving = true;
+  ctx->use_graphs = graphs;
+  return FITRIG_OK;
+}
+bool ctx_uses_graphs(const fitrig_ctx* ctx) { return ctx->use_graphs; }
+int64_t ctx_graph_replays(const fitrig_ctx* ctx) { return ctx->graph_replays; }
+
+// Device bytes the context holds (scratch buffers and mapped result memory).
+int64_t ctx_device_bytes(const fitrig_ctx* ctx) {
+  int64_t b = (int64_t)ctx->h_stage_cap;
+  for (DevBuf fitrig_ctx::* m : kBufs) b += (int64_t)(ctx->*m).cap;
+  return b;
+}
+
+namespace {
+// A call of this shape for the sizing pass (the stack pointer is a stand-in,
+// never dereferenced).
+Call shape_call(int ncarry, int n_new, int H, int W, fitrig_dtype dtype, const FreqHist* hist, int64_t cand_cap,
+                hipStream_t st) {
+  Call c;
+  memset(&c, 0, sizeof(c));
+  c.stack = (const void*)(uintptr_t)256;
+  c.carry0 = ncarry >= 1 ? c.stack : nullptr;
+  c.carry1 = ncarry >= 2 ? c.stack : nullptr;
+  c.ncarry = ncarry;
+  c.dtype = dtype;
+  c.n = ncarry + n_new;
+  c.H = H;
+  c.W = W;
+  c.tau = 1.0;
+  c.hist = hist;
+  c.cand_cap = cand_cap;
+  c.st = st;
+  return c;
+}
+
+// Sizing pass of a host-only context with ctx's config (nothing allocated or
+// launched); false when the shape is not a valid call.
+bool size_shape(const fitrig_config& cfg, const Call& c, fitrig_ctx& tmp) {
+  tmp.cfg = cfg;
+  tmp.cfg.profile = 0;
+  if (c.n < 3 || check_shape(cfg, c) != FITRIG_OK) return false;
+  return sizing_pass(&tmp, c, (size_t)result_layout(c.n - 2, c.cand_cap).bytes) == FITRIG_OK;
+}
+}  // namespace
+
+// Sizes ctx's scratch for a call of this shape (allocates, before serving).
+fitrig_status ctx_presize_for(fitrig_ctx* ctx, int ncarry, int n_new, int H, int W, fitrig_dtype dtype,
+                              const FreqHist* hist, int64_t cand_cap) {
+  const Call c = shape_call(ncarry, n_new, H, W, dtype, hist, cand_cap, ctx->stream);
+  if (c.n < 3 || check_shape(ctx->cfg, c) != FITRIG_OK) return FITRIG_E_INVAL;
+  if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FITRIG_E_HIP;
+  const fitrig_status rc = sizing_pass(ctx, c, (size_t)result_layout(c.n - 2, cand_cap).bytes);
+  if (rc != FITRIG_OK) return rc;
+  return provision(ctx, ctx->stream);
+}
+
+// Exact device bytes one call of this shape needs (the sizing pass of a
+// host-only context: nothing is allocated or launched).
+int64_t call_scratch_bytes(const fitrig_config& cfg, int ncarry, int n_new, int H, int W, fitrig_dtype dtype,
+                           const FreqHist* hist, int64_t cand_cap) {
+  fitrig_ctx tmp;
+  if (!size_shape(cfg, shape_call(ncarry, n_new, H, W, dtype, hist, cand_cap, nullptr), tmp)) return 0;
+  int64_t b = (int64_t)std::max<size_t>(tmp.h_want, 1 << 16);
+  for (DevBuf fitrig_ctx::* m : kBufs) b += (int64_t)(tmp.*m).want;
+  return b;
 }
 
 hipStream_t ctx_stream(fitrig_ctx* ctx) { return ctx->stream; }
 int32_t& ctx_last_hip(fitrig_ctx* ctx) { return ctx->last_hip; }
-
-// Device bytes a context needs for one call of this size (admission).
-int64_t scratch_estimate(const fitrig_config& cfg, int n, int H, int W) {
-  const int64_t np = n - 2, plane = (int64_t)H * W;
-  const int out_w = out_width(cfg.window / 2);
-  const int64_t ncol = (W + out_w - 1) / out_w, nbands = (H + kBand - 1) / kBand;
-  const int64_t nwg = ncol * nbands;
-  const int64_t nseg = np * H * ncol * kSegsPerGroup;
-  const int64_t segcap = cfg.max_segments > 0 ? cfg.max_segments : std::max<int64_t>(65536, std::min<int64_t>(nseg / 64, 1 << 22));
-  const int64_t Ty = (H + cfg.tile - 1) / cfg.tile, Tx = (W + cfg.tile - 1) / cfg.tile;
-  int64_t b = np * nwg * 256 + nseg * 4 + np * nbands * ncol * kPieces * 24 + np * Ty * Tx * 12;
-  b += segcap * (8 + 8 + 64 * 12) + 2 * segcap * (4 + 4 + 8 + 48 + 16 + 3 * (int64_t)sizeof(fitrig_candidate));
-  // median / MAD: the value map, plus the bracket gathers (about 4 % of it)
-  if (cfg.sigma_est == FITRIG_MEDIAN_MAD) b += np * plane * 4 + np * plane / 2;
-  // per-pixel frequency branch: the q map and the per-pixel spectrum maxima
-  if (cfg.branches & FITRIG_FREQ_PIXEL) b += np * plane * 4 + plane * 4;
-  return b;
-}
 
 }  // namespace fitrig

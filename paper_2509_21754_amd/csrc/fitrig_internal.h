@@ -155,30 +155,23 @@ struct ResultLayout {
   int64_t bytes;
 };
 
-// Host launchers of the kernels templated on the storage type, one
-// translation unit per type (dtype: 0 FP32, 1 FP16, 2 BF16). Each returns
-// false, launching nothing, when no instantiation covers the arguments.
-bool launch_stream(int dtype, int halo, bool r_signed, dim3 grid, hipStream_t st, const StreamArgs& A);
-bool launch_tile_stream(int dtype, int tile, bool r_signed, dim3 grid, hipStream_t st, const TileStreamArgs& A);
-bool launch_tile(int dtype, bool r_signed, dim3 grid, hipStream_t st, const TileArgs& A);
-bool launch_recompute(int dtype, int halo, bool r_signed, dim3 grid, hipStream_t st, const RecomputeArgs& R);
-bool launch_stack_max(int dtype, dim3 grid, hipStream_t st, const CallDev* cd, int64_t n, uint32_t* max_key);
-bool launch_stream_f32(int halo, bool r_signed, dim3 grid, hipStream_t st, const StreamArgs& A);
-bool launch_stream_f16(int halo, bool r_signed, dim3 grid, hipStream_t st, const StreamArgs& A);
-bool launch_stream_bf16(int halo, bool r_signed, dim3 grid, hipStream_t st, const StreamArgs& A);
-bool launch_tile_stream_f32(int tile, bool r_signed, dim3 grid, hipStream_t st, const TileStreamArgs& A);
-bool launch_tile_stream_f16(int tile, bool r_signed, dim3 grid, hipStream_t st, const TileStreamArgs& A);
-bool launch_tile_stream_bf16(int tile, bool r_signed, dim3 grid, hipStream_t st, const TileStreamArgs& A);
-bool launch_tile_f32(bool r_signed, dim3 grid, hipStream_t st, const TileArgs& A);
-bool launch_tile_f16(bool r_signed, dim3 grid, hipStream_t st, const TileArgs& A);
-bool launch_tile_bf16(bool r_signed, dim3 grid, hipStream_t st, const TileArgs& A);
-bool launch_recompute_f32(int halo, bool r_signed, dim3 grid, hipStream_t st, const RecomputeArgs& R);
-bool launch_recompute_f16(int halo, bool r_signed, dim3 grid, hipStream_t st, const RecomputeArgs& R);
-bool launch_recompute_bf16(int halo, bool r_signed, dim3 grid, hipStream_t st, const RecomputeArgs& R);
-bool launch_stack_max_f32(dim3 grid, hipStream_t st, const CallDev* cd, int64_t n, uint32_t* max_key);
-bool launch_stack_max_f16(dim3 grid, hipStream_t st, const CallDev* cd, int64_t n, uint32_t* max_key);
-bool launch_stack_max_bf16(dim3 grid, hipStream_t st, const CallDev* cd, int64_t n, uint32_t* max_key);
-
+// Kernels templated on the storage type, per type (fitrig_launch.hip): the
+// host handle of the instantiation for the given parameters, null if none.
+const void* kernel_stream_f32(int halo, bool r_signed);
+const void* kernel_stream_f16(int halo, bool r_signed);
+const void* kernel_stream_bf16(int halo, bool r_signed);
+const void* kernel_tile_stream_f32(int tile, bool r_signed);
+const void* kernel_tile_stream_f16(int tile, bool r_signed);
+const void* kernel_tile_stream_bf16(int tile, bool r_signed);
+const void* kernel_tile_f32(bool r_signed);
+const void* kernel_tile_f16(bool r_signed);
+const void* kernel_tile_bf16(bool r_signed);
+const void* kernel_recompute_f32(int halo, bool r_signed);
+const void* kernel_recompute_f16(int halo, bool r_signed);
+const void* kernel_recompute_bf16(int halo, bool r_signed);
+const void* kernel_stack_max_f32();
+const void* kernel_stack_max_f16();
+const void* kernel_stack_max_bf16();
 
 }  // namespace fitrig
 
@@ -203,6 +196,16 @@ fitrig_status detect_frames(fitrig_ctx* ctx, const void* carry0, const void* car
                             fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand, fitrig_stats* stats,
                             void* hip_stream, const FreqHist* hist);
 hipStream_t ctx_stream(fitrig_ctx* ctx);
+// serving slots: synchronous calls on the context's stream, launch sequences
+// replayed from HIP graphs captured per call shape (graphs = true)
+fitrig_status ctx_set_serving(fitrig_ctx* ctx, bool graphs);
+bool ctx_uses_graphs(const fitrig_ctx* ctx);
+int64_t ctx_graph_replays(const fitrig_ctx* ctx);
+int64_t ctx_device_bytes(const fitrig_ctx* ctx);
+int64_t call_scratch_bytes(const fitrig_config& cfg, int ncarry, int n_new, int H, int W, fitrig_dtype dtype,
+                           const FreqHist* hist, int64_t cand_cap);
+fitrig_status ctx_presize_for(fitrig_ctx* ctx, int ncarry, int n_new, int H, int W, fitrig_dtype dtype,
+                              const FreqHist* hist, int64_t cand_cap);
+
 int32_t& ctx_last_hip(fitrig_ctx* ctx);
-int64_t scratch_estimate(const fitrig_config& cfg, int n, int H, int W);
 }  // namespace fitrig

@@ -23,62 +23,42 @@ using T = bf16_t;
 #define SFX(name) name##_bf16
 #endif
 
-bool SFX(launch_stream)(int halo, bool rs, dim3 grid, hipStream_t st, const StreamArgs& A) {
+// Each returns the kernel for the given template parameters (the host
+// handle that hipLaunchKernel and graph kernel nodes take), or null when no
+// instantiation covers them. Every kernel takes its argument struct by value.
+const void* SFX(kernel_stream)(int halo, bool rs) {
   switch (halo) {
-#define CASE(h)                                                                                  \
-  case h:                                                                                        \
-    if (rs)                                                                                      \
-      hipLaunchKernelGGL((k_stream<T, h, true>), grid, dim3(kLanes), 0, st, A);                  \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_stream<T, h, false>), grid, dim3(kLanes), 0, st, A);                 \
-    return true;
+#define CASE(h) \
+  case h: return rs ? (const void*)&k_stream<T, h, true> : (const void*)&k_stream<T, h, false>;
     CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
-    default: return false;
+    default: return nullptr;
   }
 }
 
-bool SFX(launch_tile_stream)(int tile, bool rs, dim3 grid, hipStream_t st, const TileStreamArgs& A) {
+const void* SFX(kernel_tile_stream)(int tile, bool rs) {
   switch (tile) {
-#define CASE(t)                                                                                  \
-  case t:                                                                                        \
-    if (rs)                                                                                      \
-      hipLaunchKernelGGL((k_tile_stream<T, t, true>), grid, dim3(kLanes), 0, st, A);             \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_tile_stream<T, t, false>), grid, dim3(kLanes), 0, st, A);            \
-    return true;
+#define CASE(t) \
+  case t: return rs ? (const void*)&k_tile_stream<T, t, true> : (const void*)&k_tile_stream<T, t, false>;
     CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
 #undef CASE
-    default: return false;
+    default: return nullptr;
   }
 }
 
-bool SFX(launch_tile)(bool rs, dim3 grid, hipStream_t st, const TileArgs& A) {
-  if (rs)
-    hipLaunchKernelGGL((k_tile<T, true>), grid, dim3(kLanes), 0, st, A);
-  else
-    hipLaunchKernelGGL((k_tile<T, false>), grid, dim3(kLanes), 0, st, A);
-  return true;
-}
+const void* SFX(kernel_tile)(bool rs) { return rs ? (const void*)&k_tile<T, true> : (const void*)&k_tile<T, false>; }
 
-bool SFX(launch_recompute)(int halo, bool rs, dim3 grid, hipStream_t st, const RecomputeArgs& R) {
+const void* SFX(kernel_recompute)(int halo, bool rs) {
   switch (halo) {
-#define CASE(h)                                                                                  \
-  case h:                                                                                        \
-    if (rs)                                                                                      \
-      hipLaunchKernelGGL((k_recompute<T, h, true>), grid, dim3(64), 0, st, R);                   \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_recompute<T, h, false>), grid, dim3(64), 0, st, R);                  \
-    return true;
+#define CASE(h) \
+  case h: return rs ? (const void*)&k_recompute<T, h, true> : (const void*)&k_recompute<T, h, false>;
     CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
-    default: return false;
+    default: return nullptr;
   }
 }
 
-bool SFX(launch_stack_max)(dim3 grid, hipStream_t st, const CallDev* cd, int64_t n, uint32_t* max_key) {
-  hipLaunchKernelGGL((k_stack_max<T>), grid, dim3(256), 0, st, cd, n, max_key);
-  return true;
-}
+// k_stack_max(const CallDev* cd, int64_t n, uint32_t* max_key)
+const void* SFX(kernel_stack_max)() { return (const void*)&k_stack_max<T>; }
 
 }  // namespace fitrig

@@ -5,22 +5,27 @@
 // not depend on M) of the field's last freq_window triples, so every request
 // continues the field's sequence of triples, its M estimate from past
 // snapshots (the paper's real-time rule for M, Sec. 2.2.4) and the time
-// series the frequency branch transforms (Sec. 2.3). Requests are admitted while the memory budget allows
-// (estimated slot scratch of the running and queued requests plus the
-// resident field state); admitted requests wait for one of n_slots worker
-// slots, each with its own context and HIP stream, so requests of different
-// fields run concurrently on the device. A field's requests run in
-// submission order. Results are bitwise those of running the same frames
-// alone (the kernels are deterministic and each slot owns its scratch).
+// series the frequency branch transforms (Sec. 2.3). Requests are admitted
+// while a bound on the device memory in use fits the budget (resident field
+// state plus, per slot, the larger of its retained scratch and the exact
+// scratch of the largest queued or running request); admitted requests wait
+// for one of n_slots worker slots, each with its own context and HIP stream,
+// so requests of different fields run concurrently on the device. A slot
+// replays the launch sequence it captured into a HIP graph for the request's
+// shape. A field's requests run in submission order. Results are bitwise
+// those of running the same frames alone (the kernels are deterministic and
+// each slot owns its scratch).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -43,7 +48,9 @@ struct Req {
   fitrig_dtype dtype = FITRIG_F32;
   int n = 0, H = 0, W = 0;
   double tau = 0.0;
-  int64_t mem = 0;  // admission charge while queued or running
+  int64_t mem = 0;  // exact scratch bytes of the request (admission, while queued or running)
+  hipEvent_t ready = nullptr;  // recorded on the legacy default stream at submit
+  int replayed = 0;
   int64_t t_submit = 0, t_start = 0, t_done = 0;
   bool done = false;
   fitrig_status status = FITRIG_OK;
@@ -85,13 +92,23 @@ struct fitrig_server {
   std::vector<fitrig_ctx*> ctxs;
   int64_t next_ticket = 1;
   int64_t use_clock = 0;
-  int64_t mem_charged = 0;  // queued + running requests
+  std::multiset<int64_t> inflight;  // scratch bytes of the queued and running requests
+  std::vector<int64_t> retained;    // device bytes each slot's context holds
   int64_t mem_fields = 0;   // resident field state
   int outstanding = 0;      // admitted, not finished
   bool stop = false;
 };
 
 namespace {
+
+// Bound on the device bytes in use once every admitted request has run, with
+// `need` the largest scratch of a queued or running request: any of them may
+// run on any slot, and a slot keeps the largest scratch it has held.
+int64_t device_bound(const fitrig_server* S, int64_t need) {
+  int64_t b = S->mem_fields;
+  for (int64_t r : S->retained) b += std::max(r, need);
+  return b;
+}
 
 // Device bytes of a field's resident state.
 size_t field_bytes(const Field& f) { return 2 * f.frame_bytes + f.ring_bytes; }
@@ -105,6 +122,7 @@ void free_field(Field& f) {
 
 void worker_main(fitrig_server* S, int slot) {
   fitrig_ctx* ctx = S->ctxs[slot];
+  (void)hipSetDevice(S->cfg.base.device);
   std::vector<fitrig_candidate> buf((size_t)std::max<int64_t>(S->cfg.cand_cap, 1));
   for (;;) {
     Req* r = nullptr;
@@ -130,8 +148,12 @@ void worker_main(fitrig_server* S, int slot) {
     fitrig_stats st;
     memset(&st, 0, sizeof(st));
     int64_t ncand = 0;
-    fitrig_status rc = fitrig::detect_frames(ctx, c0, c1, nc, r->stack, r->dtype, r->n, r->H, r->W, r->tau,
+    const int64_t replays0 = fitrig::ctx_graph_replays(ctx);
+    // the slot's stream does not wait on the legacy default stream by itself
+    hipError_t we = hipStreamWaitEvent(fitrig::ctx_stream(ctx), r->ready, 0);
+    fitrig_status rc = we != hipSuccess ? FITRIG_E_HIP : fitrig::detect_frames(ctx, c0, c1, nc, r->stack, r->dtype, r->n, r->H, r->W, r->tau,
                                              buf.data(), S->cfg.cand_cap, &ncand, &st, nullptr, fh.cap ? &fh : nullptr);
+    r->replayed = fitrig::ctx_graph_replays(ctx) > replays0 ? 1 : 0;
     // the field keeps the last two frames of [carried | new]
     Field* fp;
     {
@@ -151,6 +173,8 @@ void worker_main(fitrig_server* S, int slot) {
         he = hipMemcpyAsync(fp->carry + fb, r->stack, fb, hipMemcpyDeviceToDevice, hs);
     }
     if (he == hipSuccess) he = hipStreamSynchronize(hs);
+    (void)hipEventDestroy(r->ready);
+    r->ready = nullptr;
     if (he != hipSuccess && (rc == FITRIG_OK || rc == FITRIG_E_TRUNC)) {
       fitrig::ctx_last_hip(ctx) = (int32_t)he;
       rc = FITRIG_E_HIP;
@@ -179,7 +203,9 @@ void worker_main(fitrig_server* S, int slot) {
       r->M = f.M;
       f.frames_seen += r->n;
       f.ncarry = (int)std::min<int64_t>(2, nc + r->n);
-      S->mem_charged -= r->mem;
+      S->retained[slot] = fitrig::ctx_device_bytes(ctx);
+      auto it = S->inflight.find(r->mem);
+      if (it != S->inflight.end()) S->inflight.erase(it);
       S->outstanding -= 1;
       r->done = true;
       f.busy = false;
@@ -207,13 +233,14 @@ void fitrig_server_config_default(fitrig_server_config* cfg) {
   cfg->mem_budget = 0;
   cfg->cand_cap = 65536;
   cfg->freq_window = 0;
+  cfg->graphs = 1;
 }
 
 fitrig_status fitrig_server_create(const fitrig_server_config* cfg, fitrig_server** out) {
   if (!cfg || !out) return FITRIG_E_INVAL;
   *out = nullptr;
   if (cfg->n_slots < 1 || cfg->n_slots > 64 || cfg->max_fields < 1 || cfg->cand_cap < 0 || cfg->mem_budget < 0 ||
-      cfg->freq_window < 0 || cfg->freq_window > 2048 || cfg->base.tile < 1)
+      cfg->freq_window < 0 || cfg->freq_window > 2048 || cfg->base.tile < 1 || (cfg->graphs != 0 && cfg->graphs != 1))
     return FITRIG_E_INVAL;
   fitrig_server* S = new (std::nothrow) fitrig_server();
   if (!S) return FITRIG_E_NOMEM;
@@ -228,6 +255,37 @@ fitrig_status fitrig_server_create(const fitrig_server_config* cfg, fitrig_serve
       return rc;
     }
     S->ctxs.push_back(c);
+    const fitrig_status rs = fitrig::ctx_set_serving(c, cfg->graphs != 0);
+    if (rs != FITRIG_OK) {
+      for (fitrig_ctx* x : S->ctxs) fitrig_destroy(x);
+      delete S;
+      return rs;
+    }
+  }
+  // with capacity hints every slot is sized at create for a square image of
+  // max_pixels with max_snap new frames after two carried ones and the
+  // longest frequency history, so requests up to that size do not grow it
+  const fitrig_config& b = S->cfg.base;
+  if (b.max_pixels > 0 && b.max_snap >= 3) {
+    const int side = (int)ceil(sqrt((double)b.max_pixels));
+    const bool ring = S->cfg.freq_window > 0 && (b.branches & FITRIG_FREQ) != 0;
+    const fitrig::FreqHist hs{(const double*)(uintptr_t)256, ring ? S->cfg.freq_window : 0,
+                              ring ? S->cfg.freq_window : 0, (double*)(uintptr_t)256};
+    for (fitrig_ctx* c : S->ctxs) {
+      const fitrig_status rc =
+          fitrig::ctx_presize_for(c, 2, b.max_snap, side, side, FITRIG_F32, ring ? &hs : nullptr, S->cfg.cand_cap);
+      if (rc != FITRIG_OK) {
+        for (fitrig_ctx* x : S->ctxs) fitrig_destroy(x);
+        delete S;
+        return rc;
+      }
+    }
+  }
+  for (fitrig_ctx* c : S->ctxs) S->retained.push_back(fitrig::ctx_device_bytes(c));
+  if (cfg->mem_budget > 0 && device_bound(S, 0) > cfg->mem_budget) {
+    for (fitrig_ctx* x : S->ctxs) fitrig_destroy(x);
+    delete S;
+    return FITRIG_E_NOMEM;
   }
   for (int i = 0; i < cfg->n_slots; ++i) S->workers.emplace_back(worker_main, S, i);
   *out = S;
@@ -260,9 +318,15 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
     const int64_t carried = (f0 && !resize) ? std::min<int64_t>(2, f0->frames_submitted) : 0;
     if (carried + n_snap < 3) return FITRIG_E_INVAL;
     field_mem = (fresh || resize) ? (int64_t)(2 * fb + rb) : 0;
-    mem = fitrig::scratch_estimate(S->cfg.base, (int)(carried + n_snap), H, W);
-    if (budget > 0 && field_mem + mem + S->mem_fields > budget) return FITRIG_E_BUSY;
-    if (budget == 0 || S->mem_charged + S->mem_fields + field_mem + mem <= budget) break;
+    // exact scratch of the request (the history at its longest)
+    const fitrig::FreqHist hs{(const double*)(uintptr_t)256, keep_ring ? S->cfg.freq_window : 0,
+                              keep_ring ? S->cfg.freq_window : 0, (double*)(uintptr_t)256};
+    mem = fitrig::call_scratch_bytes(S->cfg.base, (int)carried, n_snap, H, W, dtype, keep_ring ? &hs : nullptr,
+                                     S->cfg.cand_cap);
+    if (mem <= 0) return FITRIG_E_INVAL;
+    if (budget > 0 && field_mem + device_bound(S, mem) > budget) return FITRIG_E_BUSY;
+    const int64_t top = S->inflight.empty() ? mem : std::max(mem, *S->inflight.rbegin());
+    if (budget == 0 || field_mem + device_bound(S, top) <= budget) break;
     if (!blocking) return FITRIG_E_BUSY;
     S->cv_done.wait(lk);
   }
@@ -303,6 +367,15 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
   }
   Req* r = new (std::nothrow) Req();
   if (!r) return FITRIG_E_NOMEM;
+  // work queued on the legacy default stream before the submit (where the
+  // stack may have been written) completes before the request reads it
+  if (hipSetDevice(S->cfg.base.device) != hipSuccess ||
+      hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(r->ready, nullptr) != hipSuccess) {
+    if (r->ready) (void)hipEventDestroy(r->ready);
+    delete r;
+    return FITRIG_E_HIP;
+  }
   r->ticket = S->next_ticket++;
   r->field = field_id;
   r->stack = stack;
@@ -314,7 +387,7 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
   r->mem = mem;
   r->t_submit = t_submit;
   S->reqs[r->ticket] = r;
-  S->mem_charged += mem;
+  S->inflight.insert(mem);
   S->outstanding += 1;
   f->frames_submitted += n_snap;
   f->last_use = ++S->use_clock;
@@ -348,6 +421,7 @@ fitrig_status fitrig_poll(fitrig_server* S, int64_t ticket, int32_t wait, fitrig
   out->cand = r->cand.empty() ? nullptr : r->cand.data();
   out->M = r->M;
   out->freq_triples = r->freq_triples;
+  out->replayed = r->replayed;
   out->t_submit_ns = r->t_submit;
   out->t_start_ns = r->t_start;
   out->t_done_ns = r->t_done;

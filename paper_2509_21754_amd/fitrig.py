@@ -14,7 +14,7 @@ import ctypes
 import os
 from typing import Optional
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_TRUNC, E_BUSY, E_NOTREADY, E_SCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
 NOALLOC_SCRATCH_BYTES = 256 << 20
@@ -96,6 +96,7 @@ class fitrig_server_config(ctypes.Structure):
         ("mem_budget", ctypes.c_int64),
         ("cand_cap", ctypes.c_int64),
         ("freq_window", ctypes.c_int32),
+        ("graphs", ctypes.c_int32),
     ]
 
 
@@ -113,6 +114,7 @@ class fitrig_result(ctypes.Structure):
         ("t_start_ns", ctypes.c_int64),
         ("t_done_ns", ctypes.c_int64),
         ("freq_triples", ctypes.c_int32),
+        ("replayed", ctypes.c_int32),
     ]
 
 
@@ -459,9 +461,10 @@ class Server:
     (and unchanged) until their ticket is done."""
 
     def __init__(self, n_slots: int = 4, max_fields: int = 64, mem_budget: int = 0, cand_cap: int = 1 << 16,
-                 freq_window: int = 0, **base):
+                 freq_window: int = 0, graphs: int = 1, **base):
         self.cfg = fitrig_server_config_default(n_slots=n_slots, max_fields=max_fields, mem_budget=mem_budget,
-                                                cand_cap=cand_cap, freq_window=freq_window, **base)
+                                                cand_cap=cand_cap, freq_window=freq_window, graphs=graphs,
+                                                **base)
         rc, h = fitrig_server_create(self.cfg)
         if rc != OK:
             raise FitrigError(rc, "fitrig_server_create")
@@ -497,6 +500,7 @@ class Server:
         arr = _cand_array(ctypes.cast(r.cand, ctypes.c_void_p).value, k) if (k and r.cand) else _cand_array(0, 0)
         return dict(ticket=r.ticket, field_id=r.field_id, status=r.status, n_triples=r.n_triples,
                     first_triple=r.first_triple, n_cand=r.n_cand, M=r.M, freq_triples=r.freq_triples,
+                    replayed=r.replayed,
                     cands=[_rec_dict(x) for x in arr] if as_dicts else arr,
                     t_submit_ns=r.t_submit_ns, t_start_ns=r.t_start_ns, t_done_ns=r.t_done_ns)
 

@@ -40,8 +40,9 @@ def _plan(seed):
     return fields, reqs
 
 
-@pytest.mark.parametrize("branches,extra", [(1, {}), (3, {}), (3, dict(sigma_est=1)), (3, dict(mode=1, tile=8))])
-def test_server_mix_equals_alone(branches, extra):
+@pytest.mark.parametrize("branches,extra,graphs", [(1, {}, 1), (3, {}, 1), (3, {}, 0), (3, dict(sigma_est=1), 1),
+                                                   (3, dict(mode=1, tile=8), 1)])
+def test_server_mix_equals_alone(branches, extra, graphs):
     from paper_2509_21754_amd import Server
 
     tau = 4.0
@@ -51,7 +52,7 @@ def test_server_mix_equals_alone(branches, extra):
     frames = {f: [] for f in fields}   # every frame submitted so far, host float copies
     submitted = []
     keep = []
-    with Server(n_slots=3, max_fields=8, **cfg) as srv:
+    with Server(n_slots=3, max_fields=8, graphs=graphs, **cfg) as srv:
         for i, (f, n) in enumerate(reqs):
             H, W, dt = fields[f]
             X = structured_stack(100 * f + i, n, H, W)
@@ -67,6 +68,7 @@ def test_server_mix_equals_alone(branches, extra):
         done = {tk: r for (tk, *_), r in zip(submitted, results)}
         for (tk, f, first, used, dt), r in zip(submitted, results):
             assert r["status"] in (0, -4), r["status"]
+            assert r["replayed"] == graphs
             assert r["field_id"] == f
             assert r["first_triple"] == first
             assert r["n_triples"] == used.shape[0] - 2
@@ -91,6 +93,62 @@ def test_server_mix_equals_alone(branches, extra):
                 assert b["first_triple"] == a["first_triple"] + a["n_triples"]
         for tk, *_ in submitted:
             srv.release(tk)
+
+
+def test_server_graph_replays_of_one_shape():
+    """One slot serves one field with requests of one shape: the captured
+    launch sequence is replayed again and again (torch work and host
+    synchronisations between the replays), and every result equals the same
+    frames run alone."""
+    from paper_2509_21754_amd import Server
+
+    tau = 4.0
+    cfg = dict(window=7, branches=3, tile=16)
+    prev = None
+    with Server(n_slots=1, graphs=1, **cfg) as srv:
+        for i in range(6):
+            X = structured_stack(300 + i, 5, 96, 300)
+            t = torch.from_numpy(X).cuda()
+            junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between the replays
+            torch.cuda.synchronize()
+            tk = srv.submit(0, t, tau)
+            r = srv.poll(tk, as_dicts=False)
+            float(junk)
+            assert r["status"] in (0, -4) and r["replayed"] == 1
+            used = X if prev is None else np.concatenate([prev, X])
+            alone, _, _ = _alone(torch.from_numpy(np.ascontiguousarray(used)).cuda(), tau, **cfg)
+            got = r["cands"].copy()
+            img = got["branch"] == ref.IMAGE
+            got["triple"][img] -= r["first_triple"]
+            assert got.tobytes() == alone.tobytes(), i
+            prev = X[-2:]
+            srv.release(tk)
+
+
+def test_server_presized_slots_bound_device_memory():
+    """With capacity hints every slot is sized at create and charged against
+    the budget; the device memory the server takes stays within the budget,
+    also when a request larger than the hints grows a slot."""
+    from paper_2509_21754_amd import FitrigError, Server
+
+    stacks = [torch.from_numpy(structured_stack(400 + i, 6, 256, 512)).cuda() for i in range(8)]
+    big = torch.zeros((6, 600, 600), device="cuda")
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    budget = 1 << 30
+    with pytest.raises(FitrigError):
+        Server(n_slots=4, mem_budget=1 << 20, max_pixels=256 * 512, max_snap=6, window=7)
+    with Server(n_slots=4, mem_budget=budget, max_pixels=256 * 512, max_snap=6, window=7) as srv:
+        low = free0 - torch.cuda.mem_get_info()[0]
+        tks = [srv.submit(i % 3, s, 5.0) for i, s in enumerate(stacks)]
+        tks.append(srv.submit(99, big, 5.0))    # more pixels than the hints
+        for tk in tks:
+            r = srv.poll(tk)
+            assert r["status"] in (0, -4)
+            low = max(low, free0 - torch.cuda.mem_get_info()[0])
+            srv.release(tk)
+    # slack for the runtime's own per-stream and per-graph memory
+    assert low <= budget + (64 << 20), low
 
 
 def test_server_admission_by_memory():
