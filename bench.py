@@ -99,7 +99,7 @@ def cpu_baseline(spec_name: str) -> dict:
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     threads = int(os.environ.get("OMP_NUM_THREADS") or threads)
     big = (4096, 2048, 12) if base.H >= 4096 else (base.H, base.W, base.n)
-    small = (1024, 1024, 12) if base.H >= 4096 else (base.H, base.W, base.n)
+    small = (2048, 2048, 12) if base.H >= 4096 else (base.H, base.W, base.n)
     v_all, dt_all, used_all, spec = run(*big, threads)
     v_one, dt_one, _, _ = run(*small, 1)
     ref.set_threads(threads)
@@ -386,6 +386,46 @@ def localisation(ctx, stack, tau: float, spec, stream) -> dict:
             "us_per_peak": round(statistics.median(ms) * 1e3 / max(len(peaks), 1), 3)}
 
 
+def host_stream(ctx, stack, tau: float, chunk: int, steps: int, ref_n_cand: int) -> dict:
+    """The same stack from page-locked host memory, streamed to the device in
+    chunks of frames (the copy of the next chunk overlaps the path over the
+    current one), against the plain host-to-device copy rate of the link."""
+    import torch
+
+    n, H, W = stack.shape
+    h = torch.empty(stack.shape, dtype=stack.dtype, pin_memory=True)
+    h.copy_(stack)
+    torch.cuda.synchronize()
+    # ceiling: plain pinned host-to-device copies of one chunk
+    d = torch.empty((chunk, H, W), dtype=stack.dtype, device=stack.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    d.copy_(h[:chunk], non_blocking=True)
+    e0.record()
+    reps = max(1, n // chunk)
+    for i in range(reps):
+        d.copy_(h[i * chunk:(i + 1) * chunk], non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    chunk_bytes = chunk * H * W * stack.element_size()
+    ceil_gbs = reps * chunk_bytes / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del d
+    ctx.detect_host(h, tau, chunk, as_dicts=False)  # warm
+    times, ncand = [], None
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        c, st, rc = ctx.detect_host(h, tau, chunk, as_dicts=False)
+        times.append(time.perf_counter() - t0)
+        ncand = st["n_cand"]
+    t = statistics.median(times)
+    total = n * H * W * stack.element_size()
+    del h
+    return {"value": round(n * H * W / t / 1e6, 1), "unit": "Mpix/s", "ms_per_step": round(t * 1e3, 2),
+            "chunk_frames": chunk, "steps": steps, "h2d_gbs": round(total / t / 1e9, 2),
+            "h2d_copy_ceiling_gbs": round(ceil_gbs, 2), "frac_of_copy_ceiling": round(total / t / 1e9 / ceil_gbs, 3),
+            "n_candidates": ncand, "same_candidate_count_as_device": ncand == ref_n_cand,
+            "note": "stack in page-locked host memory; wall time of fitrig_detect_host (median)"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -408,6 +448,9 @@ def main() -> int:
     ap.add_argument("--serving-budget-gib", type=float, default=48.0)
     ap.add_argument("--serving-freq-window", type=int, default=30,
                     help="triples of a field's history the frequency branch covers (0 = the request's own)")
+    ap.add_argument("--no-host-stream", action="store_true",
+                    help="skip the run of the same stack streamed from host memory")
+    ap.add_argument("--host-chunk", type=int, default=4, help="frames per host-to-device chunk")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -512,6 +555,9 @@ def main() -> int:
         del s16
     if args.mode == "sliding":
         out["localisation"] = localisation(ctx, stack, tau, spec, stream)
+    if not args.no_host_stream:
+        print("[bench] streaming the stack from host memory", file=sys.stderr, flush=True)
+        out["host_stream"] = host_stream(ctx, stack, tau, args.host_chunk, 3, stats["n_cand"])
     if raw is not None:
         print("[bench] precision report on crops", file=sys.stderr, flush=True)
         out["precision_report"] = precision_report(spec, stack, raw, origins, stats, cands)

@@ -218,6 +218,34 @@ fitrig_status fitrig_detect_noalloc(fitrig_ctx* ctx, const void* stack, fitrig_d
                                     float* index_map, float* eta_map, float* eta_px_map,
                                     fitrig_stats* stats, void* hip_stream);
 
+/*
+ * Stacks in host memory, streamed to the device in chunks of frames. The
+ * paper's real-time design moves each snapshot over PCIe while the trigger
+ * kernel works on the previous one (Sec. 3.2); here the copy of chunk i + 1
+ * runs on a stream of its own while the whole path runs over chunk i. A
+ * chunk carries the two frames before it (its first two triples reach back
+ * into the previous chunk) and extends a device copy of the tile cube of
+ * every triple so far, so the frequency branch runs once, on the last chunk,
+ * over the whole series. Every result equals fitrig_detect's on the same
+ * stack in device memory, bit for bit.
+ *   host_stack   host, [n_snap][H][W] row-major, dtype as given; page-locked
+ *                memory (hipHostMalloc, a pinned torch tensor) lets the copies
+ *                overlap the kernels, pageable memory works but does not
+ *   chunk_frames frames per copy (>= 1; the first chunk holds at least 3)
+ *   cand, cand_cap, n_cand, eta_map (device, nullable), stats: as
+ *                fitrig_detect (no index maps: they would not fit the point
+ *                of streaming)
+ * The call allocates (and frees) 3 chunk buffers (4 when chunk_frames = 1)
+ * and, for the frequency branch, an (n_snap-2) * ceil(H/tile) *
+ * ceil(W/tile) FP64 history; it is synchronous on the context's stream.
+ * Errors: E_INVAL (as fitrig_detect, chunk_frames < 1, FITRIG_FREQ_PIXEL in
+ * the config), E_NOMEM, E_HIP.
+ */
+fitrig_status fitrig_detect_host(fitrig_ctx* ctx, const void* host_stack, fitrig_dtype dtype, int32_t n_snap,
+                                 int32_t H, int32_t W, double sigma, int32_t chunk_frames,
+                                 fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand,
+                                 float* eta_map, fitrig_stats* stats);
+
 /* Releases the context and its device memory. Errors: E_INVAL (null). */
 fitrig_status fitrig_destroy(fitrig_ctx* ctx);
 

@@ -401,7 +401,7 @@ Plan make_plan(const fitrig_config& cfg, const Call& c) {
   const bool want_freq = (cfg.branches & FITRIG_FREQ) != 0;
   p.ring = want_freq && c.hist && c.hist->cap > 0;
   p.nfreq = p.ring ? (int)std::min<int64_t>(c.hist->cap, (int64_t)c.hist->n_in + p.np) : p.np;
-  p.freq = want_freq && p.nfreq >= 4;
+  p.freq = want_freq && p.nfreq >= 4 && !(c.hist && c.hist->defer);
   p.fpx = (cfg.branches & FITRIG_FREQ_PIXEL) != 0 && p.sliding && p.np >= 4;
   // the tile cube: frequency branch, history, tile-mode image branch or map
   p.cube_needed = p.freq || p.ring || (!p.sliding && (p.img || c.index_map));
@@ -1310,7 +1310,7 @@ fitrig_status detect_graph(fitrig_ctx* ctx, const Call& c, fitrig_candidate* can
     }
   }
   const GraphKey key{c.n, c.H, c.W, c.ncarry, (int)c.dtype, c.hist ? c.hist->cap : 0, c.hist ? c.hist->n_in : 0,
-                     (c.hist && c.hist->out) ? 1 : 0, cap};
+                     (c.hist && c.hist->out) ? 1 + (c.hist->defer ? 1 : 0) : 0, cap};
   GraphEntry* e = nullptr;
   for (GraphEntry& g : ctx->graphs)
     if (g.key == key) e = &g;
@@ -1478,6 +1478,178 @@ fitrig_status detect_noalloc_impl(fitrig_ctx* ctx, const Call& c, fitrig_candida
                        stats ? stats->mu : nullptr, stats ? stats->sigma : nullptr, stats ? stats->flags : nullptr);
 }
 
+// A call of this shape for the sizing pass (the stack pointer is a stand-in,
+// never dereferenced).
+Call shape_call(int ncarry, int n_new, int H, int W, fitrig_dtype dtype, const FreqHist* hist, int64_t cand_cap,
+                hipStream_t st) {
+  Call c;
+  memset(&c, 0, sizeof(c));
+  c.stack = (const void*)(uintptr_t)256;
+  c.carry0 = ncarry >= 1 ? c.stack : nullptr;
+  c.carry1 = ncarry >= 2 ? c.stack : nullptr;
+  c.ncarry = ncarry;
+  c.dtype = dtype;
+  c.n = ncarry + n_new;
+  c.H = H;
+  c.W = W;
+  c.tau = 1.0;
+  c.hist = hist;
+  c.cand_cap = cand_cap;
+  c.st = st;
+  return c;
+}
+
+// Sizing pass of a host-only context with ctx's config (nothing allocated or
+// launched); false when the shape is not a valid call.
+bool size_shape(const fitrig_config& cfg, const Call& c, fitrig_ctx& tmp) {
+  tmp.cfg = cfg;
+  tmp.cfg.profile = 0;
+  if (c.n < 3 || check_shape(cfg, c) != FITRIG_OK) return false;
+  return sizing_pass(&tmp, c, (size_t)result_layout(c.n - 2, c.cand_cap).bytes) == FITRIG_OK;
+}
+
+// Device memory and streams of one host-resident call, released on scope exit.
+struct HostPipe {
+  int dev = 0;
+  char* buf = nullptr;      // nbuf chunk buffers of cap_frames frames
+  double* hist = nullptr;   // tile cube of every triple so far (frequency branch)
+  hipStream_t copy = nullptr;
+  hipEvent_t ev[4] = {};
+  ~HostPipe() {
+    (void)hipSetDevice(dev);
+    if (copy) (void)hipStreamSynchronize(copy);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (copy) (void)hipStreamDestroy(copy);
+    if (buf) (void)hipFree(buf);
+    if (hist) (void)hipFree(hist);
+  }
+};
+
+// A stack in host memory, streamed in chunks of frames: the copy of chunk
+// i + 1 (on a stream of its own) overlaps the path over chunk i, which
+// carries the two frames before it and extends the tile-cube history; the
+// frequency branch runs on the last chunk over the whole history.
+fitrig_status detect_host_impl(fitrig_ctx* ctx, const char* host, fitrig_dtype dtype, int n, int H, int W,
+                               double tau, int L, fitrig_candidate* cand, int64_t cand_cap, int64_t* n_cand,
+                               float* eta_map, fitrig_stats* stats) {
+  const fitrig_config& cfg = ctx->cfg;
+  if (cfg.branches & FITRIG_FREQ_PIXEL) return FITRIG_E_INVAL;
+  const size_t fb = (size_t)H * W * (dtype == FITRIG_F32 ? 4 : 2);
+  const int L0 = std::min(n, std::max(L, 3));  // the first chunk needs three frames
+  const int nbuf = L >= 2 ? 3 : 4;             // chunk i reads the buffers of chunks i, i-1 (and i-2 when L = 1)
+  std::vector<int> start;
+  for (int s0 = 0; s0 < n; s0 += (s0 == 0 ? L0 : L)) start.push_back(s0);
+  const int nch = (int)start.size();
+  auto len = [&](int i) { return (i + 1 < nch ? start[i + 1] : n) - start[i]; };
+  const int np_all = n - 2;
+  const int tile = cfg.tile;
+  const int64_t ntiles = (int64_t)((H + tile - 1) / tile) * ((W + tile - 1) / tile);
+  const bool freq = (cfg.branches & FITRIG_FREQ) != 0;
+  HostPipe P;
+  P.dev = cfg.device;
+  HIP_TRY(ctx, hipMalloc((void**)&P.buf, (size_t)nbuf * L0 * fb));
+  if (freq) HIP_TRY(ctx, hipMalloc((void**)&P.hist, (size_t)np_all * ntiles * 8));
+  HIP_TRY(ctx, hipStreamCreateWithFlags(&P.copy, hipStreamNonBlocking));
+  for (int i = 0; i < nbuf; ++i) HIP_TRY(ctx, hipEventCreateWithFlags(&P.ev[i], hipEventDisableTiming));
+  auto frame_dev = [&](int f) -> const char* {  // device address of frame f (its chunk resident)
+    int j = nch - 1;
+    while (start[j] > f) --j;
+    return P.buf + (size_t)(j % nbuf) * L0 * fb + (size_t)(f - start[j]) * fb;
+  };
+  auto copy_in = [&](int i) -> fitrig_status {
+    char* dst = P.buf + (size_t)(i % nbuf) * L0 * fb;
+    HIP_TRY(ctx, hipMemcpyAsync(dst, host + (size_t)start[i] * fb, (size_t)len(i) * fb, hipMemcpyHostToDevice, P.copy));
+    HIP_TRY(ctx, hipEventRecord(P.ev[i % nbuf], P.copy));
+    return FITRIG_OK;
+  };
+  fitrig_status rc;
+  // scratch for the largest chunk call up front (first chunk, then a chunk
+  // with two carried frames and the longest history), so no call grows it
+  {
+    FreqHist h0{P.hist, 0, np_all, P.hist, nch > 1 ? 1 : 0};
+    Call c0 = shape_call(0, L0, H, W, dtype, freq ? &h0 : nullptr, cand_cap, ctx->stream);
+    if ((rc = check_shape(cfg, c0)) != FITRIG_OK) return rc;
+    if ((rc = sizing_pass(ctx, c0, (size_t)result_layout(c0.n - 2, cand_cap).bytes)) != FITRIG_OK ||
+        (rc = provision(ctx, ctx->stream)) != FITRIG_OK)
+      return rc;
+    if (nch > 1) {
+      FreqHist h1{P.hist, np_all - L, np_all, P.hist, 0};
+      Call c1 = shape_call(2, L, H, W, dtype, freq ? &h1 : nullptr, cand_cap, ctx->stream);
+      if ((rc = sizing_pass(ctx, c1, (size_t)result_layout(c1.n - 2, cand_cap).bytes)) != FITRIG_OK ||
+          (rc = provision(ctx, ctx->stream)) != FITRIG_OK)
+        return rc;
+    }
+  }
+  if ((rc = copy_in(0)) != FITRIG_OK) return rc;
+  int64_t total = 0, written = 0;
+  int done_triples = 0;
+  fitrig_status status = FITRIG_OK;
+  double M = -INFINITY;
+  fitrig_stats last;
+  memset(&last, 0, sizeof(last));
+  int64_t n_img = 0;
+  uint32_t ran = 0;
+  for (int i = 0; i < nch; ++i) {
+    if (i + 1 < nch && (rc = copy_in(i + 1)) != FITRIG_OK) return rc;
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, P.ev[i % nbuf], 0));
+    Call c;
+    memset(&c, 0, sizeof(c));
+    c.stack = P.buf + (size_t)(i % nbuf) * L0 * fb;
+    c.ncarry = i == 0 ? 0 : 2;
+    c.carry0 = i == 0 ? nullptr : frame_dev(start[i] - 2);
+    c.carry1 = i == 0 ? nullptr : frame_dev(start[i] - 1);
+    c.dtype = dtype;
+    c.n = c.ncarry + len(i);
+    c.H = H;
+    c.W = W;
+    c.tau = tau;
+    c.eta_map = i + 1 == nch ? eta_map : nullptr;
+    c.st = ctx->stream;
+    const FreqHist h{P.hist, done_triples, np_all, P.hist, i + 1 < nch ? 1 : 0};
+    c.hist = freq ? &h : nullptr;
+    const int64_t room = std::max<int64_t>(0, cand_cap - written);
+    c.cand_cap = room;
+    const int np = c.n - 2;
+    fitrig_stats st;
+    memset(&st, 0, sizeof(st));
+    st.mu = stats && stats->mu ? stats->mu + done_triples : nullptr;
+    st.sigma = stats && stats->sigma ? stats->sigma + done_triples : nullptr;
+    st.flags = stats && stats->flags ? stats->flags + done_triples : nullptr;
+    int64_t nc = 0;
+    rc = detect_impl(ctx, c, room > 0 ? cand + written : nullptr, &nc, &st, false);
+    if (rc != FITRIG_OK && rc != FITRIG_E_TRUNC) return rc;
+    if (rc == FITRIG_E_TRUNC) status = FITRIG_E_TRUNC;
+    const int64_t k = std::min(nc, room);
+    for (int64_t j = 0; j < k; ++j)
+      if (cand[written + j].branch == FITRIG_IMAGE) cand[written + j].triple += done_triples;
+    written += k;
+    total += nc;
+    n_img += st.n_image_cand;
+    ran |= st.ran;
+    M = std::max(M, st.M);
+    last = st;
+    done_triples += np;
+  }
+  *n_cand = total;
+  if (total > cand_cap) status = FITRIG_E_TRUNC;
+  if (stats) {
+    stats->M = M;
+    stats->n_triples = np_all;
+    stats->status = status;
+    stats->eta_mu = last.eta_mu;
+    stats->eta_sigma = last.eta_sigma;
+    stats->n_image_cand = n_img;
+    stats->n_freq_cand = last.n_freq_cand;
+    stats->n_freq_px_cand = 0;
+    stats->eta_px_mu = 0.0;
+    stats->eta_px_sigma = 0.0;
+    stats->ran = (ran & FITRIG_IMAGE) | (last.ran & FITRIG_FREQ);
+    stats->eta_flags = last.eta_flags;
+  }
+  return status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1632,6 +1804,19 @@ fitrig_status fitrig_detect_noalloc(fitrig_ctx* ctx, const void* stack, fitrig_d
   return detect_noalloc_impl(ctx, c, cand, n_cand, stats);
 }
 
+fitrig_status fitrig_detect_host(fitrig_ctx* ctx, const void* host_stack, fitrig_dtype dtype, int32_t n_snap,
+                                 int32_t H, int32_t W, double sigma, int32_t chunk_frames, fitrig_candidate* cand,
+                                 int64_t cand_cap, int64_t* n_cand, float* eta_map, fitrig_stats* stats) {
+  if (!ctx) return FITRIG_E_INVAL;
+  fitrig_status rc = check_args(host_stack, dtype, H, W, sigma, cand, cand_cap, n_cand);
+  if (rc != FITRIG_OK) return rc;
+  if (n_snap < 3 || chunk_frames < 1) return FITRIG_E_INVAL;
+  *n_cand = 0;
+  if (hipSetDevice(ctx->cfg.device) != hipSuccess) return FITRIG_E_HIP;
+  return detect_host_impl(ctx, (const char*)host_stack, dtype, n_snap, H, W, sigma, chunk_frames, cand, cand_cap,
+                          n_cand, eta_map, stats);
+}
+
 }  // extern "C"
 
 namespace fitrig {
@@ -1698,37 +1883,6 @@ int64_t ctx_device_bytes(const fitrig_ctx* ctx) {
   return b;
 }
 
-namespace {
-// A call of this shape for the sizing pass (the stack pointer is a stand-in,
-// never dereferenced).
-Call shape_call(int ncarry, int n_new, int H, int W, fitrig_dtype dtype, const FreqHist* hist, int64_t cand_cap,
-                hipStream_t st) {
-  Call c;
-  memset(&c, 0, sizeof(c));
-  c.stack = (const void*)(uintptr_t)256;
-  c.carry0 = ncarry >= 1 ? c.stack : nullptr;
-  c.carry1 = ncarry >= 2 ? c.stack : nullptr;
-  c.ncarry = ncarry;
-  c.dtype = dtype;
-  c.n = ncarry + n_new;
-  c.H = H;
-  c.W = W;
-  c.tau = 1.0;
-  c.hist = hist;
-  c.cand_cap = cand_cap;
-  c.st = st;
-  return c;
-}
-
-// Sizing pass of a host-only context with ctx's config (nothing allocated or
-// launched); false when the shape is not a valid call.
-bool size_shape(const fitrig_config& cfg, const Call& c, fitrig_ctx& tmp) {
-  tmp.cfg = cfg;
-  tmp.cfg.profile = 0;
-  if (c.n < 3 || check_shape(cfg, c) != FITRIG_OK) return false;
-  return sizing_pass(&tmp, c, (size_t)result_layout(c.n - 2, c.cand_cap).bytes) == FITRIG_OK;
-}
-}  // namespace
 
 // Sizes ctx's scratch for a call of this shape (allocates, before serving).
 fitrig_status ctx_presize_for(fitrig_ctx* ctx, int ncarry, int n_new, int H, int W, fitrig_dtype dtype,

@@ -188,6 +188,7 @@ struct FreqHist {
   int n_in;
   int cap;
   double* out;
+  int defer;  // 1: only extend the history; the branch runs on a later call
 };
 
 // Host-side entry points shared between translation units of the library.

@@ -129,7 +129,7 @@ void worker_main(fitrig_server* S, int slot) {
     const void *c0 = nullptr, *c1 = nullptr;
     int nc = 0;
     int64_t first = 0;
-    fitrig::FreqHist fh{nullptr, 0, 0, nullptr};
+    fitrig::FreqHist fh{nullptr, 0, 0, nullptr, 0};
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_ready.wait(lk, [&] { return S->stop || !S->ready.empty(); });
@@ -142,7 +142,7 @@ void worker_main(fitrig_server* S, int slot) {
       if (nc >= 1) c0 = f.carry + (2 - nc) * f.frame_bytes;
       if (nc == 2) c1 = f.carry + f.frame_bytes;
       first = f.frames_seen - nc;
-      if (f.ring) fh = fitrig::FreqHist{f.ring, f.nring, S->cfg.freq_window, f.ring};
+      if (f.ring) fh = fitrig::FreqHist{f.ring, f.nring, S->cfg.freq_window, f.ring, 0};
     }
     r->t_start = now_ns();
     fitrig_stats st;
@@ -270,7 +270,7 @@ fitrig_status fitrig_server_create(const fitrig_server_config* cfg, fitrig_serve
     const int side = (int)ceil(sqrt((double)b.max_pixels));
     const bool ring = S->cfg.freq_window > 0 && (b.branches & FITRIG_FREQ) != 0;
     const fitrig::FreqHist hs{(const double*)(uintptr_t)256, ring ? S->cfg.freq_window : 0,
-                              ring ? S->cfg.freq_window : 0, (double*)(uintptr_t)256};
+                              ring ? S->cfg.freq_window : 0, (double*)(uintptr_t)256, 0};
     for (fitrig_ctx* c : S->ctxs) {
       const fitrig_status rc =
           fitrig::ctx_presize_for(c, 2, b.max_snap, side, side, FITRIG_F32, ring ? &hs : nullptr, S->cfg.cand_cap);
@@ -320,7 +320,7 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
     field_mem = (fresh || resize) ? (int64_t)(2 * fb + rb) : 0;
     // exact scratch of the request (the history at its longest)
     const fitrig::FreqHist hs{(const double*)(uintptr_t)256, keep_ring ? S->cfg.freq_window : 0,
-                              keep_ring ? S->cfg.freq_window : 0, (double*)(uintptr_t)256};
+                              keep_ring ? S->cfg.freq_window : 0, (double*)(uintptr_t)256, 0};
     mem = fitrig::call_scratch_bytes(S->cfg.base, (int)carried, n_snap, H, W, dtype, keep_ring ? &hs : nullptr,
                                      S->cfg.cand_cap);
     if (mem <= 0) return FITRIG_E_INVAL;

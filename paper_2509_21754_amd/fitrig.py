@@ -123,6 +123,7 @@ EXPORTS = (
     "fitrig_create",
     "fitrig_detect",
     "fitrig_detect_noalloc",
+    "fitrig_detect_host",
     "fitrig_destroy",
     "fitrig_status_string",
     "fitrig_last_hip_error",
@@ -160,6 +161,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fitrig_detect.restype = i32
     L.fitrig_detect_noalloc.argtypes = L.fitrig_detect.argtypes
     L.fitrig_detect_noalloc.restype = i32
+    L.fitrig_detect_host.argtypes = [vp, vp, i32, i32, i32, i32, dbl, i32, ctypes.POINTER(fitrig_candidate), i64,
+                                     ctypes.POINTER(i64), vp, ctypes.POINTER(fitrig_stats)]
+    L.fitrig_detect_host.restype = i32
     L.fitrig_destroy.argtypes = [vp]
     L.fitrig_destroy.restype = i32
     L.fitrig_status_string.argtypes = [i32]
@@ -216,6 +220,12 @@ def fitrig_detect_noalloc(ctx, stack_ptr, dtype, n_snap, H, W, sigma, cand, cand
                           eta_px_map, stats, hip_stream) -> int:
     return load().fitrig_detect_noalloc(ctx, stack_ptr, dtype, n_snap, H, W, sigma, cand, cand_cap, n_cand,
                                         index_map, eta_map, eta_px_map, stats, hip_stream)
+
+
+def fitrig_detect_host(ctx, host_ptr, dtype, n_snap, H, W, sigma, chunk_frames, cand, cand_cap, n_cand, eta_map,
+                       stats) -> int:
+    return load().fitrig_detect_host(ctx, host_ptr, dtype, n_snap, H, W, sigma, chunk_frames, cand, cand_cap, n_cand,
+                                     eta_map, stats)
 
 
 def fitrig_destroy(ctx) -> int:
@@ -434,6 +444,9 @@ class Context:
         rc = b["st"].status
         if rc == E_TRUNC and raise_on_trunc:
             raise FitrigError(rc, "fitrig_detect")
+        return self._results(b, cand_cap, np_, rc, as_dicts)
+
+    def _results(self, b, cand_cap, np_, rc, as_dicts):
         ncand = b["n"].value
         k = min(ncand, cand_cap)
         arr = _cand_array(ctypes.addressof(b["cand"]), k)
@@ -445,6 +458,30 @@ class Context:
                      n_image_cand=st.n_image_cand, n_freq_cand=st.n_freq_cand,
                      n_freq_px_cand=st.n_freq_px_cand, n_cand=ncand, status=st.status)
         return cands, stats, rc
+
+    def detect_host(self, stack, sigma: float, chunk_frames: int, *, cand_cap: int = 1 << 16, eta_map=None,
+                    as_dicts: bool = True):
+        """Run the path on a stack in host memory ([n][H][W] CPU tensor,
+        f32/f16/bf16; pinned memory overlaps the copies), streamed in chunks
+        of ``chunk_frames`` frames. Returns (candidates, stats, status) as
+        ``detect``."""
+        import torch
+
+        if stack.is_cuda or not stack.is_contiguous() or stack.dim() != 3:
+            raise ValueError("stack must be a contiguous 3-D host tensor")
+        if eta_map is not None and (not eta_map.is_cuda or eta_map.dtype != torch.float32 or
+                                    not eta_map.is_contiguous()):
+            raise ValueError("eta_map must be a contiguous float32 device tensor")
+        n, H, W = stack.shape
+        np_ = max(n - 2, 0)
+        b = self._buffers(cand_cap, np_)
+        rc = fitrig_detect_host(self.handle, ctypes.c_void_p(stack.data_ptr()), _dtype_code(stack), n, H, W,
+                                float(sigma), int(chunk_frames), b["cand"], cand_cap, ctypes.byref(b["n"]),
+                                ctypes.c_void_p(eta_map.data_ptr()) if eta_map is not None else None,
+                                ctypes.byref(b["st"]))
+        if rc not in (OK, E_TRUNC):
+            raise FitrigError(rc, "fitrig_detect_host", fitrig_last_hip_error(self.handle))
+        return self._results(b, cand_cap, np_, rc, as_dicts)
 
     def enqueue(self, stack, sigma, b, cand_cap, index_map, eta_map, eta_px_map, stream) -> int:
         """The asynchronous C call on ``stream`` with the host buffers ``b``
