@@ -303,6 +303,43 @@ int32_t fitrig_abi_version(void);
 fitrig_status fitrig_interp_peaks(const float* map, int32_t H, int32_t W, const int32_t* py, const int32_t* px,
                                   int32_t n, int32_t method, int32_t sub, double* out, void* hip_stream);
 
+/* ---- snapshot accumulation -------------------------------------------------
+ * For very short sampling periods adjacent snapshots are nearly the same and
+ * their differences nearly blank; the paper then applies the method to sums
+ * of adjacent snapshots, combined until adjacent sums differ enough
+ * (Sec. 3.3.2, Fig. accum: the combination is a plain sum). The paper gives
+ * no criterion; this library uses one factor K for the whole stack (so the
+ * accumulated series stays uniformly sampled for the frequency branch):
+ *   Y_j  = sum_{k = jK}^{jK+K-1} X_k, j = 0 .. P-1, P = floor(n_snap / K)
+ *          (FP32, added in frame order; the last n_snap - PK snapshots are
+ *          dropped)
+ *   c_j  = sum_p |Y_{j+1}(p) - Y_j(p)| / sum_p |Y_j(p)| over all pixels
+ *   C(K) = median of c_0 .. c_{P-2} (mean of the two middle values for an
+ *          even count; NaN when P < 2)
+ *   automatic K = the smallest K <= k_max with P >= 3 and C(K) >= gamma,
+ *          else the largest K <= k_max with P >= 3.
+ * The accumulated stack is an FP32 stack for fitrig_detect.
+ */
+
+/* out: device float [n_snap / K][H][W]. stack: device, dtype as given.
+ * Enqueued on hip_stream (NULL: the legacy default stream); returns once
+ * enqueued. Errors: E_INVAL (null pointers, sizes as fitrig_detect, K < 1,
+ * K > n_snap, unknown dtype), E_HIP. */
+fitrig_status fitrig_accumulate(const void* stack, fitrig_dtype dtype, int32_t n_snap, int32_t H, int32_t W,
+                                int32_t K, float* out, void* hip_stream);
+
+/* The automatic factor. K_out: host, the chosen K. contrast: host, nullable,
+ * k_max doubles C(1) .. C(k_max). Runs on hip_stream (NULL: the legacy
+ * default stream) and returns when the results are written; allocates a
+ * small device buffer for the duration of the call. Each C(K) reads the
+ * stack about twice.
+ * Errors: E_INVAL (null pointers, sizes as fitrig_detect, n_snap outside
+ * 3 .. 65536, k_max < 1, gamma negative or not finite, unknown dtype),
+ * E_NOMEM, E_HIP. */
+fitrig_status fitrig_accum_factor(const void* stack, fitrig_dtype dtype, int32_t n_snap, int32_t H, int32_t W,
+                                  double gamma, int32_t k_max, int32_t* K_out, double* contrast,
+                                  void* hip_stream);
+
 /* ---- serving form ----------------------------------------------------------
  * A real-time trigger loop: requests are snapshot stacks of a field (a
  * fixed sky position and image size). The server keeps each field's last two

@@ -136,6 +136,8 @@ EXPORTS = (
     "fitrig_release",
     "fitrig_server_destroy",
     "fitrig_interp_peaks",
+    "fitrig_accumulate",
+    "fitrig_accum_factor",
 )
 N_PHASES = 5
 PHASES = ("index_pass", "spread", "image_select", "freq_branch", "host_copy")
@@ -188,6 +190,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fitrig_server_destroy.restype = i32
     L.fitrig_interp_peaks.argtypes = [vp, i32, i32, vp, vp, i32, i32, i32, vp, vp]
     L.fitrig_interp_peaks.restype = i32
+    L.fitrig_accumulate.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
+    L.fitrig_accumulate.restype = i32
+    L.fitrig_accum_factor.argtypes = [vp, i32, i32, i32, i32, dbl, i32, ctypes.POINTER(i32),
+                                      ctypes.POINTER(ctypes.c_double), vp]
+    L.fitrig_accum_factor.restype = i32
     _lib = L
     return L
 
@@ -564,3 +571,45 @@ class Server:
 
     def __exit__(self, *a):
         self.close()
+
+
+# ---- snapshot accumulation ----------------------------------------------------
+
+def fitrig_accumulate(stack_ptr, dtype, n_snap, H, W, K, out_ptr, hip_stream) -> int:
+    return load().fitrig_accumulate(stack_ptr, dtype, n_snap, H, W, K, out_ptr, hip_stream)
+
+
+def fitrig_accum_factor(stack_ptr, dtype, n_snap, H, W, gamma, k_max, K_out, contrast, hip_stream) -> int:
+    return load().fitrig_accum_factor(stack_ptr, dtype, n_snap, H, W, gamma, k_max, K_out, contrast, hip_stream)
+
+
+def accumulate(stack, K: int):
+    """Sums of K consecutive snapshots ([n // K][H][W] float32 device tensor),
+    enqueued on torch's current stream."""
+    import torch
+
+    if not stack.is_cuda or not stack.is_contiguous() or stack.dim() != 3:
+        raise ValueError("stack must be a contiguous 3-D device tensor")
+    n, H, W = stack.shape
+    out = torch.empty((max(n // max(K, 1), 0), H, W), dtype=torch.float32, device=stack.device)
+    rc = fitrig_accumulate(ctypes.c_void_p(stack.data_ptr()), _dtype_code(stack), n, H, W, int(K),
+                           ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != OK:
+        raise FitrigError(rc, "fitrig_accumulate")
+    return out
+
+
+def accum_factor(stack, gamma: float, k_max: int):
+    """(K, [C(1) .. C(k_max)]): the automatic accumulation factor, on torch's current stream."""
+    import torch
+
+    if not stack.is_cuda or not stack.is_contiguous() or stack.dim() != 3:
+        raise ValueError("stack must be a contiguous 3-D device tensor")
+    n, H, W = stack.shape
+    K = ctypes.c_int32()
+    C = (ctypes.c_double * max(int(k_max), 1))()
+    rc = fitrig_accum_factor(ctypes.c_void_p(stack.data_ptr()), _dtype_code(stack), n, H, W, float(gamma),
+                             int(k_max), ctypes.byref(K), C, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != OK:
+        raise FitrigError(rc, "fitrig_accum_factor")
+    return K.value, list(C)[:k_max]
