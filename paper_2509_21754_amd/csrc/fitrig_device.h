@@ -215,19 +215,20 @@ __device__ __forceinline__ void pix_ratio(float dl, float ref, float Cf, float& 
   }
 }
 
+// Pointwise terms of one pixel from its three frames x0, x1, x2 (x1 the
+// reference). The frame differences x2 - x1 and x1 - x0 are exact in FP64
+// (24-bit significands), so Delta = ||x2 - x1| - |x1 - x0|| (Eq. (3)) is
+// rounded once, to FP32, and its error stays within half an ulp of Delta.
+// (Differences rounded to FP32 first leave an error of the order of
+// ulp(x2 - x1) in Delta, which r = Delta / |x1| magnifies without bound as the
+// reference approaches zero.) dd is returned signed, Delta = |dd| (the
+// absolute value is applied where it is consumed).
 template <bool RS>
-__device__ __forceinline__ void pix_terms(float d_new, float d_old, float ref, float Cf, float& dl, float& rl) {
-  dl = fabsf(fabsf(d_new) - fabsf(d_old));
-  pix_ratio<RS>(dl, ref, Cf, rl);
-}
-
-// Same terms, Delta returned signed: Delta = |dd| (the absolute value is
-// applied where it is consumed, as a source modifier).
-template <bool RS>
-__device__ __forceinline__ void pix_terms_signed(float d_new, float d_old, float ref, float Cf, float& dd,
-                                                 float& rl) {
-  dd = fabsf(d_new) - fabsf(d_old);
-  pix_ratio<RS>(fabsf(dd), ref, Cf, rl);
+__device__ __forceinline__ void pix3(float x0, float x1, float x2, float Cf, float& dd, float& rl) {
+  const double a = (double)x2 - (double)x1;
+  const double b = (double)x1 - (double)x0;
+  dd = (float)(fabs(a) - fabs(b));
+  pix_ratio<RS>(fabsf(dd), x1, Cf, rl);
 }
 
 // 1 / n^2 for a window of n in-image cells (n = rows * cols).
@@ -371,8 +372,8 @@ constexpr int kOffMasked = 0x40000000;
 // ---------------------------------------------------------------------------
 // Streaming index kernel (sliding window). One workgroup owns 16 output rows
 // x out_w output columns and walks every frame once, keeping the previous
-// frame and the previous difference of its (16 + 2H) x 256 input pixels in
-// registers; the next frame is loaded while the current one is reduced.
+// two frames of its (16 + 2H) x 256 input pixels in registers; the next
+// frame is loaded while the current one is reduced.
 // Per triple it writes FP64 moment partials (one per wave), the maximum q
 // of every 64-cell row segment, optional q map rows, and (tile == 32) the
 // per-column sums of the 32-row tiles for the frequency branch.
@@ -430,11 +431,10 @@ struct Stream {
     }
   }
 
-  // One frame: P holds frame k-1 (becomes the load target of frame k+1), C
-  // holds frame k; DI holds the difference of frames k-1, k-2 and DO receives
-  // the difference of frames k, k-1 (the two swap between calls).
+  // One frame: X0, P, C hold frames k-2, k-1, k; X0 becomes the load target
+  // of frame k+1 (the three rotate between calls).
   template <bool ALLROWS>
-  __device__ __forceinline__ void step(int k, float* P, const float* C, const float* DI, float* DO) {
+  __device__ __forceinline__ void step(int k, float* X0, const float* P, const float* C) {
     // running maximum on the signed-int view of the bits: it orders every
     // positive float correctly and maps non-positive values below them, which
     // is all max(., C) with C > 0 needs
@@ -445,17 +445,11 @@ struct Stream {
     float dl[NR], rl[NR];
     if (k >= 2) {
 #pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        DO[i] = C[i] - P[i];
-        pix_terms_signed<RS>(DO[i], DI[i], P[i], A.Cf, dl[i], rl[i]);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < NR; ++i) DO[i] = C[i] - P[i];
+      for (int i = 0; i < NR; ++i) pix3<RS>(X0[i], P[i], C[i], A.Cf, dl[i], rl[i]);
     }
-    // the next frame's loads go straight into P (after the last frame the
+    // the next frame's loads go straight into X0 (after the last frame the
     // same frame is re-read from cache: an unconditional load avoids copies)
-    load<ALLROWS>(k + 1 < A.n ? k + 1 : k, P);
+    load<ALLROWS>(k + 1 < A.n ? k + 1 : k, X0);
     if (k < 2) return;
     const int s = k - 2;
     // vertical windows, one quantity at a time (each goes to LDS at once, so
@@ -668,23 +662,26 @@ __global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
   for (int i = st.lane; i < 3 * kBand * S::LDW; i += kLanes) (&sh.V[0][0][0])[i] = 0.0f;
   for (int i = st.lane; i < 3 * (kLanes + 2 * S::CPAD); i += kLanes) (&sh.col[0][0])[i] = 0.0f;
   __syncthreads();
-  float fa[S::NR], fb[S::NR], da[S::NR], db[S::NR];
+  // frames k-2, k-1, k rotate through fa, fb, fc
+  float fa[S::NR], fb[S::NR], fc[S::NR];
 #pragma unroll
   for (int i = 0; i < S::NR; ++i) {
     fa[i] = 0.0f;
-    da[i] = 0.0f;
+    fb[i] = 0.0f;
   }
   if (st.all_rows) {
-    st.template load<true>(0, fb);
-    for (int k = 0; k < A.n; k += 2) {
-      st.template step<true>(k, fa, fb, da, db);
-      if (k + 1 < A.n) st.template step<true>(k + 1, fb, fa, db, da);
+    st.template load<true>(0, fc);
+    for (int k = 0; k < A.n; k += 3) {
+      st.template step<true>(k, fa, fb, fc);
+      if (k + 1 < A.n) st.template step<true>(k + 1, fb, fc, fa);
+      if (k + 2 < A.n) st.template step<true>(k + 2, fc, fa, fb);
     }
   } else {
-    st.template load<false>(0, fb);
-    for (int k = 0; k < A.n; k += 2) {
-      st.template step<false>(k, fa, fb, da, db);
-      if (k + 1 < A.n) st.template step<false>(k + 1, fb, fa, db, da);
+    st.template load<false>(0, fc);
+    for (int k = 0; k < A.n; k += 3) {
+      st.template step<false>(k, fa, fb, fc);
+      if (k + 1 < A.n) st.template step<false>(k + 1, fb, fc, fa);
+      if (k + 2 < A.n) st.template step<false>(k + 2, fc, fa, fb);
     }
   }
   int mx = st.mxi;
@@ -730,7 +727,8 @@ __global__ __launch_bounds__(kLanes) void k_tile(TileArgs A) {
       const float a = to_f<T>(f0[o]), b = to_f<T>(f1[o]), c = to_f<T>(f2[o]);
       mx = fmaxf(mx, fmaxf(a, fmaxf(b, c)));
       float dl, rl;
-      pix_terms<RS>(c - b, b - a, b, A.Cf, dl, rl);
+      pix3<RS>(a, b, c, A.Cf, dl, rl);
+      dl = fabsf(dl);
       sd += (double)dl;
       md = fmax(md, (double)dl);
       sr += (double)rl;
@@ -763,8 +761,8 @@ __global__ __launch_bounds__(kLanes) void k_tile(TileArgs A) {
 // ---------------------------------------------------------------------------
 // Streaming tile-mode kernel (tile a power of two <= 32): one workgroup per (band of tpb
 // whole tile rows, chunk of whole tiles); each lane owns a column, keeps the
-// previous frame and the previous difference of the band's rows in
-// registers and walks every frame once. Per triple it accumulates, per tile
+// previous two frames of the band's rows in registers and walks every frame
+// once. Per triple it accumulates, per tile
 // row of the band, the column's sum Delta, max Delta and sum r (FP32 over at
 // most 32 rows), then one job per tile sums its columns in FP64 and writes
 // the tile's q (Eq. (6) with the in-image count) to the cube.
@@ -782,13 +780,13 @@ __global__ __launch_bounds__(kLanes) void k_tile_stream(TileStreamArgs A) {
   const int x = chunk * kLanes + lane;
   const bool cv = x < A.W;
   const int y0 = band * ROWS;
-  float P[ROWS], D[ROWS];
+  float P[ROWS], X0[ROWS];  // frames k-1, k-2
   int mxi = INT32_MIN;
   const void *fb = A.cd->base, *fc0 = A.cd->carry0, *fc1 = A.cd->carry1;
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
     P[i] = 0.0f;
-    D[i] = 0.0f;
+    X0[i] = 0.0f;
   }
   for (int k = 0; k < A.n; ++k) {
     const T* fr = frame_ptr<T>(fb, fc0, fc1, A.ncarry, A.plane, k);
@@ -812,15 +810,15 @@ __global__ __launch_bounds__(kLanes) void k_tile_stream(TileStreamArgs A) {
       const bool in = cv && y < A.H;
       const float c = C[i];
       mxi = max(mxi, __float_as_int(c));
-      const float dn = c - P[i];
       if (k >= 2 && in) {
         float dl, rl;
-        pix_terms<RS>(dn, D[i], P[i], A.Cf, dl, rl);
+        pix3<RS>(X0[i], P[i], c, A.Cf, dl, rl);
+        dl = fabsf(dl);
         sd[i / TILE] += dl;
         md[i / TILE] = fmaxf(md[i / TILE], dl);
         sr[i / TILE] += rl;
       }
-      D[i] = dn;
+      X0[i] = P[i];
       P[i] = c;
     }
     if (k < 2) continue;
@@ -937,7 +935,8 @@ __global__ __launch_bounds__(64) void k_recompute(RecomputeArgs R) {
           b = to_f<T>(f1[o]);
           c = to_f<T>(f2[o]);
         }
-        pix_terms<RS>(c - b, b - a, b, Cf, dl[j], rl[j]);
+        pix3<RS>(a, b, c, Cf, dl[j], rl[j]);
+        dl[j] = fabsf(dl[j]);
       }
       float o8[8];
       Win<H, 8, false>::run(dl, o8, nullptr);

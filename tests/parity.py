@@ -69,15 +69,18 @@ def check_components(gpu: list, refc: list, values_ref: np.ndarray, mu: float, s
         gc = g_by[lab]
         for k in ("n_pix", "y0", "x0", "y1", "x1"):
             assert gc[k] == rc[k], (where, k, gc, rc)
-        # cells of this component (other components may share its box)
+        # cells of this component (other components may share its box),
+        # looked at inside the box only
         if labels is None:
             from scipy import ndimage
 
             labels, _ = ndimage.label(z > tau, structure=np.ones((3, 3)))
-        own = labels == labels[rc["peak_y"], rc["peak_x"]]
-        top = values_ref[own].max()
-        near = (values_ref >= top * (1 - 1e-5)) if top > 0 else (values_ref >= top * (1 + 1e-5))
-        allowed = {(int(a), int(b)) for a, b in np.argwhere(own & near)}
+        y0, y1, x0, x1 = rc["y0"], rc["y1"] + 1, rc["x0"], rc["x1"] + 1
+        own = labels[y0:y1, x0:x1] == labels[rc["peak_y"], rc["peak_x"]]
+        vals = values_ref[y0:y1, x0:x1]
+        top = vals[own].max()
+        near = (vals >= top * (1 - 1e-5)) if top > 0 else (vals >= top * (1 + 1e-5))
+        allowed = {(int(a) + y0, int(b) + x0) for a, b in np.argwhere(own & near)}
         assert (gc["peak_y"], gc["peak_x"]) in allowed, (where, "peak", gc, rc)
         if len(allowed) == 1:
             assert (gc["peak_y"], gc["peak_x"]) == (rc["peak_y"], rc["peak_x"])

@@ -7,15 +7,19 @@ compute one by one:
   cell's clipped window;
 * per-triple mean and std of q against a two-pass FP64 evaluation of the
   library's own q map (the spread stage at full size);
-* a seeded sample of candidates: the oracle's component around the
-  candidate's peak, built from oracle q over the candidate's box grown by
-  two cells, with the library's mean and std."""
+* for three seeded triples, the oracle's whole q map (from the triple's three
+  frames): its mean and std against the library's, and every candidate of
+  the triple against the oracle's components built with the oracle's own
+  mean and std;
+* a seeded sample of candidates of other triples: the oracle's component
+  around the candidate's peak, built from oracle q over the candidate's box
+  grown by two cells, with the library's mean and std."""
 import numpy as np
 import pytest
 from scipy import ndimage
 
 from oracle import ref
-from parity import CENTROID_TOL, MAP_ATOL_REL_MEAN, MAP_RTOL, STAT_RTOL, Z_BAND
+from parity import CENTROID_TOL, MAP_ATOL_REL_MEAN, MAP_RTOL, STAT_RTOL, Z_BAND, check_components
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
@@ -46,6 +50,45 @@ def c2_run():
     yield stack, qmap, cands, stats, rc, cands2, stats2, rc2
     del stack, qmap
     torch.cuda.empty_cache()
+
+
+ORACLE_TRIPLES = (0, 13, 29)
+
+
+@pytest.fixture(scope="module")
+def c2_oracle(c2_run):
+    """Oracle q, mean and std of whole triples (from their three frames)."""
+    stack = c2_run[0]
+    res = {}
+    for s in ORACLE_TRIPLES:
+        print(f"[fullsize] oracle on triple {s}", flush=True)
+        X3 = stack[s:s + 3].cpu().numpy()
+        q = ref.index_maps(X3, window=WIN)[0]
+        del X3
+        mu, sig = ref.spread(q)
+        res[s] = (q, mu, sig)
+    yield res
+
+
+def test_fullsize_spread_against_oracle(c2_run, c2_oracle):
+    stats = c2_run[3]
+    for s, (_, mu, sig) in c2_oracle.items():
+        assert stats["mu"][s] == pytest.approx(mu, rel=STAT_RTOL), s
+        assert stats["sigma"][s] == pytest.approx(sig, rel=STAT_RTOL), s
+
+
+def test_fullsize_candidates_against_oracle(c2_run, c2_oracle):
+    from paper_2509_21754_amd.fitrig import _rec_dict
+
+    cands = c2_run[2]
+    total = 0
+    for s, (q, mu, sig) in c2_oracle.items():
+        g = [_rec_dict(c) for c in cands if c["branch"] == 1 and c["triple"] == s]
+        r = ref.components(q, mu, sig, TAU)
+        for c in r:
+            c.update(branch=1, triple=s)
+        total += check_components(g, r, q, mu, sig, TAU, where=f"triple {s}")
+    assert total > 0
 
 
 def _crop(stack, s, ya, yb, xa, xb):
