@@ -426,6 +426,50 @@ def host_stream(ctx, stack, tau: float, chunk: int, steps: int, ref_n_cand: int)
             "note": "stack in page-locked host memory; wall time of fitrig_detect_host (median)"}
 
 
+def prefix_report(ctx, stack, tau: float, window: int, n_cells: int = 2000) -> dict:
+    """The window sums of the headline stack read from full-image prefix sums
+    (FP64 and FP32 integral images, the comparison variant) against the
+    direct sums of the timed path, both against the FP64 oracle at seeded
+    sampled cells (each evaluated on a crop holding its clipped window)."""
+    import numpy as np
+    import torch
+
+    from oracle import ref
+    from paper_2509_21754_amd import index_prefix
+
+    n, H, W = stack.shape
+    h = window // 2
+    rng = np.random.default_rng(77)
+    cells = np.stack([rng.integers(0, n - 2, n_cells), rng.integers(0, H, n_cells), rng.integers(0, W, n_cells)], 1)
+    cells[:4] = [[0, 0, 0], [n - 3, H - 1, W - 1], [0, 0, W - 1], [n - 3, H - 1, 0]]
+    want = []
+    for s, y, x in cells:
+        ya, yb, xa, xb = max(0, y - h), min(H, y + h + 1), max(0, x - h), min(W, x + h + 1)
+        X = stack[s:s + 3, ya:yb, xa:xb].float().cpu().numpy()
+        want.append(ref.index_cells(X, [[0, y - ya, x - xa]], window=window)[0])
+    want = np.array(want)
+    q = torch.empty((n - 2, H, W), dtype=torch.float32, device=stack.device)
+    out = {"cells": f"{n_cells} seeded cells (corners and random), oracle on crops holding each window"}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name in ("direct_fp32", "prefix_fp64", "prefix_fp32"):
+        e0.record()
+        if name == "direct_fp32":
+            ctx.detect(stack, tau, index_map=q)
+        else:
+            index_prefix(stack, window, 64 if name == "prefix_fp64" else 32, out=q)
+        e1.record()
+        torch.cuda.synchronize()
+        g = q[torch.from_numpy(cells[:, 0]).to(q.device), torch.from_numpy(cells[:, 1]).to(q.device),
+              torch.from_numpy(cells[:, 2]).to(q.device)].double().cpu().numpy()
+        rel = np.abs(g - want) / np.maximum(np.abs(want), 1e-30)
+        out[name] = {"ms": round(e0.elapsed_time(e1), 2), "rel_err_median": float(np.median(rel)),
+                     "rel_err_p99": float(np.quantile(rel, 0.99)), "rel_err_max": float(rel.max()),
+                     "cells_over_1e-5": int((rel > 1e-5).sum())}
+    del q
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,6 +492,8 @@ def main() -> int:
     ap.add_argument("--serving-budget-gib", type=float, default=48.0)
     ap.add_argument("--serving-freq-window", type=int, default=30,
                     help="triples of a field's history the frequency branch covers (0 = the request's own)")
+    ap.add_argument("--prefix-report", action="store_true",
+                    help="also compare the window sums from FP64 / FP32 prefix sums with the direct ones")
     ap.add_argument("--no-host-stream", action="store_true",
                     help="skip the run of the same stack streamed from host memory")
     ap.add_argument("--host-chunk", type=int, default=4, help="frames per host-to-device chunk")
@@ -555,6 +601,9 @@ def main() -> int:
         del s16
     if args.mode == "sliding":
         out["localisation"] = localisation(ctx, stack, tau, spec, stream)
+    if args.prefix_report and args.mode == "sliding":
+        print("[bench] prefix-sum comparison", file=sys.stderr, flush=True)
+        out["prefix_report"] = prefix_report(ctx, stack, tau, spec.window)
     if not args.no_host_stream:
         print("[bench] streaming the stack from host memory", file=sys.stderr, flush=True)
         out["host_stream"] = host_stream(ctx, stack, tau, args.host_chunk, 3, stats["n_cand"])

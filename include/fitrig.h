@@ -303,6 +303,27 @@ int32_t fitrig_abi_version(void);
 fitrig_status fitrig_interp_peaks(const float* map, int32_t H, int32_t W, const int32_t* py, const int32_t* px,
                                   int32_t n, int32_t method, int32_t sub, double* out, void* hip_stream);
 
+/* ---- window sums from full-image prefix sums (comparison variant) ----------
+ * The index maps of fitrig_detect's sliding mode with the window sums of
+ * Delta and r (Sec. 2.3, Eq. (6)) read from integral images instead of
+ * summed directly: S = I(y2+1, x2+1) - I(y1, x2+1) - I(y2+1, x1) + I(y1, x1)
+ * over the clipped window, I(y, x) = sum over y' < y, x' < x. The integral
+ * image grows with the image (about H W mean), so its four-corner difference
+ * needs FP64 beyond a few thousand pixels on a side (prefix_bits = 64); FP32
+ * (prefix_bits = 32) shows the loss. fitrig_detect never uses this path: its
+ * direct sums of at most 17 terms have no such growth. The window maximum is
+ * exact (separable); q = (S_Delta / n) max (S_r / n) in the prefix precision.
+ *   index_map  device float [n_snap-2][H][W] (q, as fitrig_detect's)
+ *   window, r_signed, C: as fitrig_config
+ * Runs on hip_stream (NULL: the legacy default stream) and returns when the
+ * map is written; allocates 2 (H+1)(W+1) prefix values and 3 H W floats for
+ * the call. Errors: E_INVAL (null pointers, sizes as fitrig_detect, even or
+ * non-positive window, prefix_bits not 32 or 64, r_signed not 0 or 1,
+ * C <= 0), E_NOMEM, E_HIP. */
+fitrig_status fitrig_index_prefix(const void* stack, fitrig_dtype dtype, int32_t n_snap, int32_t H, int32_t W,
+                                  int32_t window, int32_t prefix_bits, int32_t r_signed, double C,
+                                  float* index_map, void* hip_stream);
+
 /* ---- snapshot accumulation -------------------------------------------------
  * For very short sampling periods adjacent snapshots are nearly the same and
  * their differences nearly blank; the paper then applies the method to sums

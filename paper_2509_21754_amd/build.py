@@ -32,6 +32,7 @@ UNITS = [
     ("fitrig_server.hip", [], "fitrig_server.o"),
     ("fitrig_interp.hip", [], "fitrig_interp.o"),
     ("fitrig_accum.hip", [], "fitrig_accum.o"),
+    ("fitrig_prefix.hip", [], "fitrig_prefix.o"),
     ("fitrig_launch.hip", ["-DFITRIG_STORAGE=0"], "fitrig_launch_f32.o"),
     ("fitrig_launch.hip", ["-DFITRIG_STORAGE=1"], "fitrig_launch_f16.o"),
     ("fitrig_launch.hip", ["-DFITRIG_STORAGE=2"], "fitrig_launch_bf16.o"),

@@ -138,6 +138,7 @@ EXPORTS = (
     "fitrig_interp_peaks",
     "fitrig_accumulate",
     "fitrig_accum_factor",
+    "fitrig_index_prefix",
 )
 N_PHASES = 5
 PHASES = ("index_pass", "spread", "image_select", "freq_branch", "host_copy")
@@ -195,6 +196,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.fitrig_accum_factor.argtypes = [vp, i32, i32, i32, i32, dbl, i32, ctypes.POINTER(i32),
                                       ctypes.POINTER(ctypes.c_double), vp]
     L.fitrig_accum_factor.restype = i32
+    L.fitrig_index_prefix.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, dbl, vp, vp]
+    L.fitrig_index_prefix.restype = i32
     _lib = L
     return L
 
@@ -613,3 +616,28 @@ def accum_factor(stack, gamma: float, k_max: int):
     if rc != OK:
         raise FitrigError(rc, "fitrig_accum_factor")
     return K.value, list(C)[:k_max]
+
+
+# ---- window sums from prefix sums (comparison variant) -----------------------
+
+def fitrig_index_prefix(stack_ptr, dtype, n_snap, H, W, window, prefix_bits, r_signed, C, map_ptr, hip_stream) -> int:
+    return load().fitrig_index_prefix(stack_ptr, dtype, n_snap, H, W, window, prefix_bits, r_signed, C, map_ptr,
+                                      hip_stream)
+
+
+def index_prefix(stack, window: int, prefix_bits: int = 64, r_signed: int = 0, C: float = 1e-6, out=None):
+    """q maps of every triple ([n-2][H][W] float32 device tensor) with the window
+    sums read from integral images in FP64 (or FP32), on torch's current stream."""
+    import torch
+
+    if not stack.is_cuda or not stack.is_contiguous() or stack.dim() != 3:
+        raise ValueError("stack must be a contiguous 3-D device tensor")
+    n, H, W = stack.shape
+    if out is None:
+        out = torch.empty((max(n - 2, 0), H, W), dtype=torch.float32, device=stack.device)
+    rc = fitrig_index_prefix(ctypes.c_void_p(stack.data_ptr()), _dtype_code(stack), n, H, W, int(window),
+                             int(prefix_bits), int(r_signed), float(C), ctypes.c_void_p(out.data_ptr()),
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != OK:
+        raise FitrigError(rc, "fitrig_index_prefix")
+    return out
