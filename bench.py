@@ -38,7 +38,7 @@ WORKLOAD_TEXT = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fitrig_kernels.hip", "fitrig_api.hip", "fitrig_internal.h"):
+    for f in ("fitrig_device.h", "fitrig_launch.hip", "fitrig_kernels.hip", "fitrig_api.hip", "fitrig_internal.h"):
         with open(os.path.join(ROOT, "paper_2509_21754_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -452,17 +452,19 @@ def prefix_report(ctx, stack, tau: float, window: int, n_cells: int = 2000) -> d
     out = {"cells": f"{n_cells} seeded cells (corners and random), oracle on crops holding each window"}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for name in ("direct_fp32", "prefix_fp64", "prefix_fp32"):
-        e0.record()
-        if name == "direct_fp32":
-            ctx.detect(stack, tau, index_map=q)
-        else:
-            index_prefix(stack, window, 64 if name == "prefix_fp64" else 32, out=q)
-        e1.record()
+        for rep in range(2):  # the second run is timed (the first sizes scratch)
+            e0.record()
+            if name == "direct_fp32":
+                ctx.detect(stack, tau, index_map=q)
+            else:
+                index_prefix(stack, window, 64 if name == "prefix_fp64" else 32, out=q)
+            e1.record()
+            torch.cuda.synchronize()
         torch.cuda.synchronize()
         g = q[torch.from_numpy(cells[:, 0]).to(q.device), torch.from_numpy(cells[:, 1]).to(q.device),
               torch.from_numpy(cells[:, 2]).to(q.device)].double().cpu().numpy()
         rel = np.abs(g - want) / np.maximum(np.abs(want), 1e-30)
-        out[name] = {"ms": round(e0.elapsed_time(e1), 2), "rel_err_median": float(np.median(rel)),
+        out[name] = {"ms_whole_call": round(e0.elapsed_time(e1), 2), "rel_err_median": float(np.median(rel)),
                      "rel_err_p99": float(np.quantile(rel, 0.99)), "rel_err_max": float(rel.max()),
                      "cells_over_1e-5": int((rel > 1e-5).sum())}
     del q
