@@ -31,7 +31,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fitrig_ref.c")
-_LIB = os.path.join(_HERE, "libfitrig_ref.so")
+# FITRIG_REF_LIB: another build of the same C source (the sanitizer test)
+_LIB = os.environ.get("FITRIG_REF_LIB") or os.path.join(_HERE, "libfitrig_ref.so")
 
 SLIDING, TILES = 0, 1
 FREQ_PIXEL = 4

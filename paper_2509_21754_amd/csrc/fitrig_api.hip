@@ -1224,8 +1224,19 @@ fitrig_status check_shape(const fitrig_config& cfg, const Call& c) {
 fitrig_status sizing_pass(fitrig_ctx* ctx, const Call& c, size_t result_bytes) {
   const int64_t seg_cap = ctx->seg_cap, comp_cap = ctx->comp_cap;
   clear_wants(ctx);
+  // buffers not allocated yet get a stand-in address for the pass, so the
+  // pointer arithmetic of the sequence stays defined (nothing is
+  // dereferenced or launched while sizing)
+  bool stand_in[kNBufs];
+  for (size_t i = 0; i < kNBufs; ++i) {
+    DevBuf& b = ctx->*kBufs[i];
+    stand_in[i] = b.p == nullptr;
+    if (stand_in[i]) b.p = (void*)(uintptr_t)(1u << 20);
+  }
   ctx->sizing = true;
   fitrig_status rc = enqueue(ctx, c, true);
+  for (size_t i = 0; i < kNBufs; ++i)
+    if (stand_in[i]) (ctx->*kBufs[i]).p = nullptr;
   // results: host-visible memory, or (allocation-free entry) device scratch
   if (rc == FITRIG_OK) rc = ctx->in_arena ? ensure(ctx, ctx->res_dev, result_bytes) : ensure_host(ctx, result_bytes);
   ctx->sizing = false;
