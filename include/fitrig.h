@@ -402,8 +402,11 @@ typedef struct {
                            freq_window * ceil(H/tile) * ceil(W/tile) * 8 bytes,
                            counted in mem_budget). The branch runs once the
                            covered series has at least 4 triples. The
-                           per-pixel branch (FITRIG_FREQ_PIXEL) always covers
-                           the request's own triples. */
+                           per-pixel branch (FITRIG_FREQ_PIXEL, sliding mode)
+                           likewise covers the field's last freq_window
+                           triples, from a ring of the field's FP32 index maps
+                           (freq_window * H * W * 4 bytes, counted in
+                           mem_budget). */
   int32_t graphs;       /* 1 (default): each slot captures its launch sequence
                            into a HIP graph per request shape (frames, size,
                            dtype, carried frames, history length) and replays

@@ -94,11 +94,12 @@ struct AsyncOut {
 
 // A launch sequence captured for one call shape (serving slots).
 struct GraphKey {
-  int n, H, W, ncarry, dtype, hist_cap, hist_n_in, hist_out;
+  int n, H, W, ncarry, dtype, hist_cap, hist_n_in, hist_out, px_cap, px_n;
   int64_t cand_cap;
   bool operator==(const GraphKey& o) const {
     return n == o.n && H == o.H && W == o.W && ncarry == o.ncarry && dtype == o.dtype && hist_cap == o.hist_cap &&
-           hist_n_in == o.hist_n_in && hist_out == o.hist_out && cand_cap == o.cand_cap;
+           hist_n_in == o.hist_n_in && hist_out == o.hist_out && px_cap == o.px_cap && px_n == o.px_n &&
+           cand_cap == o.cand_cap;
   }
 };
 struct GraphEntry {
@@ -386,8 +387,9 @@ struct Call {
 // What runs for a call, from the config and the shape.
 struct Plan {
   int np;
-  bool sliding, img, robust, freq, ring, fpx, cube_needed, qpass;
+  bool sliding, img, robust, freq, ring, fpx, pring, cube_needed, qpass;
   int nfreq;
+  int npx;  // series length of the per-pixel branch
 };
 
 Plan make_plan(const fitrig_config& cfg, const Call& c) {
@@ -402,11 +404,17 @@ Plan make_plan(const fitrig_config& cfg, const Call& c) {
   p.ring = want_freq && c.hist && c.hist->cap > 0;
   p.nfreq = p.ring ? (int)std::min<int64_t>(c.hist->cap, (int64_t)c.hist->n_in + p.np) : p.np;
   p.freq = want_freq && p.nfreq >= 4 && !(c.hist && c.hist->defer);
-  p.fpx = (cfg.branches & FITRIG_FREQ_PIXEL) != 0 && p.sliding && p.np >= 4;
+  // per-pixel branch: over this call's maps, or (serving) over the last
+  // px_cap of [the field's kept maps | this call's]
+  const bool want_px = (cfg.branches & FITRIG_FREQ_PIXEL) != 0 && p.sliding;
+  p.pring = want_px && c.hist && c.hist->px_cap > 0;
+  p.npx = p.pring ? (int)std::min<int64_t>(c.hist->px_cap, (int64_t)c.hist->px_n + p.np) : p.np;
+  p.fpx = want_px && p.npx >= 4 && !(c.hist && c.hist->defer);
   // the tile cube: frequency branch, history, tile-mode image branch or map
   p.cube_needed = p.freq || p.ring || (!p.sliding && (p.img || c.index_map));
-  // the streaming sliding pass: image branch, per-pixel spectra or the map
-  p.qpass = p.sliding && (p.img || p.fpx || c.index_map);
+  // the streaming sliding pass: image branch, per-pixel spectra (or their
+  // kept maps) or the map
+  p.qpass = p.sliding && (p.img || p.fpx || p.pring || c.index_map);
   return p;
 }
 
@@ -800,6 +808,9 @@ void write_call(fitrig_ctx* ctx, const Call& c) {
   v.hist_in = c.hist ? c.hist->in : nullptr;
   v.hist_out = c.hist ? c.hist->out : nullptr;
   v.tau = c.tau;
+  v.px_ring = c.hist ? c.hist->px_ring : nullptr;
+  v.px_start = c.hist ? c.hist->px_start : 0;
+  v.px_pad = 0;
   KL(k_set_call, dim3(1), dim3(64), 0, c.st, (CallDev*)ctx->call.p, v);
 }
 
@@ -867,7 +878,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     if (byprod && (rc = ensure(ctx, ctx->tile_part, (size_t)np * nbands * ncol * kPieces * 3 * 8)) != FITRIG_OK)
       return rc;
     qmap = c.index_map;
-    if (((P.img && P.robust) || P.fpx) && !qmap) {
+    if (((P.img && P.robust) || P.fpx || P.pring) && !qmap) {
       if ((rc = ensure(ctx, ctx->qscratch, (size_t)np * plane * 4)) != FITRIG_OK) return rc;
       qmap = (float*)ctx->qscratch.p;
     }
@@ -1075,13 +1086,19 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
   }
 
   // ---- per-pixel frequency branch -------------------------------------------
+  // the series: the field's kept maps (serving), then the call's last ones
+  const int px_from_call = P.pring ? std::min(np, P.npx) : np;
+  const int px_from_ring = P.pring ? P.npx - px_from_call : 0;
+  const int px_cap = P.pring ? c.hist->px_cap : 1;
+  const int px_first = P.pring ? c.hist->px_n - px_from_ring : 0;  // held maps skipped (oldest)
   if (P.fpx) {
-    const int K = np / 2;
+    const int nps = P.npx;
+    const int K = nps / 2;
     const int nmb = (2 * K + 15) / 16;
     const int mbg = nmb <= 1 ? 1 : nmb == 2 ? 2 : nmb == 3 ? 3 : 4;
     const int64_t ntile = (plane + 63) / 64;
     const int G = (int)std::min<int64_t>(ntile, 8192);
-    const size_t lds = (size_t)np * 16 + (cfg.harm ? (size_t)K * 64 * 4 : 0);
+    const size_t lds = (size_t)nps * 16 + (cfg.harm ? (size_t)K * 64 * 4 : 0);
     if (lds > 65536) return FITRIG_E_INVAL;
     float* ef = c.eta_px_map;
     if (!ef) {
@@ -1089,13 +1106,14 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
       ef = (float*)ctx->etapx_f.p;
     }
     if ((rc = ensure(ctx, ctx->pxpart, (size_t)G * 16)) != FITRIG_OK) return rc;
-    if ((rc = ensure(ctx, ctx->tw_px, (size_t)np * 16)) != FITRIG_OK) return rc;
-    KL(k_twiddle, dim3(grid_for(np)), dim3(256), 0, st, np, (double2*)ctx->tw_px.p);
-    // 16-byte loads of four pixels: rows of the map start 16-byte aligned
-    const bool vec = plane % 4 == 0 && ((uintptr_t)qmap & 15) == 0;
+    if ((rc = ensure(ctx, ctx->tw_px, (size_t)nps * 16)) != FITRIG_OK) return rc;
+    KL(k_twiddle, dim3(grid_for(nps)), dim3(256), 0, st, nps, (double2*)ctx->tw_px.p);
+    const float* qcall = qmap + (int64_t)(np - px_from_call) * plane;
+    // 16-byte loads of four pixels: rows of the maps start 16-byte aligned
+    const bool vec = plane % 4 == 0 && ((uintptr_t)qcall & 15) == 0;
 #define EPX(MB, V)                                                                                                  \
-  KL((k_eta_px<MB, V>), dim3(G), dim3(64), lds, st, (const float*)qmap, np, plane, cfg.harm, (const double2*)ctx->tw_px.p, \
-     ef, (double*)ctx->pxpart.p)
+  KL((k_eta_px<MB, V>), dim3(G), dim3(64), lds, st, qcall, nps, plane, cfg.harm, (const double2*)ctx->tw_px.p, \
+     ef, (double*)ctx->pxpart.p, (const CallDev*)cd, px_from_ring, px_first, px_cap)
     if (vec) {
       if (mbg == 1) EPX(1, true); else if (mbg == 2) EPX(2, true); else if (mbg == 3) EPX(3, true); else EPX(4, true);
     } else {
@@ -1122,6 +1140,14 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     if ((rc = select_run(ctx, c, L, smax, px_mu, px_sig, px_flag, FITRIG_FREQ_PIXEL, (const float*)ef, halo)) !=
         FITRIG_OK)
       return rc;
+  }
+
+  if (P.pring) {
+    // the call's last maps join the field's ring (after the branch read it)
+    const int nap = std::min(np, px_cap);
+    KL(k_px_ring_append, dim3(grid_for((int64_t)nap * plane, 256, 8192)), dim3(256), 0, st, (const CallDev*)cd,
+       (const float*)(qmap + (int64_t)(np - nap) * plane), plane, nap, c.hist->px_n, px_cap);
+    LAUNCH_CHECK(ctx);
   }
 
   if (c.index_map && P.sliding && cfg.map_kind == FITRIG_MAP_TLISI) {
@@ -1214,7 +1240,7 @@ fitrig_status check_shape(const fitrig_config& cfg, const Call& c) {
   const Plan P = make_plan(cfg, c);
   // per-pixel spectra: the twiddle table (and, for harmonic sums, the
   // magnitudes of 64 pixels) in the 64 KB of LDS of one workgroup
-  if (P.fpx && P.np > (cfg.harm ? 448 : 4096)) return FITRIG_E_INVAL;
+  if (P.fpx && P.npx > (cfg.harm ? 448 : 4096)) return FITRIG_E_INVAL;
   return FITRIG_OK;
 }
 
@@ -1321,7 +1347,8 @@ fitrig_status detect_graph(fitrig_ctx* ctx, const Call& c, fitrig_candidate* can
     }
   }
   const GraphKey key{c.n, c.H, c.W, c.ncarry, (int)c.dtype, c.hist ? c.hist->cap : 0, c.hist ? c.hist->n_in : 0,
-                     (c.hist && c.hist->out) ? 1 + (c.hist->defer ? 1 : 0) : 0, cap};
+                     (c.hist && c.hist->out) ? 1 + (c.hist->defer ? 1 : 0) : 0, c.hist ? c.hist->px_cap : 0,
+                     c.hist ? c.hist->px_n : 0, cap};
   GraphEntry* e = nullptr;
   for (GraphEntry& g : ctx->graphs)
     if (g.key == key) e = &g;
@@ -1842,7 +1869,9 @@ fitrig_status detect_frames(fitrig_ctx* ctx, const void* carry0, const void* car
   fitrig_status rc = check_args(stack, dtype, H, W, sigma, cand, cand_cap, n_cand);
   if (rc != FITRIG_OK) return rc;
   if (hist && (hist->n_in < 0 || hist->cap < 0 || hist->cap > 2048 || hist->n_in > hist->cap ||
-               (hist->n_in > 0 && !hist->in)))
+               (hist->n_in > 0 && !hist->in) || hist->px_cap < 0 || hist->px_cap > 2048 || hist->px_n < 0 ||
+               hist->px_n > hist->px_cap || (hist->px_cap > 0 && (!hist->px_ring || hist->px_start < 0 ||
+                                                                  hist->px_start >= hist->px_cap))))
     return FITRIG_E_INVAL;
   if ((ncarry >= 1 && !carry0) || (ncarry == 2 && !carry1)) return FITRIG_E_INVAL;
   if (n_new < 1 || ncarry + n_new < 3) return FITRIG_E_INVAL;

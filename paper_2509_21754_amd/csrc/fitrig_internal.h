@@ -30,6 +30,9 @@ struct CallDev {
   const double* hist_in; // serving: frequency history [n_in][Ty][Tx] (nullable)
   double* hist_out;      // serving: receives the covered slices (nullable)
   double tau;            // threshold of Eqs. (9), (12)
+  float* px_ring;        // serving: ring of per-pixel q maps [cap][H][W] (nullable)
+  int32_t px_start;      // ring slot of the oldest map held
+  int32_t px_pad;
 };
 
 // Streaming index kernel arguments (one launch covers every triple).
@@ -189,6 +192,13 @@ struct FreqHist {
   int cap;
   double* out;
   int defer;  // 1: only extend the history; the branch runs on a later call
+  // per-pixel branch: ring of the sliding q maps of the field's last px_cap
+  // triples (device, [px_cap][H][W] FP32); px_n maps held, the oldest at
+  // slot px_start; the call appends its own maps (0 = not kept)
+  float* px_ring;
+  int px_cap;
+  int px_start;
+  int px_n;
 };
 
 // Host-side entry points shared between translation units of the library.

@@ -1273,7 +1273,8 @@ typedef double fitrig_v4d __attribute__((ext_vector_type(4)));
 // pixels' eta go to part[2 b], part[2 b + 1].
 template <int MBG, bool VEC>
 __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t plane, int harm, const double2* twg,
-                                               float* eta_f, double* part) {
+                                               float* eta_f, double* part, const CallDev* cd, int n_ring,
+                                               int ring_first, int ring_cap) {
   extern __shared__ double2 lds_tw[];         // [np] twiddles, then [K][64] float magnitudes (harmonic sums)
   float* ak = (float*)(lds_tw + np);
   const int lane = threadIdx.x;
@@ -1306,7 +1307,11 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
         const int s = 4 * t + kk;
         double b[4] = {0.0, 0.0, 0.0, 0.0};
         if (s < np) {
-          const float* row = q + (int64_t)s * plane + p0 + 4 * n;
+          // series step s: the newest n_ring of the field's kept maps (held
+          // from slot px_start, oldest first; serving), then the call's
+          const float* row = (s < n_ring ? cd->px_ring + (int64_t)((cd->px_start + ring_first + s) % ring_cap) * plane
+                                         : q + (int64_t)(s - n_ring) * plane) +
+                             p0 + 4 * n;
           if (VEC && full) {
             const float4 v = *reinterpret_cast<const float4*>(row);
             b[0] = v.x;
@@ -1433,6 +1438,18 @@ __global__ void k_hist_in(const CallDev* cd, int64_t hist_off, int64_t n_hist, c
        i += (int64_t)gridDim.x * blockDim.x)
     fs[i] = i < n_hist ? h[hist_off + i] : cube[cube_off + (i - n_hist)];
 }
+// The call's last n maps appended to the field's ring of per-pixel q maps
+// (slots after the n_held maps kept from slot px_start).
+__global__ void k_px_ring_append(const CallDev* cd, const float* q, int64_t plane, int n, int n_held, int cap) {
+  const int64_t tot = (int64_t)n * plane;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(i / plane);
+    const int64_t p = i - (int64_t)j * plane;
+    const int slot = (cd->px_start + n_held + j) % cap;
+    cd->px_ring[(int64_t)slot * plane + p] = q[i];
+  }
+}
+
 __global__ void k_hist_out(const CallDev* cd, const double* fs, int64_t n) {
   double* h = cd->hist_out;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

@@ -70,6 +70,9 @@ struct Field {
   double* ring = nullptr;    // tile-cube slices of the latest triples, oldest first
   size_t ring_bytes = 0;     // capacity: freq_window slices
   int nring = 0;             // slices held
+  float* pxring = nullptr;   // per-pixel branch: q maps of the latest triples (a ring)
+  size_t pxring_bytes = 0;   // capacity: freq_window maps
+  int px_start = 0, px_n = 0;  // slot of the oldest map held, maps held
   int ncarry = 0;            // frames held (0..2) once every submitted request has run
   int64_t frames_seen = 0;   // frames of finished requests
   int64_t frames_submitted = 0;
@@ -111,11 +114,13 @@ int64_t device_bound(const fitrig_server* S, int64_t need) {
 }
 
 // Device bytes of a field's resident state.
-size_t field_bytes(const Field& f) { return 2 * f.frame_bytes + f.ring_bytes; }
+size_t field_bytes(const Field& f) { return 2 * f.frame_bytes + f.ring_bytes + f.pxring_bytes; }
 
 void free_field(Field& f) {
   if (f.carry) (void)hipFree(f.carry);
   if (f.ring) (void)hipFree(f.ring);
+  if (f.pxring) (void)hipFree(f.pxring);
+  f.pxring = nullptr;
   f.carry = nullptr;
   f.ring = nullptr;
 }
@@ -143,6 +148,12 @@ void worker_main(fitrig_server* S, int slot) {
       if (nc == 2) c1 = f.carry + f.frame_bytes;
       first = f.frames_seen - nc;
       if (f.ring) fh = fitrig::FreqHist{f.ring, f.nring, S->cfg.freq_window, f.ring, 0};
+      if (f.pxring) {
+        fh.px_ring = f.pxring;
+        fh.px_cap = S->cfg.freq_window;
+        fh.px_start = f.px_start;
+        fh.px_n = f.px_n;
+      }
     }
     r->t_start = now_ns();
     fitrig_stats st;
@@ -152,7 +163,8 @@ void worker_main(fitrig_server* S, int slot) {
     // the slot's stream does not wait on the legacy default stream by itself
     hipError_t we = hipStreamWaitEvent(fitrig::ctx_stream(ctx), r->ready, 0);
     fitrig_status rc = we != hipSuccess ? FITRIG_E_HIP : fitrig::detect_frames(ctx, c0, c1, nc, r->stack, r->dtype, r->n, r->H, r->W, r->tau,
-                                             buf.data(), S->cfg.cand_cap, &ncand, &st, nullptr, fh.cap ? &fh : nullptr);
+                                             buf.data(), S->cfg.cand_cap, &ncand, &st, nullptr,
+                                             (fh.cap || fh.px_cap) ? &fh : nullptr);
     r->replayed = fitrig::ctx_graph_replays(ctx) > replays0 ? 1 : 0;
     // the field keeps the last two frames of [carried | new]
     Field* fp;
@@ -191,6 +203,15 @@ void worker_main(fitrig_server* S, int slot) {
       r->n_cand = ncand;
       r->n_triples = nc + r->n - 2 > 0 ? nc + r->n - 2 : 0;
       r->first_triple = first;
+      if (f.pxring) {
+        // the ring gained the run's last min(n_triples, window) maps
+        const bool ok = rc == FITRIG_OK || rc == FITRIG_E_TRUNC;
+        const int cap = S->cfg.freq_window;
+        const int nap = std::min(r->n_triples, cap);
+        const int n_new = (int)std::min<int64_t>(cap, (int64_t)f.px_n + r->n_triples);
+        f.px_start = ok ? (f.px_start + f.px_n + nap - n_new) % cap : 0;
+        f.px_n = ok ? n_new : 0;
+      }
       if (f.ring) {
         // the history holds what the run wrote; after a failed run it is dropped
         const bool ok = rc == FITRIG_OK || rc == FITRIG_E_TRUNC;
@@ -269,11 +290,14 @@ fitrig_status fitrig_server_create(const fitrig_server_config* cfg, fitrig_serve
   if (b.max_pixels > 0 && b.max_snap >= 3) {
     const int side = (int)ceil(sqrt((double)b.max_pixels));
     const bool ring = S->cfg.freq_window > 0 && (b.branches & FITRIG_FREQ) != 0;
+    const bool pxr = S->cfg.freq_window > 0 && (b.branches & FITRIG_FREQ_PIXEL) != 0 && b.mode == FITRIG_SLIDING;
     const fitrig::FreqHist hs{(const double*)(uintptr_t)256, ring ? S->cfg.freq_window : 0,
-                              ring ? S->cfg.freq_window : 0, (double*)(uintptr_t)256, 0};
+                              ring ? S->cfg.freq_window : 0, (double*)(uintptr_t)256, 0,
+                              pxr ? (float*)(uintptr_t)256 : nullptr, pxr ? S->cfg.freq_window : 0, 0,
+                              pxr ? S->cfg.freq_window : 0};
     for (fitrig_ctx* c : S->ctxs) {
-      const fitrig_status rc =
-          fitrig::ctx_presize_for(c, 2, b.max_snap, side, side, FITRIG_F32, ring ? &hs : nullptr, S->cfg.cand_cap);
+      const fitrig_status rc = fitrig::ctx_presize_for(c, 2, b.max_snap, side, side, FITRIG_F32,
+                                                       (ring || pxr) ? &hs : nullptr, S->cfg.cand_cap);
       if (rc != FITRIG_OK) {
         for (fitrig_ctx* x : S->ctxs) fitrig_destroy(x);
         delete S;
@@ -303,6 +327,9 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
   const int tile = S->cfg.base.tile;
   const bool keep_ring = S->cfg.freq_window > 0 && (S->cfg.base.branches & FITRIG_FREQ) != 0;
   const size_t rb = keep_ring ? (size_t)S->cfg.freq_window * ((H + tile - 1) / tile) * ((W + tile - 1) / tile) * 8 : 0;
+  const bool keep_px = S->cfg.freq_window > 0 && (S->cfg.base.branches & FITRIG_FREQ_PIXEL) != 0 &&
+                       S->cfg.base.mode == FITRIG_SLIDING;
+  const size_t pb = keep_px ? (size_t)S->cfg.freq_window * (size_t)H * W * 4 : 0;
   const int64_t budget = S->cfg.mem_budget;
   std::unique_lock<std::mutex> lk(S->mu);
   // the field's state and the charge are re-read after every wait, so
@@ -317,12 +344,14 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
     if (resize && (f0->busy || !f0->pending.empty())) return FITRIG_E_INVAL;
     const int64_t carried = (f0 && !resize) ? std::min<int64_t>(2, f0->frames_submitted) : 0;
     if (carried + n_snap < 3) return FITRIG_E_INVAL;
-    field_mem = (fresh || resize) ? (int64_t)(2 * fb + rb) : 0;
-    // exact scratch of the request (the history at its longest)
+    field_mem = (fresh || resize) ? (int64_t)(2 * fb + rb + pb) : 0;
+    // exact scratch of the request (the histories at their longest)
     const fitrig::FreqHist hs{(const double*)(uintptr_t)256, keep_ring ? S->cfg.freq_window : 0,
-                              keep_ring ? S->cfg.freq_window : 0, (double*)(uintptr_t)256, 0};
-    mem = fitrig::call_scratch_bytes(S->cfg.base, (int)carried, n_snap, H, W, dtype, keep_ring ? &hs : nullptr,
-                                     S->cfg.cand_cap);
+                              keep_ring ? S->cfg.freq_window : 0, (double*)(uintptr_t)256, 0,
+                              keep_px ? (float*)(uintptr_t)256 : nullptr, keep_px ? S->cfg.freq_window : 0, 0,
+                              keep_px ? S->cfg.freq_window : 0};
+    mem = fitrig::call_scratch_bytes(S->cfg.base, (int)carried, n_snap, H, W, dtype,
+                                     (keep_ring || keep_px) ? &hs : nullptr, S->cfg.cand_cap);
     if (mem <= 0) return FITRIG_E_INVAL;
     if (budget > 0 && field_mem + device_bound(S, mem) > budget) return FITRIG_E_BUSY;
     const int64_t top = S->inflight.empty() ? mem : std::max(mem, *S->inflight.rbegin());
@@ -346,7 +375,7 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
   // (re)create the field state
   if (fresh || resize) {
     Field& nf = S->fields[field_id];
-    if (nf.carry || nf.ring) {
+    if (nf.carry || nf.ring || nf.pxring) {
       free_field(nf);
       S->mem_fields -= (int64_t)field_bytes(nf);
     }
@@ -356,8 +385,10 @@ fitrig_status fitrig_submit(fitrig_server* S, int64_t field_id, const void* stac
     nf.dtype = dtype;
     nf.frame_bytes = fb;
     nf.ring_bytes = rb;
+    nf.pxring_bytes = pb;
     if (hipSetDevice(S->cfg.base.device) != hipSuccess || hipMalloc((void**)&nf.carry, 2 * fb) != hipSuccess ||
-        (rb && hipMalloc((void**)&nf.ring, rb) != hipSuccess)) {
+        (rb && hipMalloc((void**)&nf.ring, rb) != hipSuccess) ||
+        (pb && hipMalloc((void**)&nf.pxring, pb) != hipSuccess)) {
       free_field(nf);
       S->fields.erase(field_id);
       return FITRIG_E_NOMEM;

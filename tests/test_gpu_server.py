@@ -230,3 +230,55 @@ def test_server_freq_window_covers_field_history(branches, tile):
                 check_candidates([_rec_dict(x) for x in alone], out, tau)
             srv.release(tk)
     assert n_freq > 0
+
+
+@pytest.mark.parametrize("branches,extra,graphs", [(5, {}, 1), (7, {}, 0), (5, dict(sigma_est=1), 1)])
+def test_server_freq_window_pixel_history(branches, extra, graphs):
+    """With freq_window > 0 the per-pixel frequency branch of a request runs
+    over the field's last freq_window index maps (kept per field in a ring,
+    across requests of any size): its candidates equal those of the frames
+    covering that window run alone, and match the oracle. Two fields, one of
+    them with a ragged plane, are interleaved so that each keeps its own ring."""
+    from paper_2509_21754_amd import Server
+    from paper_2509_21754_amd.fitrig import _rec_dict
+
+    tau, win = 2.5, 6
+    cfg = dict(window=5, branches=branches, tile=16)
+    cfg.update(extra)
+    shapes = {0: (96, 200), 1: (37, 203)}
+    sizes = {0: [3, 2, 1, 4, 3, 1, 5], 1: [4, 1, 1, 7, 2]}
+    order = [0, 1, 0, 0, 1, 0, 1, 0, 1, 0, 1, 0]
+    frames = {0: [], 1: []}
+    nxt = {0: 0, 1: 0}
+    n_px = 0
+    with Server(n_slots=2, freq_window=win, graphs=graphs, **cfg) as srv:
+        for i, f in enumerate(order):
+            n = sizes[f][nxt[f]]
+            nxt[f] += 1
+            H, W = shapes[f]
+            X = structured_stack(500 + 17 * f + i, n, H, W)
+            t = torch.from_numpy(X).cuda()
+            torch.cuda.synchronize()
+            frames[f].extend(list(X))
+            tk = srv.submit(f, t, tau)
+            r = srv.poll(tk, as_dicts=False)
+            assert r["status"] == 0, (i, f)
+            T = len(frames[f]) - 2
+            nf = min(T, win)
+            got = r["cands"]
+            gp = got[got["branch"] == ref.FREQ_PIXEL]
+            if nf < 4:
+                assert len(gp) == 0
+            else:
+                used = np.stack(frames[f][T - nf:T + 2])
+                alone, _, rc = _alone(torch.from_numpy(used).cuda(), tau, **cfg)
+                assert rc == 0
+                ap = alone[alone["branch"] == ref.FREQ_PIXEL]
+                assert gp.tobytes() == ap.tobytes(), (i, f, T)
+                n_px += len(ap)
+                out = ref.detect(used.astype(np.float64), tau=tau, window=5, branches=ref.FREQ_PIXEL, tile=16,
+                                 sigma_est=cfg.get("sigma_est", 0))
+                check_candidates([_rec_dict(x) for x in ap], out, tau)
+            srv.release(tk)
+    assert nxt == {0: len(sizes[0]), 1: len(sizes[1])}
+    assert n_px > 0
