@@ -26,9 +26,12 @@ HIPCC_FLAGS = [
     "-ffp-contract=off", "-Wno-unused-result",
 ]
 
-# (source, extra defines, object name)
+# (source, extra flags and defines, object name)
 UNITS = [
-    ("fitrig_api.hip", [], "fitrig_api.o"),
+    # the per-pixel transform's matrix products keep their loop-carried
+    # accumulators in VGPRs (the default AGPR form copied all of them out and
+    # back on every step of the series)
+    ("fitrig_api.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form"], "fitrig_api.o"),
     ("fitrig_server.hip", [], "fitrig_server.o"),
     ("fitrig_interp.hip", [], "fitrig_interp.o"),
     ("fitrig_accum.hip", [], "fitrig_accum.o"),

@@ -1094,8 +1094,8 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
   if (P.fpx) {
     const int nps = P.npx;
     const int K = nps / 2;
-    const int nmb = (2 * K + 15) / 16;
-    const int mbg = nmb <= 1 ? 1 : nmb == 2 ? 2 : nmb == 3 ? 3 : 4;
+    const int nmb = (K + 15) / 16;  // blocks of 16 frequencies (cosine and sine accumulators each)
+    const int mbg = nmb <= 1 ? 1 : 2;
     const int64_t ntile = (plane + 63) / 64;
     const int G = (int)std::min<int64_t>(ntile, 8192);
     const size_t lds = (size_t)nps * 16 + (cfg.harm ? (size_t)K * 64 * 4 : 0);
@@ -1111,13 +1111,23 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     const float* qcall = qmap + (int64_t)(np - px_from_call) * plane;
     // 16-byte loads of four pixels: rows of the maps start 16-byte aligned
     const bool vec = plane % 4 == 0 && ((uintptr_t)qcall & 15) == 0;
-#define EPX(MB, V)                                                                                                  \
-  KL((k_eta_px<MB, V>), dim3(G), dim3(64), lds, st, qcall, nps, plane, cfg.harm, (const double2*)ctx->tw_px.p, \
+    // loads run 4 step groups (16 series steps) ahead, 2 for short series
+    const bool deep = (nps / 2 + 4) / 4 >= 4;
+#define EPX(MB, V, DD)                                                                                            \
+  KL((k_eta_px<MB, V, DD>), dim3(G), dim3(64), lds, st, qcall, nps, plane, cfg.harm, (const double2*)ctx->tw_px.p, \
      ef, (double*)ctx->pxpart.p, (const CallDev*)cd, px_from_ring, px_first, px_cap)
-    if (vec) {
-      if (mbg == 1) EPX(1, true); else if (mbg == 2) EPX(2, true); else if (mbg == 3) EPX(3, true); else EPX(4, true);
+    if (deep) {
+      if (vec) {
+        if (mbg == 1) EPX(1, true, 4); else EPX(2, true, 4);
+      } else {
+        if (mbg == 1) EPX(1, false, 4); else EPX(2, false, 4);
+      }
     } else {
-      if (mbg == 1) EPX(1, false); else if (mbg == 2) EPX(2, false); else if (mbg == 3) EPX(3, false); else EPX(4, false);
+      if (vec) {
+        if (mbg == 1) EPX(1, true, 2); else EPX(2, true, 2);
+      } else {
+        if (mbg == 1) EPX(1, false, 2); else EPX(2, false, 2);
+      }
     }
 #undef EPX
     LAUNCH_CHECK(ctx);

@@ -1254,24 +1254,33 @@ __global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t
 
 typedef double fitrig_v4d __attribute__((ext_vector_type(4)));
 
-// Per-pixel form of Eq. (10) on the matrix cores. For a tile of 64 pixels the
-// spectra are FP64 matrix products D = T Q: T[row][s] holds cos or sin of
-// 2 pi k s / n' for k = 1..K, Q[s][pixel] the pixel's q series. Each
-// v_mfma_f64_16x16x4 takes 16 rows x 4 series values (A: lane i + 16 kk
-// holds T[i][kk]) and 4 values x 16 pixels (B: lane n + 16 kk holds
-// Q[kk][n]) and accumulates D, whose register r of lane n + 16 c holds row
-// 4 r + c of pixel column n. Row i of a block of 16 therefore carries
-// frequency 2 (i mod 4) + floor(i / 8) + 1 (within the block's 8) and the
-// cosine for even floor(i / 4), the sine for odd: registers 0..3 of lane
-// n + 16 c then hold (re, im) of frequency 2 c + 1 and of 2 c + 2. A lane's
-// four pixel columns are the four pixels of one 16-byte load, so a block of
-// 16 columns is pixels p0 + 4 n + j. The series is not mean-removed: for k >= 1 a row of T sums
-// to zero, so the mean contributes only the FP64 rounding of that sum (the
-// products of FP32 q and FP64 twiddles are exact, accumulated in FP64).
-// MBG blocks of 16 rows are accumulated per pass over the series. Per
-// block of the grid (one wave) the FP64 sum and sum of squares of its
-// pixels' eta go to part[2 b], part[2 b + 1].
-template <int MBG, bool VEC>
+// Per-pixel form of Eq. (10) on the matrix cores. The series of a pixel is
+// real, so with u_s = x_s + x_(n'-s) and v_s = x_s - x_(n'-s) for
+// 0 < s < n' / 2 (u_s = x_s, v_s = 0 at s = 0 and s = n' / 2) the transform at
+// frequency k is
+//   Re = sum_{s=0}^{floor(n'/2)} u_s cos(2 pi k s / n'),
+//   Im = -sum_{s=1}^{floor(n'/2)} v_s sin(2 pi k s / n'),
+// half the products of the unfolded sum. u and v of FP32 q are exact in
+// FP64. For a tile of 64 pixels both are FP64 matrix products D = T U:
+// v_mfma_f64_16x16x4 takes 16 rows x 4 folded steps (A: lane i + 16 kk holds
+// T[i][kk], the cosine or sine of 2 pi f s / n' for the row's frequency f) and
+// 4 steps x 16 pixels (B: lane n + 16 kk holds u or v of step kk, pixel
+// column n) and accumulates D, whose register r of lane n + 16 c holds row
+// 4 r + c of pixel column n. A block of 16 rows is 16 consecutive
+// frequencies, with one accumulator for the cosine rows (B = u) and one for
+// the sine rows (B = v): register r of lane n + 16 c then holds Re (resp. Im)
+// of frequency 16 b + 4 r + c + 1 of pixel column n. A lane's four pixel
+// columns are the four pixels of one 16-byte load, so a block of 16 columns
+// is pixels p0 + 4 n + j. The series is not mean-removed: for k >= 1 the
+// weights of a row sum to zero, so the mean contributes only the FP64
+// rounding of that sum (the products of exact FP64 u, v and FP64 twiddles are
+// accumulated in FP64). MBG blocks of 16 frequencies are accumulated per pass
+// over the series. The loads run D step groups ahead of the products, along
+// the wave's whole walk (tiles, passes, groups; the group count padded to a
+// multiple of D with empty groups), so they cross pass and tile boundaries
+// and about D groups of loads are in flight per wave. Per block of the grid (one wave) the FP64 sum
+// and sum of squares of its pixels' eta go to part[2 b], part[2 b + 1].
+template <int MBG, bool VEC, int D>
 __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t plane, int harm, const double2* twg,
                                                float* eta_f, double* part, const CallDev* cd, int n_ring,
                                                int ring_first, int ring_cap) {
@@ -1280,77 +1289,132 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
   const int lane = threadIdx.x;
   const int n = lane & 15, kk = lane >> 4;
   const int K = np / 2;
-  const int nmb = (2 * K + 15) / 16;
-  const int T = (np + 3) / 4;
+  const int L = np / 2;                // last folded step
+  const int nmb = (K + 15) / 16;
+  const int T = (L + 4) / 4;           // step groups covering s = 0 .. L
   for (int i = lane; i < np; i += 64) lds_tw[i] = twg[i];
   __syncthreads();
-  double s1 = 0.0, s2 = 0.0;
+  // series step s: the newest n_ring of the field's kept maps (held from slot
+  // px_start, oldest first; serving), then the call's. px_start < ring_cap and
+  // ring_first + n_ring <= ring_cap, so one wrap suffices. Branch-free: the
+  // loop below keeps its accumulators in place only without branches.
+  const int rbase = n_ring > 0 ? cd->px_start + ring_first : 0;
+  const float* ring = n_ring > 0 ? cd->px_ring : q;
+  auto row_of = [&](int s) -> const float* {
+    const bool in_ring = s < n_ring;
+    int v = rbase + s;
+    v = v >= ring_cap ? v - ring_cap : v;
+    return (in_ring ? ring : q) + (int64_t)(in_ring ? v : s - n_ring) * plane;
+  };
+  // raw values of step group t for this lane: x_s and its partner x_(n'-s),
+  // zero where the step has none. Every load reads a valid step and pixel
+  // (clamped); values of pixels past the plane are never stored.
   const int64_t ntile = (plane + 63) / 64;
+  auto fetch = [&](int t, int64_t tile, float4& xs, float4& xp) {
+    const int64_t p0 = (tile < ntile ? tile : ntile - 1) * 64;
+    const int s = 4 * t + kk;
+    const bool live = s <= L;
+    const bool pair = live && s > 0 && np - s > s;
+    const float* r1 = row_of(live ? s : L) + p0;
+    const float* r2 = row_of(pair ? np - s : (live ? s : L)) + p0;
+    float4 a, b;
+    if (VEC) {
+      // plane % 4 == 0: a 16-byte group of pixels is wholly inside or outside
+      const int o = (int)min((int64_t)(4 * n), plane - 4 - p0);
+      a = *reinterpret_cast<const float4*>(r1 + o);
+      b = *reinterpret_cast<const float4*>(r2 + o);
+    } else {
+      int o[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) o[j] = (int)min((int64_t)(4 * n + j), plane - 1 - p0);
+      a = make_float4(r1[o[0]], r1[o[1]], r1[o[2]], r1[o[3]]);
+      b = make_float4(r2[o[0]], r2[o[1]], r2[o[2]], r2[o[3]]);
+    }
+    const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    xs = live ? a : z;
+    xp = pair ? b : z;
+  };
+  const int Tp = (T + D - 1) / D * D;
+  // prefetch cursor (wave-uniform): tile, pass (first block), group
+  int64_t ftile = blockIdx.x;
+  int fg = 0, fs = 0;
+  auto advance = [&]() {
+    if (++fs == Tp) {
+      fs = 0;
+      fg += MBG;
+      if (fg >= nmb) {
+        fg = 0;
+        ftile += gridDim.x;
+      }
+    }
+  };
+  float4 bs[D], bp[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    fetch(fs, ftile, bs[d], bp[d]);
+    advance();
+  }
+  double s1 = 0.0, s2 = 0.0;
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
     const int64_t p0 = tile * 64;
-    const bool full = p0 + 64 <= plane;
-    double best[4] = {0.0, 0.0, 0.0, 0.0};  // max over k of A_k^2 (pixel p0 + 4 n + j)
+    double best[4] = {0.0, 0.0, 0.0, 0.0};  // max over k of |X_k|^2 (pixel p0 + 4 n + j)
     for (int g = 0; g < nmb; g += MBG) {
-      fitrig_v4d acc[MBG][4];
+      fitrig_v4d ac[MBG][4], as[MBG][4];
       int idx[MBG], stp[MBG];
       bool rv[MBG];
 #pragma unroll
       for (int m = 0; m < MBG; ++m) {
-        const int f = 8 * (g + m) + 2 * (n & 3) + (n >> 3) + 1;  // frequency of this lane's A row
+        const int f = 16 * (g + m) + n + 1;  // frequency of this lane's A row
         rv[m] = f <= K;
         idx[m] = (int)(((int64_t)f * kk) % np);
         stp[m] = (int)(((int64_t)f * 4) % np);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[m][j] = fitrig_v4d{0.0, 0.0, 0.0, 0.0};
-      }
-      for (int t = 0; t < T; ++t) {
-        const int s = 4 * t + kk;
-        double b[4] = {0.0, 0.0, 0.0, 0.0};
-        if (s < np) {
-          // series step s: the newest n_ring of the field's kept maps (held
-          // from slot px_start, oldest first; serving), then the call's
-          const float* row = (s < n_ring ? cd->px_ring + (int64_t)((cd->px_start + ring_first + s) % ring_cap) * plane
-                                         : q + (int64_t)(s - n_ring) * plane) +
-                             p0 + 4 * n;
-          if (VEC && full) {
-            const float4 v = *reinterpret_cast<const float4*>(row);
-            b[0] = v.x;
-            b[1] = v.y;
-            b[2] = v.z;
-            b[3] = v.w;
-          } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-              if (p0 + 4 * n + j < plane) b[j] = row[j];
-          }
+        for (int j = 0; j < 4; ++j) {
+          ac[m][j] = fitrig_v4d{0.0, 0.0, 0.0, 0.0};
+          as[m][j] = fitrig_v4d{0.0, 0.0, 0.0, 0.0};
         }
+      }
+      for (int t = 0; t < Tp; t += D) {
 #pragma unroll
-        for (int m = 0; m < MBG; ++m) {
-          double a = 0.0;
-          if (rv[m] && s < np) {
+        for (int d = 0; d < D; ++d) {
+          const int s = 4 * (t + d) + kk;
+          const float4 cs = bs[d], cp = bp[d];
+          const double u[4] = {(double)cs.x + (double)cp.x, (double)cs.y + (double)cp.y,
+                               (double)cs.z + (double)cp.z, (double)cs.w + (double)cp.w};
+          const double v[4] = {(double)cs.x - (double)cp.x, (double)cs.y - (double)cp.y,
+                               (double)cs.z - (double)cp.z, (double)cs.w - (double)cp.w};
+          // the slot is free: the group D ahead goes into it
+          fetch(fs, ftile, bs[d], bp[d]);
+          advance();
+#pragma unroll
+          for (int m = 0; m < MBG; ++m) {
             const double2 w = lds_tw[idx[m]];
-            a = ((n >> 2) & 1) ? w.y : w.x;
-          }
-          idx[m] += stp[m];
-          if (idx[m] >= np) idx[m] -= np;
+            const bool on = rv[m] && s <= L;
+            const double wc = on ? w.x : 0.0, ws = on ? w.y : 0.0;
+            idx[m] += stp[m];
+            if (idx[m] >= np) idx[m] -= np;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[m][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[j], acc[m][j], 0, 0, 0);
+            for (int j = 0; j < 4; ++j) {
+              ac[m][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc, u[j], ac[m][j], 0, 0, 0);
+              as[m][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ws, v[j], as[m][j], 0, 0, 0);
+            }
+          }
         }
       }
-      // registers 0..3: (re, im) of f0 and of f0 + 1 (rows kk, kk + 4, kk + 8, kk + 12)
+      // register r: Re / Im of frequency 16 (g + m) + 4 r + kk + 1
 #pragma unroll
       for (int m = 0; m < MBG; ++m) {
-        const int f0 = 8 * (g + m) + 2 * kk + 1;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const double a0 = acc[m][j][0] * acc[m][j][0] + acc[m][j][1] * acc[m][j][1];
-          const double a1 = acc[m][j][2] * acc[m][j][2] + acc[m][j][3] * acc[m][j][3];
-          if (harm == 0) {
-            if (f0 <= K) best[j] = fmax(best[j], a0);
-            if (f0 + 1 <= K) best[j] = fmax(best[j], a1);
-          } else {
-            if (f0 <= K) ak[(f0 - 1) * 64 + 4 * n + j] = (float)sqrt(a0);
-            if (f0 + 1 <= K) ak[f0 * 64 + 4 * n + j] = (float)sqrt(a1);
+        for (int r = 0; r < 4; ++r) {
+          const int f = 16 * (g + m) + 4 * r + kk + 1;
+          if (f > K) continue;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const double a2 = ac[m][j][r] * ac[m][j][r] + as[m][j][r] * as[m][j][r];
+            if (harm == 0)
+              best[j] = fmax(best[j], a2);
+            else
+              ak[(f - 1) * 64 + 4 * n + j] = (float)sqrt(a2);
           }
         }
       }
