@@ -405,6 +405,11 @@ struct Stream {
   const void *fbase, *fc0, *fc1;  // frame pointers of the call
   int lane, wave, bid, band, grp, y0, x0, nseg_row, voff;
   int64_t wg_off;
+  // output offsets of the lane within one triple's plane (set once; the
+  // triple adds a uniform base): segment maxima, q map, moment partials,
+  // tile pieces
+  uint32_t seg_lane, q_lane;
+  int stat_lane, tile_lane;
   bool all_rows, interior;
   float inv_full;
   int mxi;
@@ -584,9 +589,9 @@ struct Stream {
     gmax = fmaxf(gmax, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(gmax), 0xB1, 0xF, 0xF, false)));
     gmax = fmaxf(gmax, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(gmax), 0x4E, 0xF, 0xF, false)));
     if ((ch & 3) == 0 && y < A.H && xc < A.W && NT * ch < A.out_w)
-      A.seg_max[((int64_t)s * A.H + y) * nseg_row + grp * kSegsPerGroup + (ch >> 2)] = gmax;
+      A.seg_max[(int64_t)s * ((int64_t)A.H * nseg_row) + seg_lane] = gmax;
     if (A.qmap && chv) {
-      float* dst = A.qmap + ((int64_t)s * A.H + y) * A.W + xc;
+      float* dst = A.qmap + (int64_t)s * A.plane + q_lane;
       if (xc + NT <= A.W && ((uintptr_t)dst & 15) == 0) {
         // whole chunk inside the row, 16-byte aligned: four 16-byte stores
 #pragma unroll
@@ -601,7 +606,7 @@ struct Stream {
     const double a1 = row_sum_f64(s1);
     const double a2 = row_sum_f64(s2);
     if ((lane & 15) == 15) {
-      double* sp = A.stat_part + (((int64_t)s * gridDim.x + bid) * 16 + (lane >> 4)) * 2;
+      double* sp = A.stat_part + ((int64_t)s * gridDim.x + bid) * 32 + stat_lane;
       sp[0] = a1;
       sp[1] = a2;
     }
@@ -628,7 +633,7 @@ struct Stream {
       sm += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sm), 0x141, 0xF, 0xF, false));
       mb = max(mb, (uint32_t)__builtin_amdgcn_mov_dpp((int)mb, 0x141, 0xF, 0xF, false));
       if (sub == 0 && qd < 3)
-        A.tile_part[((((int64_t)s * A.nbands + band) * A.ncol + grp) * kPieces + p) * 3 + qd] =
+        A.tile_part[(int64_t)s * ((int64_t)A.nbands * A.ncol * kPieces * 3) + tile_lane] =
             (double)(qd == 1 ? __uint_as_float(mb) : sm);
     }
     __syncthreads();
@@ -656,6 +661,15 @@ __global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
   st.all_rows = (st.y0 - H >= 0) && (st.y0 + kBand + H <= A.H);
   st.interior = st.all_rows && (st.x0 - H >= 0) && (st.x0 + A.out_w - 1 + H < A.W);
   st.nseg_row = A.ncol * kSegsPerGroup;
+  {
+    const int r = st.lane >> 4, ch = st.lane & 15;  // horizontal task of the lane
+    const int job = st.lane >> 3;                   // tile-piece job of the lane
+    const int qd = job / kPieces, p = job - kPieces * (job / kPieces);
+    st.seg_lane = (uint32_t)(st.y0 + r) * (uint32_t)st.nseg_row + (uint32_t)(st.grp * kSegsPerGroup + (ch >> 2));
+    st.q_lane = (uint32_t)(st.y0 + r) * (uint32_t)A.W + (uint32_t)(st.x0 + S::NT * ch);
+    st.stat_lane = (st.lane >> 4) * 2;
+    st.tile_lane = ((st.band * A.ncol + st.grp) * kPieces + p) * 3 + qd;
+  }
   constexpr int WN = (2 * H + 1) * (2 * H + 1);
   st.inv_full = 1.0f / (float)(WN * WN);
   st.mxi = INT32_MIN;
