@@ -386,6 +386,10 @@ def localisation(ctx, stack, tau: float, spec, stream) -> dict:
             "us_per_peak": round(statistics.median(ms) * 1e3 / max(len(peaks), 1), 3)}
 
 
+# largest stack the host-streaming measurement copies into page-locked memory
+HOST_STREAM_MAX_GIB = 48
+
+
 def host_stream(ctx, stack, tau: float, chunk: int, steps: int, ref_n_cand: int) -> dict:
     """The same stack from page-locked host memory, streamed to the device in
     chunks of frames (the copy of the next chunk overlaps the path over the
@@ -606,7 +610,11 @@ def main() -> int:
     if args.prefix_report and args.mode == "sliding":
         print("[bench] prefix-sum comparison", file=sys.stderr, flush=True)
         out["prefix_report"] = prefix_report(ctx, stack, tau, spec.window)
-    if not args.no_host_stream:
+    stack_gib = stack.numel() * stack.element_size() / 2**30
+    if not args.no_host_stream and stack_gib > HOST_STREAM_MAX_GIB:
+        out["host_stream"] = {"skipped": f"stack of {stack_gib:.1f} GiB exceeds the {HOST_STREAM_MAX_GIB} GiB "
+                                         "page-locked host copy this run allocates"}
+    elif not args.no_host_stream:
         print("[bench] streaming the stack from host memory", file=sys.stderr, flush=True)
         out["host_stream"] = host_stream(ctx, stack, tau, args.host_chunk, 3, stats["n_cand"])
     if raw is not None:
