@@ -1024,7 +1024,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
       }
       SegLayout L{Ty, Tx, np, 1, 64, (Tx + 63) / 64, 1, Ty};
       if ((rc = ensure(ctx, ctx->seg_max, (size_t)np * Ty * L.nseg_row * 4)) != FITRIG_OK) return rc;
-      KL(k_segmax_direct, dim3(grid_for((int64_t)np * Ty * L.nseg_row)), dim3(256), 0, st, (const float*)ctx->cube_f.p,
+      KL(k_segmax_direct, dim3(grid_for((int64_t)np * Ty * L.nseg_row * 16)), dim3(256), 0, st, (const float*)ctx->cube_f.p,
          L, (float*)ctx->seg_max.p);
       if ((rc = ensure_selection(ctx, (int64_t)np * Ty * L.nseg_row)) != FITRIG_OK) return rc;
       if ((rc = select_run(ctx, c, L, (float*)ctx->seg_max.p, mu, sigma, flags, FITRIG_IMAGE,
@@ -1076,7 +1076,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     const int64_t ne = (int64_t)Ty * L.nseg_row;
     if ((rc = ensure(ctx, ctx->seg_max2, (size_t)ne * 4)) != FITRIG_OK) return rc;
     float* smax = (float*)ctx->seg_max2.p;
-    KL(k_segmax_direct, dim3(grid_for(ne)), dim3(256), 0, st, (const float*)ctx->eta_f.p, L, smax);
+    KL(k_segmax_direct, dim3(grid_for(ne * 16)), dim3(256), 0, st, (const float*)ctx->eta_f.p, L, smax);
     if ((rc = ensure_selection(ctx, ne)) != FITRIG_OK) return rc;
     if ((rc = select_run(ctx, c, L, smax, est + ES_MU, est + ES_SIG, eflags, FITRIG_FREQ, (const float*)ctx->eta_f.p,
                          halo)) != FITRIG_OK)
@@ -1145,7 +1145,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     const int64_t ne = (int64_t)c.H * L.nseg_row;
     if ((rc = ensure(ctx, ctx->seg_max2, (size_t)ne * 4)) != FITRIG_OK) return rc;
     float* smax = (float*)ctx->seg_max2.p;
-    KL(k_segmax_direct, dim3(grid_for(ne)), dim3(256), 0, st, (const float*)ef, L, smax);
+    KL(k_segmax_direct, dim3(grid_for(ne * 16)), dim3(256), 0, st, (const float*)ef, L, smax);
     if ((rc = ensure_selection(ctx, ne)) != FITRIG_OK) return rc;
     if ((rc = select_run(ctx, c, L, smax, px_mu, px_sig, px_flag, FITRIG_FREQ_PIXEL, (const float*)ef, halo)) !=
         FITRIG_OK)

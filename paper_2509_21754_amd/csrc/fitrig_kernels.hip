@@ -700,16 +700,28 @@ __global__ void k_rs_finish(const double* lohi_med, const double* lohi_dev, int 
 // Selection: segment maxima of a direct value array, flags, deterministic
 // compaction, exact cell recompute, union-find components.
 // ---------------------------------------------------------------------------
-__global__ void k_segmax_direct(const float* vals, SegLayout L, float* seg_max) {
+// 16 threads per segment, 4 consecutive cells each (a segment's 64 cells are
+// read as 256 contiguous bytes), then a maximum over the 16 lanes.
+__global__ __launch_bounds__(256) void k_segmax_direct(const float* vals, SegLayout L, float* seg_max) {
   const int64_t total = (int64_t)L.nsets * L.Ho * L.nseg_row;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+  const int sub = threadIdx.x & 15;
+  // every lane of a 16-lane group runs the same iterations: the shuffles
+  // below see the whole group
+  for (int64_t e = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4; e < total;
+       e += ((int64_t)gridDim.x * blockDim.x) >> 4) {
     const int g = (int)(e % L.nseg_row);
     const int64_t row = e / L.nseg_row;  // set * Ho + y
     const int x0 = seg_x0(L, g), w = seg_width(L, g);
+    const float* v = vals + row * L.Wo + x0;
     float m = -INFINITY;
-    const float* v = vals + row * L.Wo;
-    for (int i = 0; i < w; ++i) m = fmaxf(m, v[x0 + i]);
-    seg_max[e] = m;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = 4 * sub + j;
+      if (i < w) m = fmaxf(m, v[i]);
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (sub == 0) seg_max[e] = m;
   }
 }
 
