@@ -73,6 +73,8 @@ __device__ __forceinline__ void tile_of(int t, int nbands, int ncol, int bb_size
   band = bb * bb_size + (u - grp * hb);
 }
 
+typedef float fitrig_v4f __attribute__((ext_vector_type(4)));
+
 // Order-preserving map of a float to uint32 (and back).
 __device__ __forceinline__ uint32_t ord_key(float v) {
   const uint32_t u = __float_as_uint(v);
@@ -593,10 +595,12 @@ struct Stream {
     if (A.qmap && chv) {
       float* dst = A.qmap + (int64_t)s * A.plane + q_lane;
       if (xc + NT <= A.W && ((uintptr_t)dst & 15) == 0) {
-        // whole chunk inside the row, 16-byte aligned: four 16-byte stores
+        // whole chunk inside the row, 16-byte aligned: four 16-byte stores,
+        // non-temporal (the map is read back by a later kernel, not by this one)
 #pragma unroll
         for (int c = 0; c < NT; c += 4)
-          *reinterpret_cast<float4*>(dst + c) = make_float4(qv[c], qv[c + 1], qv[c + 2], qv[c + 3]);
+          __builtin_nontemporal_store(fitrig_v4f{qv[c], qv[c + 1], qv[c + 2], qv[c + 3]},
+                                      reinterpret_cast<fitrig_v4f*>(dst + c));
       } else {
 #pragma unroll
         for (int c = 0; c < NT; ++c)

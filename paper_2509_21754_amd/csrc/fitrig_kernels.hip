@@ -1333,8 +1333,11 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
     if (VEC) {
       // plane % 4 == 0: a 16-byte group of pixels is wholly inside or outside
       const int o = (int)min((int64_t)(4 * n), plane - 4 - p0);
-      a = *reinterpret_cast<const float4*>(r1 + o);
-      b = *reinterpret_cast<const float4*>(r2 + o);
+      // read once: non-temporal
+      const fitrig_v4f av = __builtin_nontemporal_load(reinterpret_cast<const fitrig_v4f*>(r1 + o));
+      const fitrig_v4f bv = __builtin_nontemporal_load(reinterpret_cast<const fitrig_v4f*>(r2 + o));
+      a = make_float4(av.x, av.y, av.z, av.w);
+      b = make_float4(bv.x, bv.y, bv.z, bv.w);
     } else {
       int o[4];
 #pragma unroll
