@@ -1113,9 +1113,16 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     const bool vec = plane % 4 == 0 && ((uintptr_t)qcall & 15) == 0;
     // loads run 4 step groups (16 series steps) ahead, 2 for short series
     const bool deep = (nps / 2 + 4) / 4 >= 4;
-#define EPX(MB, V, DD)                                                                                            \
-  KL((k_eta_px<MB, V, DD>), dim3(G), dim3(64), lds, st, qcall, nps, plane, cfg.harm, (const double2*)ctx->tw_px.p, \
-     ef, (double*)ctx->pxpart.p, (const CallDev*)cd, px_from_ring, px_first, px_cap)
+#define EPX2(MB, V, DD, RG)                                                                                     \
+  KL((k_eta_px<MB, V, DD, RG>), dim3(G), dim3(64), lds, st, qcall, nps, plane, cfg.harm,                          \
+     (const double2*)ctx->tw_px.p, ef, (double*)ctx->pxpart.p, (const CallDev*)cd, px_from_ring, px_first, px_cap)
+#define EPX(MB, V, DD)        \
+  do {                        \
+    if (px_from_ring > 0)     \
+      EPX2(MB, V, DD, true);  \
+    else                      \
+      EPX2(MB, V, DD, false); \
+  } while (0)
     if (deep) {
       if (vec) {
         if (mbg == 1) EPX(1, true, 4); else EPX(2, true, 4);
@@ -1130,6 +1137,7 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
       }
     }
 #undef EPX
+#undef EPX2
     LAUNCH_CHECK(ctx);
     double* px_mu = est + ES_PXMU;
     double* px_sig = est + ES_PXSIG;

@@ -1266,6 +1266,17 @@ __global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t
 
 typedef double fitrig_v4d __attribute__((ext_vector_type(4)));
 
+// f(integral_constant<int, I>) for I = B .. E - 1, unrolled at compile time.
+template <int B, int E, class F>
+__device__ __forceinline__ void fitrig_static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    fitrig_static_for<B + 1, E>(f);
+  }
+}
+typedef __attribute__((address_space(1))) float fitrig_gf;        // global memory
+typedef __attribute__((address_space(1))) fitrig_v4f fitrig_gv4f;
+
 // Per-pixel form of Eq. (10) on the matrix cores. The series of a pixel is
 // real, so with u_s = x_s + x_(n'-s) and v_s = x_s - x_(n'-s) for
 // 0 < s < n' / 2 (u_s = x_s, v_s = 0 at s = 0 and s = n' / 2) the transform at
@@ -1292,7 +1303,7 @@ typedef double fitrig_v4d __attribute__((ext_vector_type(4)));
 // multiple of D with empty groups), so they cross pass and tile boundaries
 // and about D groups of loads are in flight per wave. Per block of the grid (one wave) the FP64 sum
 // and sum of squares of its pixels' eta go to part[2 b], part[2 b + 1].
-template <int MBG, bool VEC, int D>
+template <int MBG, bool VEC, int D, bool RING>
 __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t plane, int harm, const double2* twg,
                                                float* eta_f, double* part, const CallDev* cd, int n_ring,
                                                int ring_first, int ring_cap) {
@@ -1318,50 +1329,69 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
     v = v >= ring_cap ? v - ring_cap : v;
     return (in_ring ? ring : q) + (int64_t)(in_ring ? v : s - n_ring) * plane;
   };
-  // raw values of step group t for this lane: x_s and its partner x_(n'-s),
-  // zero where the step has none. Every load reads a valid step and pixel
-  // (clamped); values of pixels past the plane are never stored.
-  const int64_t ntile = (plane + 63) / 64;
-  auto fetch = [&](int t, int64_t tile, float4& xs, float4& xp) {
-    const int64_t p0 = (tile < ntile ? tile : ntile - 1) * 64;
+  // raw values of step group t for this lane: x_s and its partner x_(n'-s).
+  // Every load reads a valid step and pixel (clamped); values of pixels past
+  // the plane are never stored. Steps without a value or a partner are zeroed
+  // where the values are used, not here: a select on a load's result would
+  // make the wave wait for that load at once and undo the prefetch.
+  // 32-bit wave-uniform tile and plane arithmetic (plane < 2^32, so tiles
+  // < 2^26): 64-bit compares and multiplies would run on the vector ALU
+  const int ntile = (int)((plane + 63) / 64);
+  const uint32_t plane32 = (uint32_t)plane;
+  const int gsz = gridDim.x;
+  auto fetch = [&](int t, int tile, float4& xs, float4& xp) {
+    const uint32_t tc = (uint32_t)(tile < ntile ? tile : ntile - 1);
+    const int64_t p0 = (int64_t)tc * 64;
     const int s = 4 * t + kk;
-    const bool live = s <= L;
-    const bool pair = live && s > 0 && np - s > s;
-    const float* r1 = row_of(live ? s : L) + p0;
-    const float* r2 = row_of(pair ? np - s : (live ? s : L)) + p0;
-    float4 a, b;
+    // rows read: x_s and x_(n'-s), or any valid row where the step has no
+    // value or no partner (those are zeroed where the values are used)
+    const int s1 = min(s, np - 1);
+    const int s2 = max(0, min(np - s, np - 1));
+    // global address space: generic (flat) loads would also count against
+    // the LDS counter, so every wait for a twiddle read would wait for all
+    // prefetched rows
+    const fitrig_gf* g1;
+    const fitrig_gf* g2;
+    if constexpr (RING) {
+      g1 = (const fitrig_gf*)(row_of(s1) + p0);
+      g2 = (const fitrig_gf*)(row_of(s2) + p0);
+    } else {
+      // one 32 x 32 -> 64-bit multiply-add per row
+      const fitrig_gf* base = (const fitrig_gf*)q + p0;
+      g1 = base + (uint64_t)(uint32_t)s1 * plane32;
+      g2 = base + (uint64_t)(uint32_t)s2 * plane32;
+    }
+    const uint32_t rem = plane32 - tc * 64u;  // pixels from p0 to the end of the plane (>= 1)
     if (VEC) {
       // plane % 4 == 0: a 16-byte group of pixels is wholly inside or outside
-      const int o = (int)min((int64_t)(4 * n), plane - 4 - p0);
+      const int o = min(4 * n, (int)min(rem - 4u, 60u));
       // read once: non-temporal
-      const fitrig_v4f av = __builtin_nontemporal_load(reinterpret_cast<const fitrig_v4f*>(r1 + o));
-      const fitrig_v4f bv = __builtin_nontemporal_load(reinterpret_cast<const fitrig_v4f*>(r2 + o));
-      a = make_float4(av.x, av.y, av.z, av.w);
-      b = make_float4(bv.x, bv.y, bv.z, bv.w);
+      const fitrig_v4f av = __builtin_nontemporal_load((const fitrig_gv4f*)(g1 + o));
+      const fitrig_v4f bv = __builtin_nontemporal_load((const fitrig_gv4f*)(g2 + o));
+      xs = make_float4(av.x, av.y, av.z, av.w);
+      xp = make_float4(bv.x, bv.y, bv.z, bv.w);
     } else {
+      const int lim = (int)min(rem - 1u, 63u);
       int o[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) o[j] = (int)min((int64_t)(4 * n + j), plane - 1 - p0);
-      a = make_float4(r1[o[0]], r1[o[1]], r1[o[2]], r1[o[3]]);
-      b = make_float4(r2[o[0]], r2[o[1]], r2[o[2]], r2[o[3]]);
+      for (int j = 0; j < 4; ++j) o[j] = min(4 * n + j, lim);
+      xs = make_float4(g1[o[0]], g1[o[1]], g1[o[2]], g1[o[3]]);
+      xp = make_float4(g2[o[0]], g2[o[1]], g2[o[2]], g2[o[3]]);
     }
-    const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    xs = live ? a : z;
-    xp = pair ? b : z;
   };
   const int Tp = (T + D - 1) / D * D;
   // prefetch cursor (wave-uniform): tile, pass (first block), group
-  int64_t ftile = blockIdx.x;
+  int ftile = blockIdx.x;
   int fg = 0, fs = 0;
+  // branch-free (selects): branches would split the unrolled loop body and
+  // make the compiler copy the prefetch slots at the back edge
   auto advance = [&]() {
-    if (++fs == Tp) {
-      fs = 0;
-      fg += MBG;
-      if (fg >= nmb) {
-        fg = 0;
-        ftile += gridDim.x;
-      }
-    }
+    const bool w1 = fs + 1 == Tp;
+    fs = w1 ? 0 : fs + 1;
+    const int g1 = fg + (w1 ? MBG : 0);
+    const bool w2 = g1 >= nmb;
+    fg = w2 ? 0 : g1;
+    ftile += w2 ? gsz : 0;
   };
   float4 bs[D], bp[D];
 #pragma unroll
@@ -1370,11 +1400,11 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
     advance();
   }
   double s1 = 0.0, s2 = 0.0;
-  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    const int64_t p0 = tile * 64;
+  for (int tile = blockIdx.x; tile < ntile; tile += gsz) {
+    const int64_t p0 = (int64_t)tile * 64;
     double best[4] = {0.0, 0.0, 0.0, 0.0};  // max over k of |X_k|^2 (pixel p0 + 4 n + j)
     for (int g = 0; g < nmb; g += MBG) {
-      fitrig_v4d ac[MBG][4], as[MBG][4];
+      fitrig_v4d ac[MBG][4], as[MBG][4];  // written by the pass's first step group
       int idx[MBG], stp[MBG];
       bool rv[MBG];
 #pragma unroll
@@ -1383,39 +1413,56 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
         rv[m] = f <= K;
         idx[m] = (int)(((int64_t)f * kk) % np);
         stp[m] = (int)(((int64_t)f * 4) % np);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          ac[m][j] = fitrig_v4d{0.0, 0.0, 0.0, 0.0};
-          as[m][j] = fitrig_v4d{0.0, 0.0, 0.0, 0.0};
-        }
       }
-      for (int t = 0; t < Tp; t += D) {
+      // one step group (slot DC of the group t .. t + D - 1); the first group
+      // of a pass starts its products from a zero accumulator instead of
+      // clearing 64 registers per tile
+      auto group = [&](auto FIRSTC, auto DC, int t) {
+        constexpr bool FIRST = decltype(FIRSTC)::value;
+        constexpr int d = decltype(DC)::value;
+        const int s = 4 * (t + d) + kk;
+        const bool live = s <= L;
+        const bool pair = live && s > 0 && np - s > s;
+        // a step past the series has zero weights (below), so only a missing
+        // partner is zeroed; the slot holds finite q of a valid row
+        const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const float4 cs = bs[d], cp = pair ? bp[d] : z;
+        double u[4] = {(double)cs.x + (double)cp.x, (double)cs.y + (double)cp.y, (double)cs.z + (double)cp.z,
+                       (double)cs.w + (double)cp.w};
+        double v[4] = {(double)cs.x - (double)cp.x, (double)cs.y - (double)cp.y, (double)cs.z - (double)cp.z,
+                       (double)cs.w - (double)cp.w};
+        // the slot is free: the group D ahead goes into it. u and v are
+        // materialised first and the load cannot move above the empty asm,
+        // so the new value can take the old one's registers (otherwise the
+        // back edge copies them, and a copy waits for its load)
+        asm volatile("" : "+v"(u[0]), "+v"(u[1]), "+v"(u[2]), "+v"(u[3]), "+v"(v[0]), "+v"(v[1]), "+v"(v[2]),
+                     "+v"(v[3])
+                     :
+                     : "memory");
+        fetch(fs, ftile, bs[d], bp[d]);
+        advance();
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const int s = 4 * (t + d) + kk;
-          const float4 cs = bs[d], cp = bp[d];
-          const double u[4] = {(double)cs.x + (double)cp.x, (double)cs.y + (double)cp.y,
-                               (double)cs.z + (double)cp.z, (double)cs.w + (double)cp.w};
-          const double v[4] = {(double)cs.x - (double)cp.x, (double)cs.y - (double)cp.y,
-                               (double)cs.z - (double)cp.z, (double)cs.w - (double)cp.w};
-          // the slot is free: the group D ahead goes into it
-          fetch(fs, ftile, bs[d], bp[d]);
-          advance();
+        for (int m = 0; m < MBG; ++m) {
+          const double2 w = lds_tw[idx[m]];
+          const bool on = rv[m] && s <= L;
+          const double wc = on ? w.x : 0.0, ws = on ? w.y : 0.0;
+          idx[m] += stp[m];
+          if (idx[m] >= np) idx[m] -= np;
 #pragma unroll
-          for (int m = 0; m < MBG; ++m) {
-            const double2 w = lds_tw[idx[m]];
-            const bool on = rv[m] && s <= L;
-            const double wc = on ? w.x : 0.0, ws = on ? w.y : 0.0;
-            idx[m] += stp[m];
-            if (idx[m] >= np) idx[m] -= np;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
+          for (int j = 0; j < 4; ++j) {
+            if constexpr (FIRST) {
+              const fitrig_v4d zero = {0.0, 0.0, 0.0, 0.0};
+              ac[m][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc, u[j], zero, 0, 0, 0);
+              as[m][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ws, v[j], zero, 0, 0, 0);
+            } else {
               ac[m][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc, u[j], ac[m][j], 0, 0, 0);
               as[m][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ws, v[j], as[m][j], 0, 0, 0);
             }
           }
         }
-      }
+      };
+      fitrig_static_for<0, D>([&](auto DC) { group(std::integral_constant<bool, DC.value == 0>{}, DC, 0); });
+      for (int t = D; t < Tp; t += D) fitrig_static_for<0, D>([&](auto DC) { group(std::false_type{}, DC, t); });
       // register r: Re / Im of frequency 16 (g + m) + 4 r + kk + 1
 #pragma unroll
       for (int m = 0; m < MBG; ++m) {
@@ -1440,17 +1487,14 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
         best[j] = fmax(best[j], __shfl_xor(best[j], 16));
         best[j] = fmax(best[j], __shfl_xor(best[j], 32));
       }
-      if (kk == 0) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int64_t p = p0 + 4 * n + j;
-          if (p < plane) {
-            const double e = sqrt(best[j]);
-            eta_f[p] = (float)e;
-            s1 += e;
-            s2 = fma(e, e, s2);
-          }
-        }
+      // lane n + 16 kk finishes pixel p0 + 4 n + kk (one square root per lane)
+      const double bj = kk == 0 ? best[0] : kk == 1 ? best[1] : kk == 2 ? best[2] : best[3];
+      const int64_t p = p0 + 4 * n + kk;
+      if (p < plane) {
+        const double e = sqrt(bj);
+        eta_f[p] = (float)e;
+        s1 += e;
+        s2 = fma(e, e, s2);
       }
     } else {
       __syncthreads();
