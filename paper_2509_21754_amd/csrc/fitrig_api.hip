@@ -1113,15 +1113,22 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     const bool vec = plane % 4 == 0 && ((uintptr_t)qcall & 15) == 0;
     // loads run 4 step groups (16 series steps) ahead, 2 for short series
     const bool deep = (nps / 2 + 4) / 4 >= 4;
+    // short series: one pass of at most 16 frequencies and one round of step
+    // groups, no field ring (weights and row offsets fixed per lane)
+    const int tgroups = (nps / 2 + 4) / 4, dpre = deep ? 4 : 2;
+    const bool shortk = px_from_ring == 0 && nmb == 1 && (tgroups + dpre - 1) / dpre * dpre == dpre;
 #define EPX2(MB, V, DD, RG)                                                                                     \
   KL((k_eta_px<MB, V, DD, RG>), dim3(G), dim3(64), lds, st, qcall, nps, plane, cfg.harm,                          \
      (const double2*)ctx->tw_px.p, ef, (double*)ctx->pxpart.p, (const CallDev*)cd, px_from_ring, px_first, px_cap)
-#define EPX(MB, V, DD)        \
-  do {                        \
-    if (px_from_ring > 0)     \
-      EPX2(MB, V, DD, true);  \
-    else                      \
-      EPX2(MB, V, DD, false); \
+#define EPX(MB, V, DD)                                                                                 \
+  do {                                                                                                 \
+    if (px_from_ring > 0)                                                                              \
+      EPX2(MB, V, DD, true);                                                                           \
+    else if (MB == 1 && shortk)                                                                        \
+      KL((k_eta_px_short<V, DD>), dim3(G), dim3(64), lds, st, qcall, nps, plane, cfg.harm,             \
+         (const double2*)ctx->tw_px.p, ef, (double*)ctx->pxpart.p);                                    \
+    else                                                                                               \
+      EPX2(MB, V, DD, false);                                                                          \
   } while (0)
     if (deep) {
       if (vec) {

@@ -1303,10 +1303,10 @@ typedef __attribute__((address_space(1))) fitrig_v4f fitrig_gv4f;
 // multiple of D with empty groups), so they cross pass and tile boundaries
 // and about D groups of loads are in flight per wave. Per block of the grid (one wave) the FP64 sum
 // and sum of squares of its pixels' eta go to part[2 b], part[2 b + 1].
-template <int MBG, bool VEC, int D, bool RING>
-__global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t plane, int harm, const double2* twg,
-                                               float* eta_f, double* part, const CallDev* cd, int n_ring,
-                                               int ring_first, int ring_cap) {
+template <int MBG, bool VEC, int D, bool RING, bool SHORT>
+__device__ __forceinline__ void eta_px_body(const float* q, int np, int64_t plane, int harm, const double2* twg,
+                                            float* eta_f, double* part, const CallDev* cd, int n_ring,
+                                            int ring_first, int ring_cap) {
   extern __shared__ double2 lds_tw[];         // [np] twiddles, then [K][64] float magnitudes (harmonic sums)
   float* ak = (float*)(lds_tw + np);
   const int lane = threadIdx.x;
@@ -1343,10 +1343,11 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
     const uint32_t tc = (uint32_t)(tile < ntile ? tile : ntile - 1);
     const int64_t p0 = (int64_t)tc * 64;
     const int s = 4 * t + kk;
-    // rows read: x_s and x_(n'-s), or any valid row where the step has no
-    // value or no partner (those are zeroed where the values are used)
+    // rows read: x_s and x_(n'-s); a step without a partner reads its own
+    // row twice (u = 2 x_s, v = 0 exactly; its weight is halved where the
+    // values are used), a step past the series any valid row (weight zero)
     const int s1 = min(s, np - 1);
-    const int s2 = max(0, min(np - s, np - 1));
+    const int s2 = (s > 0 && 2 * s < np) ? np - s : s1;
     // global address space: generic (flat) loads would also count against
     // the LDS counter, so every wait for a twiddle read would wait for all
     // prefetched rows
@@ -1379,6 +1380,23 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
       xp = make_float4(g2[o[0]], g2[o[1]], g2[o[2]], g2[o[3]]);
     }
   };
+  // Short series (SHORT: one pass of at most 16 frequencies, one round of D
+  // step groups, no ring): a lane's weights are the same for every tile, so
+  // they are set once (no twiddle read, index update or weight factor per
+  // step group).
+  double wcs[D], wss[D];
+  if constexpr (SHORT) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int s = 4 * d + kk;
+      const double2 w = lds_tw[(int)(((int64_t)(n + 1) * s) % np)];
+      const double sc = s > L ? 0.0 : (s > 0 && 2 * s < np) ? 1.0 : 0.5;
+      // rows of frequencies above K get zero weights: their magnitudes are 0
+      const bool fv = n + 1 <= K;
+      wcs[d] = fv ? w.x * sc : 0.0;
+      wss[d] = fv ? w.y : 0.0;
+    }
+  }
   const int Tp = (T + D - 1) / D * D;
   // prefetch cursor (wave-uniform): tile, pass (first block), group
   int ftile = blockIdx.x;
@@ -1406,11 +1424,9 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
     for (int g = 0; g < nmb; g += MBG) {
       fitrig_v4d ac[MBG][4], as[MBG][4];  // written by the pass's first step group
       int idx[MBG], stp[MBG];
-      bool rv[MBG];
 #pragma unroll
       for (int m = 0; m < MBG; ++m) {
         const int f = 16 * (g + m) + n + 1;  // frequency of this lane's A row
-        rv[m] = f <= K;
         idx[m] = (int)(((int64_t)f * kk) % np);
         stp[m] = (int)(((int64_t)f * 4) % np);
       }
@@ -1421,12 +1437,11 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
         constexpr bool FIRST = decltype(FIRSTC)::value;
         constexpr int d = decltype(DC)::value;
         const int s = 4 * (t + d) + kk;
-        const bool live = s <= L;
-        const bool pair = live && s > 0 && np - s > s;
-        // a step past the series has zero weights (below), so only a missing
-        // partner is zeroed; the slot holds finite q of a valid row
-        const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        const float4 cs = bs[d], cp = pair ? bp[d] : z;
+        // cosine weight factor: 1 for a pair, 1/2 for x_0 and x_(n'/2) (read
+        // twice, u = 2 x_s), 0 past the series; the sine rows see v = 0
+        // wherever there is no pair. Rows of frequencies above K are never read.
+        const double sc = s > L ? 0.0 : (s > 0 && 2 * s < np) ? 1.0 : 0.5;
+        const float4 cs = bs[d], cp = bp[d];
         double u[4] = {(double)cs.x + (double)cp.x, (double)cs.y + (double)cp.y, (double)cs.z + (double)cp.z,
                        (double)cs.w + (double)cp.w};
         double v[4] = {(double)cs.x - (double)cp.x, (double)cs.y - (double)cp.y, (double)cs.z - (double)cp.z,
@@ -1443,11 +1458,17 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
         advance();
 #pragma unroll
         for (int m = 0; m < MBG; ++m) {
-          const double2 w = lds_tw[idx[m]];
-          const bool on = rv[m] && s <= L;
-          const double wc = on ? w.x : 0.0, ws = on ? w.y : 0.0;
-          idx[m] += stp[m];
-          if (idx[m] >= np) idx[m] -= np;
+          double wc, ws;
+          if constexpr (SHORT) {
+            wc = wcs[d];
+            ws = wss[d];
+          } else {
+            const double2 w = lds_tw[idx[m]];
+            wc = w.x * sc;
+            ws = w.y;
+            idx[m] += stp[m];
+            if (idx[m] >= np) idx[m] -= np;
+          }
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             if constexpr (FIRST) {
@@ -1462,21 +1483,39 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
         }
       };
       fitrig_static_for<0, D>([&](auto DC) { group(std::integral_constant<bool, DC.value == 0>{}, DC, 0); });
-      for (int t = D; t < Tp; t += D) fitrig_static_for<0, D>([&](auto DC) { group(std::false_type{}, DC, t); });
-      // register r: Re / Im of frequency 16 (g + m) + 4 r + kk + 1
+      if constexpr (!SHORT)
+        for (int t = D; t < Tp; t += D) fitrig_static_for<0, D>([&](auto DC) { group(std::false_type{}, DC, t); });
+      // register r: Re / Im of frequency 16 (g + m) + 4 r + kk + 1 (the test
+      // of harm is uniform and taken once, not per element)
+      if (harm == 0) {
+        // per pixel: the maximum over this pass's rows first (values of
+        // arithmetic, no canonicalisation), then one maximum with best
 #pragma unroll
-      for (int m = 0; m < MBG; ++m) {
+        for (int j = 0; j < 4; ++j) {
+          double mj = 0.0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int f = 16 * (g + m) + 4 * r + kk + 1;
-          if (f > K) continue;
+          for (int m = 0; m < MBG; ++m) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const double a2 = ac[m][j][r] * ac[m][j][r] + as[m][j][r] * as[m][j][r];
-            if (harm == 0)
-              best[j] = fmax(best[j], a2);
-            else
-              ak[(f - 1) * 64 + 4 * n + j] = (float)sqrt(a2);
+            for (int r = 0; r < 4; ++r) {
+              const int f = 16 * (g + m) + 4 * r + kk + 1;
+              double a2 = fma(ac[m][j][r], ac[m][j][r], as[m][j][r] * as[m][j][r]);
+              if constexpr (!SHORT) a2 = f > K ? 0.0 : a2;  // SHORT: those rows are 0
+              mj = (m == 0 && r == 0) ? a2 : fmax(mj, a2);
+            }
+          }
+          best[j] = fmax(best[j], mj);
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < MBG; ++m) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = 16 * (g + m) + 4 * r + kk + 1;
+            if (f > K) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              ak[(f - 1) * 64 + 4 * n + j] =
+                  (float)sqrt(fma(ac[m][j][r], ac[m][j][r], as[m][j][r] * as[m][j][r]));
           }
         }
       }
@@ -1523,6 +1562,21 @@ __global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t p
     part[2 * (int64_t)blockIdx.x] = s1;
     part[2 * (int64_t)blockIdx.x + 1] = s2;
   }
+}
+
+template <int MBG, bool VEC, int D, bool RING>
+__global__ __launch_bounds__(64) void k_eta_px(const float* q, int np, int64_t plane, int harm, const double2* twg,
+                                               float* eta_f, double* part, const CallDev* cd, int n_ring,
+                                               int ring_first, int ring_cap) {
+  eta_px_body<MBG, VEC, D, RING, false>(q, np, plane, harm, twg, eta_f, part, cd, n_ring, ring_first, ring_cap);
+}
+
+// Short series (one pass of at most 16 frequencies, one round of step groups,
+// no field ring): weights set once per wave.
+template <bool VEC, int D>
+__global__ __launch_bounds__(64) void k_eta_px_short(
+    const float* q, int np, int64_t plane, int harm, const double2* twg, float* eta_f, double* part) {
+  eta_px_body<1, VEC, D, false, true>(q, np, plane, harm, twg, eta_f, part, nullptr, 0, 0, 1);
 }
 
 // ---------------------------------------------------------------------------

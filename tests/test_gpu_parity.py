@@ -317,6 +317,9 @@ def test_crop_interior_bitwise(w, dt):
 
 @pytest.mark.parametrize("n,H,W,window,branches,dtype,sigma_est,harm", [
     (12, 48, 300, 5, 7, "f32", 0, 0),     # n' = 10, all three branches
+    (32, 40, 200, 5, 4, "f32", 0, 0),     # n' = 30 (one round of four step groups)
+    (26, 21, 77, 3, 5, "f32", 0, 2),      # n' = 24, harmonic sum, H*W not a multiple of 4
+    (33, 30, 96, 7, 4, "f16", 1, 0),      # n' = 31 (odd), median/MAD
     (34, 40, 260, 3, 4, "f32", 0, 0),     # n' = 32, per-pixel branch alone
     (66, 30, 130, 5, 5, "f32", 1, 3),     # n' = 64, median/MAD, harmonic sum
     (22, 37, 250, 7, 6, "f16", 0, 0),     # FP16 storage
