@@ -460,7 +460,8 @@ __global__ void k_rs_mad_window(const uint32_t* bkt1, int nsets, double* pl, uin
 // cells counted (cnt1[2s+1]) and gathered (the bits of q) into g1. Two LDS
 // stages, each appended with one atomic per flush. NONNEG: every value is
 // +0 or positive (then its order key is its bits with the top bit set).
-constexpr int kGather2Round = 256 * 8;
+constexpr int kGather2PT = 8;  // values per thread per round (16 measured slower)
+constexpr int kGather2Round = 256 * kGather2PT;
 template <bool VEC, bool NONNEG>
 __global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t per_set, const uint32_t* bkt0,
                                                     const uint32_t* wk, int64_t cap0, int64_t cap1,
@@ -489,10 +490,12 @@ __global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t p
       if ((int64_t)(b0 + j) < cap) out[b0 + j] = stage[which][j];
     __syncthreads();  // stage and gbase read before they are reused
   };
-  auto fetch = [&](int64_t base, float (&q)[8]) {
+  constexpr int PT = kGather2PT;
+  static_assert(PT % 4 == 0 && PT <= 16, "two selection bits per value in 32 bits; 16-bit round counts");
+  auto fetch = [&](int64_t base, float (&q)[PT]) {
     if (VEC) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < PT / 4; ++j) {
         const int64_t i = base + 4 * ((int64_t)j * 256 + threadIdx.x);  // per_set % 4 == 0
         const float4 x = i < per_set ? *reinterpret_cast<const float4*>(v + i) : make_float4(0.f, 0.f, 0.f, 0.f);
         q[4 * j + 0] = x.x;
@@ -502,7 +505,7 @@ __global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t p
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < PT; ++j) {
         const int64_t i = base + (int64_t)j * 256 + threadIdx.x;
         q[j] = i < per_set ? v[i] : 0.0f;
       }
@@ -511,26 +514,26 @@ __global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t p
   auto index_of = [&](int64_t base, int j) -> int64_t {
     return VEC ? base + 4 * ((int64_t)(j >> 2) * 256 + threadIdx.x) + (j & 3) : base + (int64_t)j * 256 + threadIdx.x;
   };
-  float q[8];
+  float q[PT];
   int64_t base = blockIdx.x * (int64_t)kGather2Round;
   if (base < per_set) fetch(base, q);
   for (; base < per_set; base += step) {
-    float nq[8];
+    float nq[PT];
     if (base + step < per_set) fetch(base + step, nq);
-    uint32_t k[8];
-    uint32_t sel = 0;  // bit j: median bracket, bit 8 + j: MAD window
+    uint32_t k[PT];
+    uint32_t sel = 0;  // bit j: median bracket, bit PT + j: MAD window
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < PT; ++j) {
       const bool ok = index_of(base, j) < per_set;
       k[j] = NONNEG ? (__float_as_uint(q[j]) | 0x80000000u) : ord_key(q[j]);
       const bool in_w = k[j] > kB && k[j] < kC;
       below += (ok && k[j] < lo) ? 1u : 0u;
       inner += (ok && in_w) ? 1u : 0u;
       sel |= (ok && k[j] - lo <= hi - lo) ? (1u << j) : 0u;
-      sel |= (ok && !in_w && k[j] - kA <= kD - kA) ? (1u << (8 + j)) : 0u;
+      sel |= (ok && !in_w && k[j] - kA <= kD - kA) ? (1u << (PT + j)) : 0u;
     }
-    // counts of both stages packed in 16-bit halves (at most 2048 each)
-    const uint32_t c = (uint32_t)__popc(sel & 0xFFu) | ((uint32_t)__popc(sel >> 8) << 16);
+    // counts of both stages packed in 16-bit halves (at most 256 PT each)
+    const uint32_t c = (uint32_t)__popc(sel & ((1u << PT) - 1u)) | ((uint32_t)__popc(sel >> PT) << 16);
     const uint32_t inc = wave_incl_scan(c);
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
@@ -551,16 +554,16 @@ __global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t p
       const uint32_t ex = woff + inc - c;
       uint32_t p0 = nst0 + (ex & 0xFFFFu), p1 = nst1 + (ex >> 16);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < PT; ++j) {
         if (sel & (1u << j)) stage[0][p0++] = k[j];
-        if (sel & (1u << (8 + j))) stage[1][p1++] = __float_as_uint(q[j]);
+        if (sel & (1u << (PT + j))) stage[1][p1++] = __float_as_uint(q[j]);
       }
     }
     nst0 += tot0;
     nst1 += tot1;
     __syncthreads();  // stages written and wsum read by every thread
 #pragma unroll
-    for (int j = 0; j < 8; ++j) q[j] = nq[j];
+    for (int j = 0; j < PT; ++j) q[j] = nq[j];
   }
   if (nst0) flush(0, nst0);
   if (nst1) flush(1, nst1);
