@@ -782,8 +782,11 @@ __global__ __launch_bounds__(kLanes) void k_tile(TileArgs A) {
 // previous two frames of the band's rows in registers and walks every frame
 // once. Per triple it accumulates, per tile
 // row of the band, the column's sum Delta, max Delta and sum r (FP32 over at
-// most 32 rows), then one job per tile sums its columns in FP64 and writes
-// the tile's q (Eq. (6) with the in-image count) to the cube.
+// most 32 rows). For tiles of 16 and 32 the TILE lanes of a tile then combine
+// their columns by a fixed butterfly of shuffles (sums in FP64, maximum
+// exact), with no LDS and no barrier per triple; for smaller tiles the
+// partials go through LDS and one job per tile sums its columns in FP64. The
+// tile's q (Eq. (6) with the in-image count) goes to the cube.
 // ---------------------------------------------------------------------------
 constexpr int kTileTpbMax = 8;    // tile rows per band
 template <typename T, int TILE, bool RS>
@@ -791,7 +794,8 @@ __global__ __launch_bounds__(kLanes) void k_tile_stream(TileStreamArgs A) {
   constexpr int TPB = (32 / TILE) < kTileTpbMax ? (32 / TILE) : kTileTpbMax;
   constexpr int ROWS = TPB * TILE;
   constexpr int TPC = kLanes / TILE;        // whole tiles per chunk
-  __shared__ float col[TPB][3][kLanes];
+  static_assert(TILE <= 64 && (TILE & (TILE - 1)) == 0, "a tile's lanes lie in one wave");
+  __shared__ float col[TILE >= 16 ? 1 : TPB][3][kLanes];
   __shared__ int mxs[kLanes / 64];
   const int lane = threadIdx.x;
   const int chunk = blockIdx.x % A.nchunk, band = blockIdx.x / A.nchunk;
@@ -841,34 +845,63 @@ __global__ __launch_bounds__(kLanes) void k_tile_stream(TileStreamArgs A) {
     }
     if (k < 2) continue;
     const int s = k - 2;
-    __syncthreads();  // the previous triple's jobs have read col
-#pragma unroll
-    for (int t = 0; t < TPB; ++t) {
-      col[t][0][lane] = sd[t];
-      col[t][1][lane] = md[t];
-      col[t][2][lane] = sr[t];
-    }
-    __syncthreads();
-    // one job per (tile row of the band, tile of the chunk)
-    for (int job = lane; job < TPB * TPC; job += kLanes) {
-      const int t = job / TPC, j = job - t * TPC;
-      const int ty = band * TPB + t;
-      const int tx = chunk * TPC + j;
-      if (ty >= A.Ty || tx >= A.Tx) continue;
+    if constexpr (TILE >= 16) {
+      // few tiles per chunk: the TILE lanes of a tile combine their columns
+      const int j = lane / TILE;  // tile of the chunk
       const int ca = j * TILE;
-      const int cb = min(ca + TILE, A.W - chunk * kLanes);
-      double a0 = 0.0, a2 = 0.0;
-      float a1 = 0.0f;
-      for (int c = ca; c < cb; ++c) {
-        a0 += (double)col[t][0][c];
-        a1 = fmaxf(a1, col[t][1][c]);
-        a2 += (double)col[t][2][c];
+      const int cb = min(ca + TILE, A.W - chunk * kLanes);  // in-image columns end
+#pragma unroll
+      for (int t = 0; t < TPB; ++t) {
+        double a0 = (double)sd[t], a2 = (double)sr[t];
+        float a1 = md[t];
+#pragma unroll
+        for (int off = 1; off < TILE; off <<= 1) {
+          a0 += __shfl_xor(a0, off);
+          a2 += __shfl_xor(a2, off);
+          a1 = fmaxf(a1, __shfl_xor(a1, off));
+        }
+        const int ty = band * TPB + t;
+        const int tx = chunk * TPC + j;
+        if ((lane & (TILE - 1)) == 0 && ty < A.Ty && tx < A.Tx) {
+          const double n = (double)(min(ty * TILE + TILE, A.H) - ty * TILE) * (double)(cb - ca);
+          const double v = (a0 / n) * (double)a1 * (a2 / n);
+          const int64_t o = ((int64_t)s * A.Ty + ty) * A.Tx + tx;
+          A.cube[o] = v;
+          A.cube_f[o] = (float)v;
+        }
       }
-      const double n = (double)(min(ty * TILE + TILE, A.H) - ty * TILE) * (double)(cb - ca);
-      const double v = (a0 / n) * (double)a1 * (a2 / n);
-      const int64_t o = ((int64_t)s * A.Ty + ty) * A.Tx + tx;
-      A.cube[o] = v;
-      A.cube_f[o] = (float)v;
+    } else {
+      // many tiles per chunk: per-column partials through LDS, one job per
+      // (tile row, tile) summing its columns
+      __syncthreads();  // the previous triple's jobs have read col
+#pragma unroll
+      for (int t = 0; t < TPB; ++t) {
+        col[t][0][lane] = sd[t];
+        col[t][1][lane] = md[t];
+        col[t][2][lane] = sr[t];
+      }
+      __syncthreads();
+      // one job per (tile row of the band, tile of the chunk)
+      for (int job = lane; job < TPB * TPC; job += kLanes) {
+        const int t = job / TPC, j = job - t * TPC;
+        const int ty = band * TPB + t;
+        const int tx = chunk * TPC + j;
+        if (ty >= A.Ty || tx >= A.Tx) continue;
+        const int ca = j * TILE;
+        const int cb = min(ca + TILE, A.W - chunk * kLanes);
+        double a0 = 0.0, a2 = 0.0;
+        float a1 = 0.0f;
+        for (int c = ca; c < cb; ++c) {
+          a0 += (double)col[t][0][c];
+          a1 = fmaxf(a1, col[t][1][c]);
+          a2 += (double)col[t][2][c];
+        }
+        const double n = (double)(min(ty * TILE + TILE, A.H) - ty * TILE) * (double)(cb - ca);
+        const double v = (a0 / n) * (double)a1 * (a2 / n);
+        const int64_t o = ((int64_t)s * A.Ty + ty) * A.Tx + tx;
+        A.cube[o] = v;
+        A.cube_f[o] = (float)v;
+      }
     }
   }
 #pragma unroll
