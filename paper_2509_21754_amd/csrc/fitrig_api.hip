@@ -1060,8 +1060,15 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     if ((rc = ensure(ctx, ctx->eta_f, ntiles * 4)) != FITRIG_OK) return rc;
     if ((rc = ensure(ctx, ctx->tw, (size_t)P.nfreq * 16)) != FITRIG_OK) return rc;
     KL(k_twiddle, dim3(grid_for(P.nfreq)), dim3(256), 0, st, P.nfreq, (double2*)ctx->tw.p);
-    KL(k_eta, dim3(grid_for(ntiles, 256, 4096)), dim3(256), 0, st, series, P.nfreq, ntiles, cfg.harm,
-       (const double2*)ctx->tw.p, (double*)ctx->eta_d.p, (float*)ctx->eta_f.p);
+    // long series: a workgroup per tile (twiddles, series and magnitudes in LDS)
+    const size_t blk_lds = (size_t)P.nfreq * 16 + (size_t)P.nfreq * 8 + (size_t)(P.nfreq / 2) * 8;
+    if (P.nfreq >= 128 && blk_lds <= 60 * 1024) {
+      KL(k_eta_blk, dim3((unsigned)std::min<int64_t>(ntiles, 65536)), dim3(256), blk_lds, st, series, P.nfreq,
+         ntiles, cfg.harm, (const double2*)ctx->tw.p, (double*)ctx->eta_d.p, (float*)ctx->eta_f.p);
+    } else {
+      KL(k_eta, dim3(grid_for(ntiles, 256, 4096)), dim3(256), 0, st, series, P.nfreq, ntiles, cfg.harm,
+         (const double2*)ctx->tw.p, (double*)ctx->eta_d.p, (float*)ctx->eta_f.p);
+    }
     LAUNCH_CHECK(ctx);
     if (!P.robust) {
       if ((rc = moments(ctx, st, (const double*)ctx->eta_d.p, 1, ntiles, 1, ntiles, est + ES_MU, est + ES_SIG,

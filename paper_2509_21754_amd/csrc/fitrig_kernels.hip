@@ -1267,6 +1267,73 @@ __global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t
   }
 }
 
+// Tile branch for long series: one workgroup per tile, the threads over the
+// frequencies. The series (mean removed; the mean summed serially in s, as in
+// k_eta), the twiddles and the magnitudes |X_k| sit in LDS; each |X_k| is
+// formed once (k_eta forms |X_jk| again for every harmonic sum that uses it),
+// then each thread takes the harmonic sums of its frequencies and the block
+// takes their maximum. Per frequency the arithmetic and its order are k_eta's,
+// so eta is the same.
+__global__ __launch_bounds__(256) void k_eta_blk(const double* cube, int np, int64_t ntiles, int harm,
+                                                 const double2* twg, double* eta, float* eta_f) {
+  extern __shared__ double2 lds_e[];  // [np] twiddles, [np] series, [K] magnitudes
+  __shared__ double red[256];
+  __shared__ double smean;
+  double2* tw = lds_e;
+  double* ser = (double*)(lds_e + np);
+  double* amp = ser + np;
+  const int K = np / 2;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < np; i += 256) tw[i] = twg[i];
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int s = tid; s < np; s += 256) ser[s] = cube[(int64_t)s * ntiles + t];
+    __syncthreads();
+    if (tid == 0) {
+      double mean = 0.0;
+      for (int s = 0; s < np; ++s) mean += ser[s];
+      smean = mean / (double)np;
+    }
+    __syncthreads();
+    const double mean = smean;
+    for (int k = 1 + tid; k <= K; k += 256) {
+      double re = 0.0, im = 0.0;
+      int ph = 0;
+      for (int s = 0; s < np; ++s) {
+        const double v = ser[s] - mean;
+        const double2 w = tw[ph];
+        re = fma(v, w.x, re);
+        im = fma(-v, w.y, im);
+        ph += k;
+        if (ph >= np) ph -= np;
+      }
+      amp[k - 1] = sqrt(re * re + im * im);
+    }
+    __syncthreads();
+    // harmonic sums (j = 1 .. harm, jk <= K, in order of j) and their maximum
+    double best = 0.0;
+    bool have = false;
+    const int jmax = harm == 0 ? 1 : harm;
+    for (int k = 1 + tid; k <= K; k += 256) {
+      double val = 0.0;
+      for (int j = 1; j <= jmax && j * k <= K; ++j) val += amp[j * k - 1];
+      if (!have || val > best) best = val;
+      have = true;
+    }
+    red[tid] = have ? best : -1.0;  // magnitudes are >= 0
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double b = K < 1 ? 0.0 : red[0];
+      eta[t] = b;
+      if (eta_f) eta_f[t] = (float)b;
+    }
+    __syncthreads();  // ser, amp and red are reused by the next tile
+  }
+}
+
 typedef double fitrig_v4d __attribute__((ext_vector_type(4)));
 
 // f(integral_constant<int, I>) for I = B .. E - 1, unrolled at compile time.

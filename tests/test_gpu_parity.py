@@ -231,6 +231,25 @@ def test_freq_branch_only(harm):
     assert all(c["branch"] == ref.FREQ and c["triple"] == -1 for c in cands)
 
 
+@pytest.mark.parametrize("n,harm", [(200, 0), (200, 4), (303, 3)])
+def test_freq_branch_long_series(n, harm):
+    """Tile branch on series of n' >= 128 (a workgroup per tile): eta per tile
+    against the oracle, candidates by component; H, W not multiples of the
+    tile."""
+    rng = np.random.default_rng(n + harm)
+    X = structured_stack(70 + n, n, 45, 110)
+    period = int(rng.integers(5, 12))
+    for k in range(0, n, period):
+        X[k, 10:15, 40:46] += 8.0
+    tau = 3.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, branches=2, harm=harm, tile=16)
+    assert rc == 0
+    out = ref.detect(used, tau=tau, branches=ref.FREQ, harm=harm, tile=16)
+    check_eta(eta, out["eta"])
+    check_candidates(cands, out, tau)
+    assert any(c["branch"] == ref.FREQ for c in cands)
+
+
 def test_r_signed_reading():
     X = structured_stack(61, 6, 40, 280)
     X -= 1.0
