@@ -228,16 +228,21 @@ fitrig_status fitrig_detect_noalloc(fitrig_ctx* ctx, const void* stack, fitrig_d
  * every triple so far, so the frequency branch runs once, on the last chunk,
  * over the whole series. Every result equals fitrig_detect's on the same
  * stack in device memory, bit for bit.
- *   host_stack   host, [n_snap][H][W] row-major, dtype as given; page-locked
- *                memory (hipHostMalloc, a pinned torch tensor) lets the copies
- *                overlap the kernels, pageable memory works but does not
+ *   host_stack   host, [n_snap][H][W] row-major, dtype as given. Page-locked
+ *                memory (hipHostMalloc, a pinned torch tensor) is copied
+ *                directly; pageable memory is copied by host threads into two
+ *                page-locked staging buffers of chunk_frames frames ahead of
+ *                the device (for stacks that cannot be page-locked whole). In
+ *                both cases the copies overlap the kernels. A device pointer
+ *                is E_INVAL.
  *   chunk_frames frames per copy (>= 1; the first chunk holds at least 3)
  *   cand, cand_cap, n_cand, eta_map (device, nullable), stats: as
  *                fitrig_detect (no index maps: they would not fit the point
  *                of streaming)
- * The call allocates (and frees) 3 chunk buffers (4 when chunk_frames = 1)
- * and, for the frequency branch, an (n_snap-2) * ceil(H/tile) *
- * ceil(W/tile) FP64 history; it is synchronous on the context's stream.
+ * The call allocates (and frees) 3 chunk buffers (4 when chunk_frames = 1),
+ * for pageable input the 2 staging buffers and one filler thread, and, for
+ * the frequency branch, an (n_snap-2) * ceil(H/tile) * ceil(W/tile) FP64
+ * history; it is synchronous on the context's stream.
  * Errors: E_INVAL (as fitrig_detect, chunk_frames < 1, FITRIG_FREQ_PIXEL in
  * the config), E_NOMEM, E_HIP.
  */

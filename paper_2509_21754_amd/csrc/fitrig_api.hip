@@ -23,9 +23,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -1579,13 +1581,69 @@ bool size_shape(const fitrig_config& cfg, const Call& c, fitrig_ctx& tmp) {
 }
 
 // Device memory and streams of one host-resident call, released on scope exit.
+// Pageable input: chunks are copied by host threads into two page-locked
+// staging buffers ahead of the device, and each transfer goes from a staging
+// buffer, so transfers overlap the path as they do from page-locked input.
+// The filler thread refills a buffer once the transfer out of it has
+// completed; the caller's thread waits for a chunk to be staged before it
+// issues its transfer.
+struct Stager {
+  int dev = 0;
+  char* buf[2] = {nullptr, nullptr};
+  hipEvent_t out[2] = {nullptr, nullptr};  // transfer out of buffer b done
+  std::mutex mu;
+  std::condition_variable cv;
+  int staged = 0;   // chunks copied into a buffer
+  int issued = 0;   // chunks whose transfer has been enqueued
+  bool stop = false;
+  bool failed = false;
+  std::thread th;
+  void finish() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    if (th.joinable()) th.join();
+  }
+  ~Stager() {
+    finish();
+    (void)hipSetDevice(dev);
+    for (int b = 0; b < 2; ++b) {
+      if (out[b]) (void)hipEventSynchronize(out[b]);
+      if (out[b]) (void)hipEventDestroy(out[b]);
+      if (buf[b]) (void)hipHostFree(buf[b]);
+    }
+  }
+};
+
+// memcpy of n bytes split over up to 16 host threads
+void parallel_copy(char* dst, const char* src, size_t n) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int T = (int)std::min<size_t>(std::min(16u, hw), std::max<size_t>(1, n >> 24));
+  if (T <= 1) {
+    memcpy(dst, src, n);
+    return;
+  }
+  std::vector<std::thread> ts;
+  const size_t part = (n + T - 1) / T;
+  for (int t = 1; t < T; ++t) {
+    const size_t a = (size_t)t * part, b = std::min(n, a + part);
+    if (a < b) ts.emplace_back([=] { memcpy(dst + a, src + a, b - a); });
+  }
+  memcpy(dst, src, std::min(n, part));
+  for (std::thread& x : ts) x.join();
+}
+
 struct HostPipe {
   int dev = 0;
   char* buf = nullptr;      // nbuf chunk buffers of cap_frames frames
   double* hist = nullptr;   // tile cube of every triple so far (frequency branch)
   hipStream_t copy = nullptr;
   hipEvent_t ev[4] = {};
+  Stager* stage = nullptr;  // pageable input only
   ~HostPipe() {
+    delete stage;  // stops the filler thread first
     (void)hipSetDevice(dev);
     if (copy) (void)hipStreamSynchronize(copy);
     for (hipEvent_t e : ev)
@@ -1627,9 +1685,76 @@ fitrig_status detect_host_impl(fitrig_ctx* ctx, const char* host, fitrig_dtype d
     while (start[j] > f) --j;
     return P.buf + (size_t)(j % nbuf) * L0 * fb + (size_t)(f - start[j]) * fb;
   };
+  // page-locked input is copied straight from the caller's memory; pageable
+  // input through the stager
+  bool pinned = false;
+  {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, host) == hipSuccess) {
+      if (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeArray) return FITRIG_E_INVAL;
+      pinned = at.type == hipMemoryTypeHost;
+    } else {
+      (void)hipGetLastError();  // unregistered memory may report an error
+    }
+  }
+  if (!pinned) {
+    P.stage = new (std::nothrow) Stager;
+    if (!P.stage) return FITRIG_E_NOMEM;
+    Stager& S = *P.stage;
+    S.dev = cfg.device;
+    for (int b = 0; b < 2; ++b) {
+      if (hipHostMalloc((void**)&S.buf[b], (size_t)L0 * fb, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        S.buf[b] = nullptr;
+        return FITRIG_E_NOMEM;
+      }
+      HIP_TRY(ctx, hipEventCreateWithFlags(&S.out[b], hipEventDisableTiming));
+    }
+    S.th = std::thread([&S, &start, len, host, fb, nch] {
+      (void)hipSetDevice(S.dev);
+      for (int j = 0; j < nch; ++j) {
+        const int b = j & 1;
+        {
+          // buffer b is free once the transfer of chunk j - 2 is enqueued and done
+          std::unique_lock<std::mutex> lk(S.mu);
+          S.cv.wait(lk, [&] { return S.stop || S.issued >= j - 1; });
+          if (S.stop) return;
+        }
+        if (j >= 2 && hipEventSynchronize(S.out[b]) != hipSuccess) {
+          std::lock_guard<std::mutex> lk(S.mu);
+          S.failed = true;
+          S.cv.notify_all();
+          return;
+        }
+        parallel_copy(S.buf[b], host + (size_t)start[j] * fb, (size_t)len(j) * fb);
+        {
+          std::lock_guard<std::mutex> lk(S.mu);
+          S.staged = j + 1;
+        }
+        S.cv.notify_all();
+      }
+    });
+  }
   auto copy_in = [&](int i) -> fitrig_status {
     char* dst = P.buf + (size_t)(i % nbuf) * L0 * fb;
-    HIP_TRY(ctx, hipMemcpyAsync(dst, host + (size_t)start[i] * fb, (size_t)len(i) * fb, hipMemcpyHostToDevice, P.copy));
+    if (pinned) {
+      HIP_TRY(ctx, hipMemcpyAsync(dst, host + (size_t)start[i] * fb, (size_t)len(i) * fb, hipMemcpyHostToDevice,
+                                  P.copy));
+    } else {
+      Stager& S = *P.stage;
+      {
+        std::unique_lock<std::mutex> lk(S.mu);
+        S.cv.wait(lk, [&] { return S.failed || S.staged > i; });
+        if (S.failed) return FITRIG_E_HIP;
+      }
+      HIP_TRY(ctx, hipMemcpyAsync(dst, S.buf[i & 1], (size_t)len(i) * fb, hipMemcpyHostToDevice, P.copy));
+      HIP_TRY(ctx, hipEventRecord(S.out[i & 1], P.copy));
+      {
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.issued = i + 1;
+      }
+      S.cv.notify_all();
+    }
     HIP_TRY(ctx, hipEventRecord(P.ev[i % nbuf], P.copy));
     return FITRIG_OK;
   };

@@ -472,7 +472,8 @@ class Context:
     def detect_host(self, stack, sigma: float, chunk_frames: int, *, cand_cap: int = 1 << 16, eta_map=None,
                     as_dicts: bool = True):
         """Run the path on a stack in host memory ([n][H][W] CPU tensor,
-        f32/f16/bf16; pinned memory overlaps the copies), streamed in chunks
+        f32/f16/bf16; pinned memory is copied directly, pageable memory through
+        page-locked staging buffers filled by host threads), streamed in chunks
         of ``chunk_frames`` frames. Returns (candidates, stats, status) as
         ``detect``."""
         import torch
