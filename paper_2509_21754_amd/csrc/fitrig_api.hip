@@ -98,10 +98,11 @@ struct AsyncOut {
 struct GraphKey {
   int n, H, W, ncarry, dtype, hist_cap, hist_n_in, hist_out, px_cap, px_n;
   int64_t cand_cap;
+  int maps;  // bit 0: index map, bit 1: eta map, bit 2: per-pixel eta map (the kernels chosen depend on them)
   bool operator==(const GraphKey& o) const {
     return n == o.n && H == o.H && W == o.W && ncarry == o.ncarry && dtype == o.dtype && hist_cap == o.hist_cap &&
            hist_n_in == o.hist_n_in && hist_out == o.hist_out && px_cap == o.px_cap && px_n == o.px_n &&
-           cand_cap == o.cand_cap;
+           cand_cap == o.cand_cap && maps == o.maps;
   }
 };
 struct GraphEntry {
@@ -326,9 +327,10 @@ int grid_for(int64_t n, int per = 256, int maxg = 8192) {
 // Kernels templated on the storage type: one argument struct by value (the
 // stack maximum: three arguments).
 bool dispatch_stream(fitrig_ctx* ctx, int dt, int halo, bool rs, dim3 g, hipStream_t st, const StreamArgs& A) {
-  const void* fn = dt == FITRIG_F32 ? kernel_stream_f32(halo, rs)
-                   : dt == FITRIG_F16 ? kernel_stream_f16(halo, rs)
-                                      : kernel_stream_bf16(halo, rs);
+  const bool q = A.qmap != nullptr;
+  const void* fn = dt == FITRIG_F32 ? kernel_stream_f32(halo, rs, q)
+                   : dt == FITRIG_F16 ? kernel_stream_f16(halo, rs, q)
+                                      : kernel_stream_bf16(halo, rs, q);
   if (!fn) return false;
   void* a[] = {(void*)&A};
   note_launch(ctx, launch_raw(ctx, fn, g, dim3(kLanes), 0, st, a));
@@ -1382,7 +1384,8 @@ fitrig_status detect_graph(fitrig_ctx* ctx, const Call& c, fitrig_candidate* can
   }
   const GraphKey key{c.n, c.H, c.W, c.ncarry, (int)c.dtype, c.hist ? c.hist->cap : 0, c.hist ? c.hist->n_in : 0,
                      (c.hist && c.hist->out) ? 1 + (c.hist->defer ? 1 : 0) : 0, c.hist ? c.hist->px_cap : 0,
-                     c.hist ? c.hist->px_n : 0, cap};
+                     c.hist ? c.hist->px_n : 0, cap,
+                     (c.index_map ? 1 : 0) | (c.eta_map ? 2 : 0) | (c.eta_px_map ? 4 : 0)};
   GraphEntry* e = nullptr;
   for (GraphEntry& g : ctx->graphs)
     if (g.key == key) e = &g;

@@ -380,7 +380,9 @@ constexpr int kOffMasked = 0x40000000;
 // of every 64-cell row segment, optional q map rows, and (tile == 32) the
 // per-column sums of the 32-row tiles for the frequency branch.
 // ---------------------------------------------------------------------------
-template <typename T, int H, bool RS>
+// Q: the call writes the q map (a compile-time switch: the map's stores and
+// pointer would otherwise hold scalar registers the loop needs)
+template <typename T, int H, bool RS, bool Q>
 struct Stream {
   static constexpr int NR = kBand + 2 * H;
   static constexpr int NT = 16;            // outputs per horizontal task
@@ -565,7 +567,7 @@ struct Stream {
       s1 *= id;
       s2 *= id * id;
       gmax *= inv_full;
-      if (A.qmap) {
+      if constexpr (Q) {
 #pragma unroll
         for (int c = 0; c < NT; ++c) qv[c] = pv[c] * inv_full;
       }
@@ -592,7 +594,7 @@ struct Stream {
     gmax = fmaxf(gmax, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(gmax), 0x4E, 0xF, 0xF, false)));
     if ((ch & 3) == 0 && y < A.H && xc < A.W && NT * ch < A.out_w)
       A.seg_max[(int64_t)s * ((int64_t)A.H * nseg_row) + seg_lane] = gmax;
-    if (A.qmap && chv) {
+    if (Q && chv) {
       float* dst = A.qmap + (int64_t)s * A.plane + q_lane;
       if (xc + NT <= A.W && ((uintptr_t)dst & 15) == 0) {
         // whole chunk inside the row, 16-byte aligned: four 16-byte stores,
@@ -644,9 +646,9 @@ struct Stream {
   }
 };
 
-template <typename T, int H, bool RS>
+template <typename T, int H, bool RS, bool Q>
 __global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
-  using S = Stream<T, H, RS>;
+  using S = Stream<T, H, RS, Q>;
   __shared__ typename S::Shared sh;
   S st(A, sh);
   st.fbase = A.cd->base;

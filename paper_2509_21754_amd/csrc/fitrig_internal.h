@@ -160,9 +160,9 @@ struct ResultLayout {
 
 // Kernels templated on the storage type, per type (fitrig_launch.hip): the
 // host handle of the instantiation for the given parameters, null if none.
-const void* kernel_stream_f32(int halo, bool r_signed);
-const void* kernel_stream_f16(int halo, bool r_signed);
-const void* kernel_stream_bf16(int halo, bool r_signed);
+const void* kernel_stream_f32(int halo, bool r_signed, bool qmap);
+const void* kernel_stream_f16(int halo, bool r_signed, bool qmap);
+const void* kernel_stream_bf16(int halo, bool r_signed, bool qmap);
 const void* kernel_tile_stream_f32(int tile, bool r_signed);
 const void* kernel_tile_stream_f16(int tile, bool r_signed);
 const void* kernel_tile_stream_bf16(int tile, bool r_signed);

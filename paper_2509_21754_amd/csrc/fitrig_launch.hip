@@ -26,10 +26,12 @@ using T = bf16_t;
 // Each returns the kernel for the given template parameters (the host
 // handle that hipLaunchKernel and graph kernel nodes take), or null when no
 // instantiation covers them. Every kernel takes its argument struct by value.
-const void* SFX(kernel_stream)(int halo, bool rs) {
+const void* SFX(kernel_stream)(int halo, bool rs, bool q) {
   switch (halo) {
-#define CASE(h) \
-  case h: return rs ? (const void*)&k_stream<T, h, true> : (const void*)&k_stream<T, h, false>;
+#define CASE(h)                                                                                     \
+  case h:                                                                                           \
+    return q ? (rs ? (const void*)&k_stream<T, h, true, true> : (const void*)&k_stream<T, h, false, true>) \
+             : (rs ? (const void*)&k_stream<T, h, true, false> : (const void*)&k_stream<T, h, false, false>);
     CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: return nullptr;

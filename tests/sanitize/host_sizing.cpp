@@ -9,9 +9,9 @@
 
 namespace fitrig {
 // The launch pass never runs here; the kernel handles are not needed.
-const void* kernel_stream_f32(int, bool) { return nullptr; }
-const void* kernel_stream_f16(int, bool) { return nullptr; }
-const void* kernel_stream_bf16(int, bool) { return nullptr; }
+const void* kernel_stream_f32(int, bool, bool) { return nullptr; }
+const void* kernel_stream_f16(int, bool, bool) { return nullptr; }
+const void* kernel_stream_bf16(int, bool, bool) { return nullptr; }
 const void* kernel_tile_stream_f32(int, bool) { return nullptr; }
 const void* kernel_tile_stream_f16(int, bool) { return nullptr; }
 const void* kernel_tile_stream_bf16(int, bool) { return nullptr; }
