@@ -71,7 +71,9 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
         with ThreadPoolExecutor(max_workers=n) as ex:
             objs = list(ex.map(compile_unit, UNITS))
         tmp = LIB + ".tmp"
-        cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
+        # roctx: named ranges of the launch phases for rocprofv3 --marker-trace
+        cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread",
+               "-lrocprofiler-sdk-roctx"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

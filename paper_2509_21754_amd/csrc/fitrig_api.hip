@@ -19,6 +19,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -853,7 +854,24 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     prof = cs == hipStreamCaptureStatusNone;
   }
   if (!ctx->sizing) ctx->ev_recorded = prof;
+  // named host ranges of the phases being enqueued (rocprofv3 --marker-trace);
+  // the guard closes the open one on every return
+  struct PhaseRange {
+    bool on, open = false;
+    void to(const char* name) {
+      if (!on) return;
+      if (open) roctxRangePop();
+      roctxRangePushA(name);
+      open = true;
+    }
+    ~PhaseRange() {
+      if (open) roctxRangePop();
+    }
+  } range{!ctx->sizing};
+  static const char* const kPhaseName[5] = {"fitrig: index pass", "fitrig: spread", "fitrig: image selection",
+                                            "fitrig: frequency branches", "fitrig: results"};
   auto mark = [&](int i) -> fitrig_status {
+    range.to(kPhaseName[i]);
     if (prof) HIP_TRY(ctx, hipEventRecord(ctx->ev[i], st));
     return FITRIG_OK;
   };

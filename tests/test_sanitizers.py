@@ -43,7 +43,7 @@ def test_host_runtime_under_sanitizers(tmp_path):
     for f in SAN:
         cmd += ["-Xarch_host", f]
     cmd += ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2509_21754_amd", "csrc"),
-            os.path.join(ROOT, "tests", "sanitize", "host_sizing.cpp"), "-o", str(exe)]
+            os.path.join(ROOT, "tests", "sanitize", "host_sizing.cpp"), "-o", str(exe), "-lrocprofiler-sdk-roctx"]
     b = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
     assert b.returncode == 0, b.stderr[-4000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
