@@ -414,6 +414,8 @@ struct Stream {
   // tile pieces
   uint32_t seg_lane, q_lane;
   int stat_lane, tile_lane;
+  bool qvec;  // the lane's q-map chunk is whole and 16-byte aligned in every triple
+  int qn;     // q-map cells of the lane's chunk inside the row
   bool all_rows, interior;
   float inv_full;
   int mxi;
@@ -596,7 +598,7 @@ struct Stream {
       A.seg_max[(int64_t)s * ((int64_t)A.H * nseg_row) + seg_lane] = gmax;
     if (Q && chv) {
       float* dst = A.qmap + (int64_t)s * A.plane + q_lane;
-      if (xc + NT <= A.W && ((uintptr_t)dst & 15) == 0) {
+      if (qvec) {
         // whole chunk inside the row, 16-byte aligned: four 16-byte stores,
         // non-temporal (the map is read back by a later kernel, not by this one)
 #pragma unroll
@@ -606,7 +608,7 @@ struct Stream {
       } else {
 #pragma unroll
         for (int c = 0; c < NT; ++c)
-          if (xc + c < A.W) dst[c] = qv[c];
+          if (c < qn) dst[c] = qv[c];
       }
     }
     const double a1 = row_sum_f64(s1);
@@ -673,6 +675,10 @@ __global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
     const int qd = job / kPieces, p = job - kPieces * (job / kPieces);
     st.seg_lane = (uint32_t)(st.y0 + r) * (uint32_t)st.nseg_row + (uint32_t)(st.grp * kSegsPerGroup + (ch >> 2));
     st.q_lane = (uint32_t)(st.y0 + r) * (uint32_t)A.W + (uint32_t)(st.x0 + S::NT * ch);
+    // the map is 16-byte aligned; a triple's plane keeps the alignment when
+    // H W is a multiple of 4
+    st.qn = max(0, min(S::NT, A.W - (st.x0 + S::NT * ch)));
+    st.qvec = Q && st.qn == S::NT && A.plane % 4 == 0 && st.q_lane % 4 == 0 && ((uintptr_t)A.qmap & 15) == 0;
     st.stat_lane = (st.lane >> 4) * 2;
     st.tile_lane = ((st.band * A.ncol + st.grp) * kPieces + p) * 3 + qd;
   }

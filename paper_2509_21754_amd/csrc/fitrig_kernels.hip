@@ -497,7 +497,9 @@ __global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t p
 #pragma unroll
       for (int j = 0; j < PT / 4; ++j) {
         const int64_t i = base + 4 * ((int64_t)j * 256 + threadIdx.x);  // per_set % 4 == 0
-        const float4 x = i < per_set ? *reinterpret_cast<const float4*>(v + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+        // read once: non-temporal
+        const fitrig_v4f x = i < per_set ? __builtin_nontemporal_load(reinterpret_cast<const fitrig_v4f*>(v + i))
+                                         : fitrig_v4f{0.f, 0.f, 0.f, 0.f};
         q[4 * j + 0] = x.x;
         q[4 * j + 1] = x.y;
         q[4 * j + 2] = x.z;
