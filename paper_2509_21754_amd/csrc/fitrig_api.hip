@@ -727,6 +727,9 @@ fitrig_status select_run(fitrig_ctx* ctx, const Call& c, const SegLayout& L, flo
     return rc;
 
   const int gsel = (int)std::min<int64_t>(cap, 4096);
+  // recompute: one wave per segment, grid-stride; 8192 waves put 8 on each
+  // SIMD, which hides the latency of the frame reads
+  const int grec = (int)std::min<int64_t>(cap, 8192);
   if (direct_vals) {
     KL(k_fill_direct, dim3(gsel), dim3(64), 0, st, direct_vals, L, (const int64_t*)seg_entry,
        (const int64_t*)(cnt + CNT_NSEL), cap, mu, sigma, cd, mask, cq);
@@ -746,7 +749,7 @@ fitrig_status select_run(fitrig_ctx* ctx, const Call& c, const SegLayout& L, flo
     R.sigma = sigma;
     R.mask = mask;
     R.cell_q = cq;
-    if (!dispatch_recompute(ctx, c.dtype, halo, ctx->cfg.r_signed != 0, dim3(gsel), st, R)) return FITRIG_E_INVAL;
+    if (!dispatch_recompute(ctx, c.dtype, halo, ctx->cfg.r_signed != 0, dim3(grec), st, R)) return FITRIG_E_INVAL;
   }
   LAUNCH_CHECK(ctx);
   const int gcell = grid_for(cap * 64, 256, 4096);
@@ -1087,6 +1090,16 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
     if (P.nfreq >= 128 && blk_lds <= 60 * 1024) {
       KL(k_eta_blk, dim3((unsigned)std::min<int64_t>(ntiles, 65536)), dim3(256), blk_lds, st, series, P.nfreq,
          ntiles, cfg.harm, (const double2*)ctx->tw.p, (double*)ctx->eta_d.p, (float*)ctx->eta_f.p);
+    } else if (P.nfreq <= 64) {
+      // short series: held in registers
+#define ETA_REG(NPM)                                                                                           \
+  KL(k_eta_reg<NPM>, dim3(grid_for(ntiles, 256, 4096)), dim3(256), 0, st, series, P.nfreq, ntiles, cfg.harm, \
+     (const double2*)ctx->tw.p, (double*)ctx->eta_d.p, (float*)ctx->eta_f.p)
+      if (P.nfreq <= 32)
+        ETA_REG(32);
+      else
+        ETA_REG(64);
+#undef ETA_REG
     } else {
       KL(k_eta, dim3(grid_for(ntiles, 256, 4096)), dim3(256), 0, st, series, P.nfreq, ntiles, cfg.harm,
          (const double2*)ctx->tw.p, (double*)ctx->eta_d.p, (float*)ctx->eta_f.p);

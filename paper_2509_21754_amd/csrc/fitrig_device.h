@@ -19,6 +19,7 @@
 #include <hip/hip_fp16.h>
 #include <math.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "fitrig.h"
 #include "fitrig_internal.h"
@@ -981,29 +982,46 @@ __global__ __launch_bounds__(64) void k_recompute(RecomputeArgs R) {
     const T* f0 = frame_ptr<T>(base, c0, c1, ncarry, plane, s);
     const T* f1 = frame_ptr<T>(base, c0, c1, ncarry, plane, s + 1);
     const T* f2 = frame_ptr<T>(base, c0, c1, ncarry, plane, s + 2);
-    for (int cc = lane; cc < ncols; cc += 64) {
-      const int col = cmin + cc;
-      float dl[NV], rl[NV];
+    // Vertical windows of row y, evaluated as output y - by of the 8-row
+    // block (the association k_stream uses for that row). With the row a
+    // compile-time index, the other outputs and the rows outside y's window
+    // are never computed or read.
+    auto column = [&](auto CY) {
+      constexpr int C = decltype(CY)::value;
+      for (int cc = lane; cc < ncols; cc += 64) {
+        const int col = cmin + cc;
+        float dl[NV], rl[NV];
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        const int yy = by - H + j;
-        float a = 0.0f, b = 0.0f, c = 0.0f;
-        if (col >= 0 && col < Wh && yy >= 0 && yy < Hh) {
-          const int64_t o = (int64_t)yy * Wh + col;
-          a = to_f<T>(f0[o]);
-          b = to_f<T>(f1[o]);
-          c = to_f<T>(f2[o]);
+        for (int j = 0; j < NV; ++j) {
+          const int yy = by - H + j;
+          float a = 0.0f, b = 0.0f, c = 0.0f;
+          if (col >= 0 && col < Wh && yy >= 0 && yy < Hh) {
+            const int64_t o = (int64_t)yy * Wh + col;
+            a = to_f<T>(f0[o]);
+            b = to_f<T>(f1[o]);
+            c = to_f<T>(f2[o]);
+          }
+          pix3<RS>(a, b, c, Cf, dl[j], rl[j]);
+          dl[j] = fabsf(dl[j]);
         }
-        pix3<RS>(a, b, c, Cf, dl[j], rl[j]);
-        dl[j] = fabsf(dl[j]);
+        float o8[8];
+        Win<H, 8, false>::run(dl, o8, nullptr);
+        sv[0][cc] = o8[C];
+        WinMax<H, 8>::run(dl, o8);
+        sv[1][cc] = o8[C];
+        Win<H, 8, false>::run(rl, o8, nullptr);
+        sv[2][cc] = o8[C];
       }
-      float o8[8];
-      Win<H, 8, false>::run(dl, o8, nullptr);
-      sv[0][cc] = o8[y - by];
-      WinMax<H, 8>::run(dl, o8);
-      sv[1][cc] = o8[y - by];
-      Win<H, 8, false>::run(rl, o8, nullptr);
-      sv[2][cc] = o8[y - by];
+    };
+    switch (y - by) {
+      case 0: column(std::integral_constant<int, 0>{}); break;
+      case 1: column(std::integral_constant<int, 1>{}); break;
+      case 2: column(std::integral_constant<int, 2>{}); break;
+      case 3: column(std::integral_constant<int, 3>{}); break;
+      case 4: column(std::integral_constant<int, 4>{}); break;
+      case 5: column(std::integral_constant<int, 5>{}); break;
+      case 6: column(std::integral_constant<int, 6>{}); break;
+      default: column(std::integral_constant<int, 7>{}); break;
     }
     __syncthreads();
     bool sel = false;

@@ -778,10 +778,21 @@ __global__ __launch_bounds__(256) void k_blk_count(const float* seg_max, const d
     if (seg_width(L, q.g) > 0 && !flags[q.s]) {
       const int y0 = q.yb * L.br, y1 = min(y0 + L.br, L.Ho);
       const float* p = seg_max + ((int64_t)q.s * L.Ho + y0) * L.nseg_row + q.g;
-      float m = p[0];
-      for (int y = y0 + 1; y < y1; ++y) {
-        p += L.nseg_row;
-        m = fmaxf(m, *p);
+      float m;
+      if (y1 - y0 == kBand) {
+        // a whole block: every row requested before the first is used
+        float v[kBand];
+#pragma unroll
+        for (int i = 0; i < kBand; ++i) v[i] = p[(int64_t)i * L.nseg_row];
+        m = v[0];
+#pragma unroll
+        for (int i = 1; i < kBand; ++i) m = fmaxf(m, v[i]);
+      } else {
+        m = p[0];
+        for (int y = y0 + 1; y < y1; ++y) {
+          p += L.nseg_row;
+          m = fmaxf(m, *p);
+        }
       }
       f = zsel(m, mu[q.s], sigma[q.s], tau);
     }
@@ -1256,6 +1267,64 @@ __global__ __launch_bounds__(256) void k_eta(const double* cube, int np, int64_t
           const double2 w = tw[ph];
           re = fma(v, w.x, re);
           im = fma(-v, w.y, im);
+          ph += kk;
+          if (ph >= np) ph -= np;
+        }
+        val += sqrt(re * re + im * im);
+      }
+      if (k == 1 || val > best) best = val;
+    }
+    if (K < 1) best = 0.0;
+    eta[t] = best;
+    if (eta_f) eta_f[t] = (float)best;
+  }
+}
+
+// Tile branch for series of at most NPMAX values: k_eta with the tile's
+// series read once into registers (k_eta reads it again for every
+// frequency). The twiddle index depends only on the loop counters: every lane
+// reads the same LDS word (a broadcast). Mean, mean removal and every sum are
+// k_eta's, in the same order, so eta is the same.
+template <int NPMAX>
+__global__ __launch_bounds__(256) void k_eta_reg(const double* cube, int np, int64_t ntiles, int harm,
+                                                 const double2* twg, double* eta, float* eta_f) {
+  __shared__ double2 tw[NPMAX];
+  for (int i = threadIdx.x; i < np; i += blockDim.x) tw[i] = twg[i];
+  __syncthreads();
+  const int K = np / 2;
+  const int jmax = harm == 0 ? 1 : harm;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+    double x[NPMAX];
+    const double* p = cube + t;
+#pragma unroll
+    for (int s = 0; s < NPMAX; ++s) {
+      // one running address; past the series it stays on the last value
+      // (read again, replaced by zero below), so every read is in range
+      asm volatile("" : "+v"(p));
+      x[s] = *p;
+      p += s + 1 < np ? ntiles : 0;
+    }
+    double mean = 0.0;
+#pragma unroll
+    for (int s = 0; s < NPMAX; ++s)
+      if (s < np) mean += x[s];
+    mean /= (double)np;
+    // the mean-removed series, zero past its end: the extra products of the
+    // sums below add exact zeros
+#pragma unroll
+    for (int s = 0; s < NPMAX; ++s) x[s] = s < np ? x[s] - mean : 0.0;
+    double best = 0.0;
+    for (int k = 1; k <= K; ++k) {
+      double val = 0.0;
+      for (int j = 1; j <= jmax && j * k <= K; ++j) {
+        const int kk = j * k;
+        double re = 0.0, im = 0.0;
+        int ph = 0;
+#pragma unroll
+        for (int s = 0; s < NPMAX; ++s) {
+          const double2 w = tw[ph];
+          re = fma(x[s], w.x, re);
+          im = fma(-x[s], w.y, im);
           ph += kk;
           if (ph >= np) ph -= np;
         }

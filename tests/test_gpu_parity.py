@@ -272,6 +272,23 @@ def test_tlisi_map_kind():
     np.testing.assert_allclose(qmap.cpu().numpy(), 1 - q / M**2, rtol=0, atol=2e-7)
 
 
+@pytest.mark.parametrize("w,dt", [(3, "f32"), (5, "f16"), (9, "f32"), (9, "bf16"), (13, "f32"), (17, "f32")])
+def test_recompute_matches_stream_bitwise(w, dt):
+    """The q of the selected segments, evaluated again for their cells, is the
+    streaming pass's q bit for bit (one arithmetic, Eqs. (3)-(6)): every
+    image candidate's peak q equals the q map at its peak cell. A low tau
+    gives peaks at every row position of the 8-row blocks, in ragged bands
+    and column groups."""
+    X = structured_stack(300 + w, 7, 200, 700)
+    cands, stats, q, eta, used, rc = run_gpu(X, 2.5, dtype=dt, window=w, branches=1)
+    assert rc == 0
+    img = [c for c in cands if c["branch"] == ref.IMAGE]
+    assert len(img) > 50
+    assert {c["peak_y"] % 8 for c in img} == set(range(8))
+    for c in img:
+        assert np.float32(c["peak_q"]) == q[c["triple"], c["peak_y"], c["peak_x"]], c
+
+
 def test_determinism_bitwise():
     X = structured_stack(81, 10, 120, 600)
     r1 = run_gpu(X, 3.0, window=9)
