@@ -1064,12 +1064,22 @@ __device__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
   }
 }
 
+// Each selected cell starts linked to the first cell of its run of selected
+// cells in the slot (the run's lowest slot, so every parent is at most its
+// cell and a root is its set's lowest slot): the horizontal unions inside a
+// slot are made here.
 __global__ void k_uf_init(const uint64_t* seg_mask, const int64_t* nsel_p, int64_t cap, int32_t* parent) {
   int64_t nsel = nsel_p[0];
   if (nsel > cap) nsel = cap;
   const int64_t ns = nsel * 64;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x)
-    parent[i] = ((seg_mask[i >> 6] >> (i & 63)) & 1ull) ? (int32_t)i : -1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t m = seg_mask[i >> 6];
+    const int off = (int)(i & 63);
+    // unselected cells before off; the run starts after the last of them
+    const uint64_t gap = ~m & ((1ull << off) - 1ull);
+    const int start = gap ? 64 - __clzll((long long)gap) : 0;
+    parent[i] = ((m >> off) & 1ull) ? (int32_t)((i & ~63ll) + start) : -1;
+  }
 }
 
 struct SlotMap {
@@ -1112,14 +1122,34 @@ __global__ void k_uf_union(SlotMap M, const uint64_t* seg_mask, const int64_t* s
   if (nsel > cap) nsel = cap;
   const int64_t ns = nsel * 64;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
-    if (!((seg_mask[i >> 6] >> (i & 63)) & 1ull)) continue;
+    const uint64_t m = seg_mask[i >> 6];
+    const int off = (int)(i & 63);
+    if (!((m >> off) & 1ull)) continue;
     int64_t set;
     int y, x;
     slot_pos(seg_entry, L, i, set, y, x);
-    const int dy[4] = {0, 1, 1, 1};
-    const int dx[4] = {1, -1, 0, 1};
-    for (int k = 0; k < 4; ++k) {
-      const int32_t nb = slot_at(M, seg_mask, L, set, y + dy[k], x + dx[k]);
+    // 8-connectivity from the upper cell of each pair. The right neighbour
+    // inside the slot is in the same run (linked at init); across the slot's
+    // last cell it is looked up. Below: the cell under x; the lower-left and
+    // lower-right cells only from the run's first and last cells (under any
+    // other cell of the run they are under its run neighbour).
+    const bool first = off == 0 || !((m >> (off - 1)) & 1ull);
+    const bool last = off == 63 || !((m >> (off + 1)) & 1ull);
+    const int g = seg_of_x(L, x);
+    if (off == seg_width(L, g) - 1) {
+      const int32_t nb = slot_at(M, seg_mask, L, set, y, x + 1);
+      if (nb >= 0) uf_union(parent, (int32_t)i, nb);
+    }
+    {
+      const int32_t nb = slot_at(M, seg_mask, L, set, y + 1, x);
+      if (nb >= 0) uf_union(parent, (int32_t)i, nb);
+    }
+    if (first) {
+      const int32_t nb = slot_at(M, seg_mask, L, set, y + 1, x - 1);
+      if (nb >= 0) uf_union(parent, (int32_t)i, nb);
+    }
+    if (last) {
+      const int32_t nb = slot_at(M, seg_mask, L, set, y + 1, x + 1);
       if (nb >= 0) uf_union(parent, (int32_t)i, nb);
     }
   }
@@ -1164,23 +1194,68 @@ __global__ void k_comp_accum(const uint64_t* seg_mask, const int64_t* seg_entry,
   int64_t nsel = nsel_p[0];
   if (nsel > cap) nsel = cap;
   const int64_t ns = nsel * 64;
+  // the stride and ns are multiples of 64 and blocks are whole waves: every
+  // wave holds the 64 cells of one slot (one row of one set) per iteration
+  const int lane = threadIdx.x & 63;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
-    if (!((seg_mask[i >> 6] >> (i & 63)) & 1ull)) continue;
-    const int32_t c = comp_of[parent[i]];
-    if (c < 0) continue;
+    bool act = (seg_mask[i >> 6] >> lane) & 1ull;
+    const int32_t c = act ? comp_of[parent[i]] : -1;
+    act = act && c >= 0;
+    const uint64_t am = __ballot(act);
+    if (!am) continue;
     int64_t set;
     int y, x;
     slot_pos(seg_entry, L, i, set, y, x);
-    const float q = cell_q[i];
+    const float q = act ? cell_q[i] : 0.0f;
     const double z = ((double)q - mu[set]) / sigma[set];
-    atomicAdd(npix + c, 1);
     const uint32_t lin = (uint32_t)((int64_t)y * L.Wo + x);
-    const unsigned long long k = ((unsigned long long)ord_key(q) << 32) | (unsigned long long)(0xFFFFFFFFu - lin);
+    const unsigned long long k =
+        act ? ((unsigned long long)ord_key(q) << 32) | (unsigned long long)(0xFFFFFFFFu - lin) : 0ull;
+    const unsigned long long wz = act ? (unsigned long long)llround(z * 1048576.0) : 0ull;
+    const unsigned long long wy = wz * (unsigned long long)y, wx = wz * (unsigned long long)x;
+    const int lead = __ffsll((unsigned long long)am) - 1;
+    const int32_t c0 = __shfl(c, lead);
+    if (__ballot(act && c != c0) == 0) {
+      // one component in the slot's row: integer totals of the wave (exact,
+      // so the same as per-cell atomics), added by one lane
+      unsigned long long km = k;
+      unsigned long long lo[3] = {wz, wy, wx}, hi[3] = {0ull, 0ull, 0ull};
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long ko = __shfl_xor(km, o);
+        km = ko > km ? ko : km;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const unsigned long long l2 = __shfl_xor(lo[j], o), h2 = __shfl_xor(hi[j], o);
+          const unsigned long long sl = lo[j] + l2;
+          hi[j] += h2 + (sl < l2 ? 1ull : 0ull);
+          lo[j] = sl;
+        }
+      }
+      if (lane == lead) {
+        atomicAdd(npix + c0, (int)__popcll(am));
+        atomicMax(key + c0, km);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          unsigned long long* p = w + c0 * 6 + 2 * j;
+          const unsigned long long old = atomicAdd(p, lo[j]);
+          const unsigned long long h = hi[j] + (old + lo[j] < old ? 1ull : 0ull);
+          if (h) atomicAdd(p + 1, h);
+        }
+        const int xs = x - lane;  // the slot's first cell
+        atomicMin(box + c0 * 4 + 0, y);
+        atomicMin(box + c0 * 4 + 1, xs + lead);
+        atomicMax(box + c0 * 4 + 2, y);
+        atomicMax(box + c0 * 4 + 3, xs + 63 - __clzll((long long)am));
+      }
+      continue;
+    }
+    if (!act) continue;
+    atomicAdd(npix + c, 1);
     atomicMax(key + c, k);
-    const unsigned long long wz = (unsigned long long)llround(z * 1048576.0);
     add128(w + c * 6 + 0, wz);
-    add128(w + c * 6 + 2, wz * (unsigned long long)y);
-    add128(w + c * 6 + 4, wz * (unsigned long long)x);
+    add128(w + c * 6 + 2, wy);
+    add128(w + c * 6 + 4, wx);
     atomicMin(box + c * 4 + 0, y);
     atomicMin(box + c * 4 + 1, x);
     atomicMax(box + c * 4 + 2, y);
