@@ -289,6 +289,35 @@ def test_recompute_matches_stream_bitwise(w, dt):
         assert np.float32(c["peak_q"]) == q[c["triple"], c["peak_y"], c["peak_x"]], c
 
 
+def test_components_across_slot_seams():
+    """8-connected components whose cells cross the 64-cell slot seams and
+    the column-group seams (window 3: groups of 254 cells), compared with
+    the oracle's labelling: diagonal lines both ways, a run along a row,
+    a U whose arms join below, and shapes meeting at one corner."""
+    rng = np.random.default_rng(404)
+    n, H, W = 6, 64, 700
+    X = rng.normal(size=(n, H, W))
+    img = np.zeros((H, W))
+    for x0 in (60, 124, 250, 315):
+        for t in range(12):
+            img[4 + t, x0 + t] = 40.0           # down-right diagonal over the seam
+            img[30 + t, x0 + 8 - t] = 40.0      # down-left diagonal over the seam
+        img[20, x0 - 6:x0 + 10] = 40.0          # run along a row over the seam
+        img[44:52, x0 - 2] = 40.0               # U: two arms ...
+        img[44:52, x0 + 6] = 40.0
+        img[52, x0 - 2:x0 + 7] = 40.0           # ... joined below
+    img[57:60, 61:64] = 40.0                     # two squares meeting at a corner
+    img[60:63, 64:67] = 40.0                     # on the seam at x = 64
+    X[3] += img
+    tau = 5.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, window=3, branches=1)
+    assert rc == 0
+    out = ref.detect(used, tau=tau, window=3, branches=ref.IMAGE)
+    check_maps(q, out["q"])
+    n_chk = check_candidates(cands, out, tau)
+    assert n_chk >= 12
+
+
 def test_determinism_bitwise():
     X = structured_stack(81, 10, 120, 600)
     r1 = run_gpu(X, 3.0, window=9)
