@@ -924,7 +924,9 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
       A.r_signed = cfg.r_signed;
       A.Cf = (float)cfg.C;
       A.qmap = qmap;
-      A.stat_part = (double*)ctx->stat_part.p;
+      // moment partials only when the call takes the mean/std spread of q
+      // (the map-free form always writes them)
+      A.stat_part = (qmap && !(P.img && !P.robust)) ? nullptr : (double*)ctx->stat_part.p;
       A.seg_max = (float*)ctx->seg_max.p;
       A.tile_part = byprod ? (double*)ctx->tile_part.p : nullptr;
       A.max_key = (uint32_t*)ctx->max_key.p;

@@ -553,18 +553,26 @@ struct Stream {
     // gives exactly zero variance
     double s1 = 0.0, s2 = 0.0;
     float gmax = -INFINITY;
+    // the map-writing form skips the moments when the call does not use them
+    // (robust spread): no partials buffer
+    const bool mom = !Q || A.stat_part != nullptr;
     if (interior) {
       // every chunk but the 16th is fully inside the image: no per-cell masks,
       // the idle chunk is dropped once per lane. The constant 1/n^2 is applied
       // after the reductions: q = p * inv with p = (S max) R, and rounding
       // p * inv is monotone, so max q = (max p) * inv exactly.
+      if (mom) {
 #pragma unroll
-      for (int c = 0; c < NT; ++c) {
-        const float pq = pv[c];
-        const double pd = (double)pq;
-        s1 += pd;
-        s2 = fma(pd, pd, s2);
-        gmax = fmaxf(gmax, pq);
+        for (int c = 0; c < NT; ++c) {
+          const float pq = pv[c];
+          const double pd = (double)pq;
+          s1 += pd;
+          s2 = fma(pd, pd, s2);
+          gmax = fmaxf(gmax, pq);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < NT; ++c) gmax = fmaxf(gmax, pv[c]);
       }
       const double id = (double)inv_full;
       s1 *= id;
@@ -612,12 +620,14 @@ struct Stream {
           if (c < qn) dst[c] = qv[c];
       }
     }
-    const double a1 = row_sum_f64(s1);
-    const double a2 = row_sum_f64(s2);
-    if ((lane & 15) == 15) {
-      double* sp = A.stat_part + ((int64_t)s * gridDim.x + bid) * 32 + stat_lane;
-      sp[0] = a1;
-      sp[1] = a2;
+    if (mom) {
+      const double a1 = row_sum_f64(s1);
+      const double a2 = row_sum_f64(s2);
+      if ((lane & 15) == 15) {
+        double* sp = A.stat_part + ((int64_t)s * gridDim.x + bid) * 32 + stat_lane;
+        sp[0] = a1;
+        sp[1] = a2;
+      }
     }
     if (A.tile_part) {
       // job = (quantity qd, piece p) on 8 lanes; lane sub sums columns

@@ -47,7 +47,7 @@ struct StreamArgs {
   int32_t r_signed;
   float Cf;
   float* qmap;           // nullable [n-2][H][W]
-  double* stat_part;     // [n-2][nwg][2]  (sum q, sum q^2)
+  double* stat_part;     // [n-2][nwg][2]  (sum q, sum q^2); nullable when qmap is set
   float* seg_max;        // [n-2][H][ncol*4]
   double* tile_part;     // nullable [n-2][nbands][ncol][kPieces][3]
   uint32_t* max_key;     // order-preserving key of the stack maximum (atomic max)
