@@ -522,7 +522,7 @@ void sample_bracket(fitrig_ctx* ctx, hipStream_t st, const uint32_t* samp, int n
 // sets not on it. Same keys, same order statistics on every path.
 // nonneg: every value is +0 or positive (q with |x_hat| in Eq. (4), eta).
 fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, int nsets, int64_t per_set,
-                            bool nonneg, double* mu, double* sigma, uint32_t* flags) {
+                            bool nonneg, double* mu, double* sigma, uint32_t* flags, int64_t pre_S = 0) {
   fitrig_status rc;
   if ((rc = ensure(ctx, ctx->hist, (size_t)nsets * kHistBins * 4)) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->rs_state, (size_t)nsets * sizeof(RsState))) != FITRIG_OK) return rc;
@@ -539,7 +539,7 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
     KL(k_rs_finish, g1d, dim3(64), 0, st, (const double*)med_out, (const double*)dev_out, nsets, mu, sigma, flags,
        mode);
   };
-  constexpr int64_t kSample = 1 << 20;
+  constexpr int64_t kSample = kRsSample;
   if (per_set < 8 * kSample) {
     for (int mode = 0; mode < 2; ++mode) {
       if ((rc = rs_select_middle(ctx, st, vals, nsets, per_set, mode, mode, mu, nullptr, nullptr, r_lo, r_hi, per_set,
@@ -551,7 +551,10 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
     return FITRIG_OK;
   }
 
-  const int64_t S = kSample;
+  // pre_S > 0: the sample (pre_S order keys per set, at least 2^20 and below
+  // 2^21) is already in rs_samp, written by the index pass on a grid of cells
+  // 16 or more apart; otherwise 2^20 hashed positions are read from the values
+  const int64_t S = pre_S > 0 ? pre_S : kSample;
   // sample i is value (i * mult) mod per_set: an odd multiplier near
   // per_set * (golden ratio - 1), made coprime to per_set
   uint64_t mult = (uint64_t)((double)per_set * 0.6180339887498949) | 1u;
@@ -592,8 +595,9 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
   const dim3 gs(grid_for(S, 256, 1024), nsets);
 
   // brackets from the sample: median keys, then the MAD window around its midpoint
-  KL(k_rs_sample, gs, dim3(256), 0, st, vals, per_set, 0, (const double*)nullptr, S, mult, samp,
-     (const uint32_t*)nullptr, 0u);
+  if (pre_S <= 0)
+    KL(k_rs_sample, gs, dim3(256), 0, st, vals, per_set, 0, (const double*)nullptr, S, mult, samp,
+       (const uint32_t*)nullptr, 0u);
   sample_bracket(ctx, st, samp, nsets, S, a, b, bkt0, nullptr, 0u);
   KL(k_rs_mad_center, g1d, dim3(64), 0, st, (const uint32_t*)bkt0, nsets, pl, mhat);
   KL(k_rs_sample_dev, gs, dim3(256), 0, st, samp, S, (const double*)mhat, (const uint32_t*)nullptr, 0u);
@@ -907,6 +911,24 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
       if ((rc = ensure(ctx, ctx->qscratch, (size_t)np * plane * 4)) != FITRIG_OK) return rc;
       qmap = (float*)ctx->qscratch.p;
     }
+    // robust spread of a large q map: the index pass writes its bracket
+    // sample, q at the first cell of every 16-cell chunk of the first row of
+    // every bstride-th band (cells 16 or more apart, so the windows of
+    // sampled cells do not overlap), with bstride set for 2^20 to 2^21 samples
+    // per triple; smaller maps keep the hashed sample of the map
+    int64_t pre_S = 0;
+    int samp_bstride = 1, samp_cpg = 0, samp_nch = 0;
+    if (P.img && P.robust && plane >= 8 * (int64_t)kRsSample) {
+      samp_cpg = (out_w + 15) / 16;
+      const int last_w = c.W - (ncol - 1) * out_w;
+      samp_nch = samp_cpg * (ncol - 1) + std::min(samp_cpg, (last_w + 15) / 16);
+      const int64_t grid = (int64_t)nbands * samp_nch;
+      if (grid >= kRsSample) {
+        samp_bstride = (int)std::max<int64_t>(1, grid / kRsSample);
+        pre_S = (int64_t)((nbands + samp_bstride - 1) / samp_bstride) * samp_nch;
+        if ((rc = ensure(ctx, ctx->rs_samp, (size_t)np * pre_S * 4)) != FITRIG_OK) return rc;
+      }
+    }
     if (!ctx->sizing) {
       StreamArgs A;
       A.cd = cd;
@@ -930,6 +952,18 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
       A.seg_max = (float*)ctx->seg_max.p;
       A.tile_part = byprod ? (double*)ctx->tile_part.p : nullptr;
       A.max_key = (uint32_t*)ctx->max_key.p;
+      A.qsamp = nullptr;
+      A.samp_S = 0;
+      A.samp_bstride = 1;
+      A.samp_cpg = 0;
+      A.samp_nch = 0;
+      if (pre_S > 0) {
+        A.qsamp = (uint32_t*)ctx->rs_samp.p;
+        A.samp_S = pre_S;
+        A.samp_bstride = samp_bstride;
+        A.samp_cpg = samp_cpg;
+        A.samp_nch = samp_nch;
+      }
       if (!dispatch_stream(ctx, c.dtype, halo, cfg.r_signed != 0, dim3((unsigned)nwg), st, A)) return FITRIG_E_INVAL;
     }
     LAUNCH_CHECK(ctx);
@@ -949,7 +983,8 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
           FITRIG_OK)
         return rc;
     } else if (P.img) {
-      if ((rc = robust_spread(ctx, st, qmap, np, plane, !cfg.r_signed, mu, sigma, flags)) != FITRIG_OK) return rc;
+      if ((rc = robust_spread(ctx, st, qmap, np, plane, !cfg.r_signed, mu, sigma, flags, pre_S)) != FITRIG_OK)
+        return rc;
     }
   }
 

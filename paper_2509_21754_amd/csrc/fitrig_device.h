@@ -414,6 +414,7 @@ struct Stream {
   // triple adds a uniform base): segment maxima, q map, moment partials,
   // tile pieces
   uint32_t seg_lane, q_lane;
+  uint32_t samp_lane;  // the lane's slot in the q sample, or ~0u
   int stat_lane, tile_lane;
   bool qvec;  // the lane's q-map chunk is whole and 16-byte aligned in every triple
   int qn;     // q-map cells of the lane's chunk inside the row
@@ -620,6 +621,7 @@ struct Stream {
           if (c < qn) dst[c] = qv[c];
       }
     }
+    if (Q && samp_lane != ~0u) A.qsamp[(int64_t)s * A.samp_S + samp_lane] = ord_key(qv[0]);
     if (mom) {
       const double a1 = row_sum_f64(s1);
       const double a2 = row_sum_f64(s2);
@@ -690,6 +692,10 @@ __global__ __launch_bounds__(kLanes) void k_stream(StreamArgs A) {
     // H W is a multiple of 4
     st.qn = max(0, min(S::NT, A.W - (st.x0 + S::NT * ch)));
     st.qvec = Q && st.qn == S::NT && A.plane % 4 == 0 && st.q_lane % 4 == 0 && ((uintptr_t)A.qmap & 15) == 0;
+    st.samp_lane = ~0u;
+    if (Q && A.qsamp && r == 0 && st.band % A.samp_bstride == 0 && S::NT * ch < A.out_w &&
+        st.x0 + S::NT * ch < A.W)
+      st.samp_lane = (uint32_t)((st.band / A.samp_bstride) * A.samp_nch + st.grp * A.samp_cpg + ch);
     st.stat_lane = (st.lane >> 4) * 2;
     st.tile_lane = ((st.band * A.ncol + st.grp) * kPieces + p) * 3 + qd;
   }

@@ -11,6 +11,7 @@ namespace fitrig {
 constexpr int kBand = 16;
 constexpr int kLanes = 256;
 constexpr int kSegsPerGroup = 4;
+constexpr int64_t kRsSample = 1 << 20;  // bracket sample of the robust spread (values per set)
 constexpr int kMaxHalo = 8;          // window <= 17
 constexpr int kPieces = 9;           // 32-wide tile pieces a column group can touch
 constexpr int kHistBins = 2048;      // radix-select digit bins (11 bits)
@@ -51,6 +52,13 @@ struct StreamArgs {
   float* seg_max;        // [n-2][H][ncol*4]
   double* tile_part;     // nullable [n-2][nbands][ncol][kPieces][3]
   uint32_t* max_key;     // order-preserving key of the stack maximum (atomic max)
+  // nullable (map-writing form only): order keys of q on a sample grid, the
+  // first cell of every 16-cell chunk in the first row of every samp_bstride-th
+  // band, [n-2][samp_S] (index: band / samp_bstride * samp_nch + group *
+  // samp_cpg + chunk)
+  uint32_t* qsamp;
+  int64_t samp_S;
+  int32_t samp_bstride, samp_cpg, samp_nch;
 };
 
 // Generic tile-mode kernel arguments (re-reads the three frames of a triple).

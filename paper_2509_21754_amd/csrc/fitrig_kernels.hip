@@ -278,7 +278,7 @@ __global__ void k_rs_sample(const float* vals, int64_t per_set, int mode, const 
   if (gated_off(gate, s, want)) return;
   const double m = mode == 1 ? med[s] : 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x) {
-    // i < 2^20 and mult < per_set < 2^32: the product fits in 64 bits
+    // i < 2^21 and mult < per_set < 2^32: the product fits in 64 bits
     const uint64_t pos = ((uint64_t)i * mult) % (uint64_t)per_set;
     samp[(int64_t)s * S + i] = rs_key(vals[(int64_t)s * per_set + (int64_t)pos], mode, m);
   }
