@@ -69,3 +69,17 @@ def test_median_mad_grid_sample_strided_ragged():
     stack = torch.randn((3, H, W), generator=g, device="cuda", dtype=torch.float32) + 3.0
     stack[1, 1000:1040, 5000:5040] += 25.0
     run_mad(stack, 5, 8.0, [0])
+
+
+def test_median_mad_grid_sample_defeated():
+    """Window 1 (q is pointwise): a pulse on every cell of the sample grid
+    (rows and columns that are multiples of 16) makes every sampled q an
+    outlier, so the brackets from the sample miss the middle ranks and the
+    fallback selections run; the result must still be the exact order
+    statistics. (tau is far above every z: only the spread is checked.)"""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(91)
+    H = W = 16384
+    stack = torch.randn((3, H, W), generator=g, device="cuda", dtype=torch.float32) + 3.0
+    stack[1, ::16, ::16] += 50.0
+    run_mad(stack, 1, 1e9, [0])
