@@ -456,7 +456,7 @@ fitrig_status moments(fitrig_ctx* ctx, hipStream_t st, const double* src, int ns
 fitrig_status rs_select_middle(fitrig_ctx* ctx, hipStream_t st, const float* vals, int nsets, int64_t per_set,
                                int kmode, int vmode, const double* med, const unsigned long long* nvalid,
                                const unsigned long long* base, int64_t rank_lo, int64_t rank_hi, int64_t n_max,
-                               double* out, const uint32_t* gate, uint32_t want) {
+                               double* out, const uint32_t* gate, uint32_t want, const uint32_t* kb = nullptr) {
   uint32_t* hist = (uint32_t*)ctx->hist.p;
   RsState* rs = (RsState*)ctx->rs_state.p;
   unsigned long long* cnt_le = (unsigned long long*)ctx->rs_next.p;
@@ -466,7 +466,7 @@ fitrig_status rs_select_middle(fitrig_ctx* ctx, hipStream_t st, const float* val
   const int gx = grid_for(n_max, 1 << 13, 1024);
   const dim3 g1((nsets + 63) / 64);
   if (base)
-    KL(k_rs_init_gathered, g1, dim3(64), 0, st, rs, nsets, rank_lo, base, gate, want);
+    KL(k_rs_init_gathered, g1, dim3(64), 0, st, rs, nsets, rank_lo, base, kb, gate, want);
   else
     KL(k_rs_init_rank, g1, dim3(64), 0, st, rs, nsets, rank_lo, gate, want);
   for (int p = 0; p < 3; ++p) {
@@ -572,7 +572,7 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
   const bool vec = per_set % 4 == 0 && ((uintptr_t)vals & 15) == 0;
   if ((rc = ensure(ctx, ctx->rs_samp, (size_t)nsets * S * 4)) != FITRIG_OK ||
       (rc = ensure(ctx, ctx->rs_gbuf, (size_t)nsets * (cap0 + cap1) * 4)) != FITRIG_OK ||
-      (rc = ensure(ctx, ctx->rs_bkt, (size_t)nsets * 8 * 4)) != FITRIG_OK ||
+      (rc = ensure(ctx, ctx->rs_bkt, (size_t)nsets * 10 * 4)) != FITRIG_OK ||
       (rc = ensure(ctx, ctx->rs_cnt, (size_t)nsets * 4 * 8)) != FITRIG_OK ||
       (rc = ensure(ctx, ctx->rs_nvalid, (size_t)nsets * 2 * 8)) != FITRIG_OK ||
       (rc = ensure(ctx, ctx->rs_plan, (size_t)nsets * 5 * 8)) != FITRIG_OK ||
@@ -582,6 +582,7 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
   uint32_t* bkt0 = (uint32_t*)ctx->rs_bkt.p;
   uint32_t* bkt1 = bkt0 + 2 * nsets;
   uint32_t* wk = bkt0 + 4 * nsets;
+  uint32_t* dkb = bkt0 + 8 * nsets;  // bounds of the MAD window's keys
   unsigned long long* cnt0 = (unsigned long long*)ctx->rs_cnt.p;
   unsigned long long* cnt1 = cnt0 + 2 * nsets;
   unsigned long long* nv0 = (unsigned long long*)ctx->rs_nvalid.p;
@@ -625,15 +626,17 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
      kPathGathered, kPathFallback, nv1);
   // median: inside the bracket (rank offsets at cnt0[2 s]), or over the whole set
   if ((rc = rs_select_middle(ctx, st, (const float*)g0, nsets, cap0, 2, 0, mu, nv0, cnt0, r_lo, r_hi, cap0, med_out,
-                             gate_med, kPathGathered)) != FITRIG_OK ||
+                             gate_med, kPathGathered, bkt0)) != FITRIG_OK ||
       (rc = rs_select_middle(ctx, st, vals, nsets, per_set, 0, 0, mu, nullptr, nullptr, r_lo, r_hi, per_set, med_out,
                              gate_med, kPathFull)) != FITRIG_OK)
     return rc;
   finish(0);
   // MAD inside the window (g1 holds the values q: keys |q - med| are formed
   // as the passes read them), then verified against the exact median
+  KL(k_rs_mad_keybounds, g1d, dim3(64), 0, st, (const double*)pl, (const double*)mu, (const uint32_t*)wk, nsets,
+     (const uint32_t*)gate_mad, kPathGathered, dkb);
   if ((rc = rs_select_middle(ctx, st, (const float*)g1, nsets, cap1, 1, 1, mu, nv1, cnt1, r_lo, r_hi, cap1, dev_out,
-                             gate_mad, kPathGathered)) != FITRIG_OK)
+                             gate_mad, kPathGathered, dkb)) != FITRIG_OK)
     return rc;
   KL(k_rs_mad_verify, g1d, dim3(64), 0, st, (const double*)pl, (const double*)mu, (const double*)dev_out,
      (const unsigned long long*)cnt1, nsets, gate_mad);
@@ -652,7 +655,7 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
   KL(k_rs_plan, g1d, dim3(64), 0, st, (const unsigned long long*)cnt1, nsets, cap1, r_lo, r_hi, gate_mad,
      kPathFallback, kPathFallback, kPathFull, nv1);
   if ((rc = rs_select_middle(ctx, st, (const float*)g1, nsets, cap1, 2, 1, mu, nv1, cnt1, r_lo, r_hi, cap1, dev_out,
-                             gate_mad, kPathFallback)) != FITRIG_OK ||
+                             gate_mad, kPathFallback, bkt1)) != FITRIG_OK ||
       (rc = rs_select_middle(ctx, st, vals, nsets, per_set, 1, 1, mu, nullptr, nullptr, r_lo, r_hi, per_set, dev_out,
                              gate_mad, kPathFull)) != FITRIG_OK)
     return rc;

@@ -166,10 +166,11 @@ __global__ __launch_bounds__(256) void k_rs_hist(const float* vals, int64_t per_
   __shared__ uint32_t h[kHistBins];
   const int s = blockIdx.y;
   if (gated_off(gate, s, want)) return;
-  for (int i = threadIdx.x; i < kHistBins; i += 256) h[i] = 0;
-  __syncthreads();
   const RsState S = st[s];
   const uint32_t dmask = (1u << nbits) - 1u;
+  if (((S.known >> shift) & dmask) == dmask) return;  // digit known from the start
+  for (int i = threadIdx.x; i < kHistBins; i += 256) h[i] = 0;
+  __syncthreads();
   const float* v = vals + (int64_t)s * per_set;
   const double m = mode == 1 ? med[s] : 0.0;
   const int64_t n = nvalid ? min((int64_t)nvalid[s], per_set) : per_set;
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(256) void k_rs_pick(RsState* st, uint32_t* hist, in
   const int s = blockIdx.x, t = threadIdx.x;
   if (gated_off(gate, s, want)) return;
   const RsState S = st[s];
+  if (((S.known >> shift) & ((1u << nbits) - 1u)) == ((1u << nbits) - 1u)) return;  // known from the start
   uint32_t* h = hist + (int64_t)s * kHistBins;
   const int nb = 1 << nbits, per = nb / 256;
   uint32_t c[kHistBins / 256];
@@ -258,15 +260,50 @@ __global__ void k_rs_init_rank(RsState* st, int nsets, int64_t rank, const uint3
 }
 
 // Rank within the gathered keys: global rank minus the keys below them.
+// kb (nullable): bounds kb[2 s] <= key <= kb[2 s + 1] of every gathered key;
+// the digits (11, 11, 10 bits from the top) inside the common leading bits
+// of the two bounds are the same in every gathered key, so they start known
+// (their passes are skipped).
 __global__ void k_rs_init_gathered(RsState* st, int nsets, int64_t rank, const unsigned long long* cnt,
-                                   const uint32_t* gate, uint32_t want) {
+                                   const uint32_t* kb, const uint32_t* gate, uint32_t want) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsets || gated_off(gate, s, want)) return;
   RsState S;
   S.prefix = 0;
   S.known = 0;
+  if (kb && kb[2 * s] <= kb[2 * s + 1]) {
+    const uint32_t d = kb[2 * s] ^ kb[2 * s + 1];
+    const int common = d ? __clz((int)d) : 32;
+    uint32_t known = 0;
+    if (common >= 11) known |= 0xFFE00000u;
+    if (common >= 22) known |= 0x001FFC00u;
+    if (common >= 32) known = 0xFFFFFFFFu;
+    S.known = known;
+    S.prefix = kb[2 * s] & known;
+  }
   S.rank = rank - (int64_t)cnt[2 * s];
   st[s] = S;
+}
+
+// Bounds of the MAD keys bits((float)|q - med|) of the cells gathered in the
+// MAD window (k_rs_mad_window: |q - mhat| at most t_out, and at least t_in
+// when the window has inner cells, kB != kC, up to the FP32 rounding of the
+// window's bounds) once the median med is exact: |q - med| is within
+// e = |med - mhat| of |q - mhat|. The bounds are widened by 2^-20 of
+// |mhat| + t_out + e, far beyond every rounding involved.
+__global__ void k_rs_mad_keybounds(const double* pl, const double* med, const uint32_t* wk, int nsets,
+                                   const uint32_t* gate, uint32_t want, uint32_t* kb) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsets || gated_off(gate, s, want)) return;
+  const double mh = pl[4 * s + 0], t_in = pl[4 * s + 2], t_out = pl[4 * s + 3];
+  const bool inner = wk[4 * s + 1] != wk[4 * s + 2];
+  const double e = fabs(med[s] - mh);
+  const double slack = (fabs(mh) + fabs(t_out) + e) * 0x1p-20;
+  const double lo = (inner && t_in > 0.0) ? fmax(0.0, t_in - e - slack) : 0.0;
+  const double hi = t_out + e + slack;
+  const bool ok = isfinite(lo) && isfinite(hi) && hi >= lo;
+  kb[2 * s] = ok ? __float_as_uint(__double2float_rd(lo)) : 1u;
+  kb[2 * s + 1] = ok ? __float_as_uint(__double2float_ru(hi)) : 0u;  // lo > hi: no seed
 }
 
 // Keys of a sample of each set: sample i is value (i * mult) mod per_set
