@@ -529,14 +529,17 @@ __global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t p
   };
   constexpr int PT = kGather2PT;
   static_assert(PT % 4 == 0 && PT <= 16, "two selection bits per value in 32 bits; 16-bit round counts");
+  // Every read is in range and unconditional: past the end the address is
+  // clamped to the set's last values, which the ok flags below ignore. (A
+  // per-lane condition on the read would put the round's prefetch behind a
+  // branch, and the wait for the current round would then also wait for it.)
   auto fetch = [&](int64_t base, float (&q)[PT]) {
     if (VEC) {
 #pragma unroll
       for (int j = 0; j < PT / 4; ++j) {
-        const int64_t i = base + 4 * ((int64_t)j * 256 + threadIdx.x);  // per_set % 4 == 0
+        const int64_t i = min(base + 4 * ((int64_t)j * 256 + threadIdx.x), per_set - 4);  // per_set % 4 == 0
         // read once: non-temporal
-        const fitrig_v4f x = i < per_set ? __builtin_nontemporal_load(reinterpret_cast<const fitrig_v4f*>(v + i))
-                                         : fitrig_v4f{0.f, 0.f, 0.f, 0.f};
+        const fitrig_v4f x = __builtin_nontemporal_load(reinterpret_cast<const fitrig_v4f*>(v + i));
         q[4 * j + 0] = x.x;
         q[4 * j + 1] = x.y;
         q[4 * j + 2] = x.z;
@@ -544,21 +547,14 @@ __global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t p
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < PT; ++j) {
-        const int64_t i = base + (int64_t)j * 256 + threadIdx.x;
-        q[j] = i < per_set ? v[i] : 0.0f;
-      }
+      for (int j = 0; j < PT; ++j) q[j] = v[min(base + (int64_t)j * 256 + threadIdx.x, per_set - 1)];
     }
   };
   auto index_of = [&](int64_t base, int j) -> int64_t {
     return VEC ? base + 4 * ((int64_t)(j >> 2) * 256 + threadIdx.x) + (j & 3) : base + (int64_t)j * 256 + threadIdx.x;
   };
-  float q[PT];
-  int64_t base = blockIdx.x * (int64_t)kGather2Round;
-  if (base < per_set) fetch(base, q);
-  for (; base < per_set; base += step) {
-    float nq[PT];
-    if (base + step < per_set) fetch(base + step, nq);
+  // one round: place this round's values (q, read one round earlier)
+  auto round = [&](const float (&q)[PT], int64_t base) {
     uint32_t k[PT];
     uint32_t sel = 0;  // bit j: median bracket, bit PT + j: MAD window
 #pragma unroll
@@ -601,8 +597,24 @@ __global__ __launch_bounds__(256) void k_rs_gather2(const float* vals, int64_t p
     nst0 += tot0;
     nst1 += tot1;
     __syncthreads();  // stages written and wsum read by every thread
-#pragma unroll
-    for (int j = 0; j < PT; ++j) q[j] = nq[j];
+  };
+  // Two buffers in turn (no register copies between rounds): the next
+  // round's reads are issued, a scheduling barrier keeps this round's work
+  // after them, then the round is placed. Past the last round the reads are
+  // clamped and unused. Every thread runs the same rounds.
+  float qa[PT], qb[PT];
+  int64_t base = blockIdx.x * (int64_t)kGather2Round;
+  if (base < per_set) fetch(base, qa);
+  while (base < per_set) {
+    fetch(base + step, qb);
+    __builtin_amdgcn_sched_barrier(0);
+    round(qa, base);
+    base += step;
+    if (base >= per_set) break;
+    fetch(base + step, qa);
+    __builtin_amdgcn_sched_barrier(0);
+    round(qb, base);
+    base += step;
   }
   if (nst0) flush(0, nst0);
   if (nst1) flush(1, nst1);
