@@ -1341,8 +1341,8 @@ uint32_t branches_ran(const fitrig_config& cfg, const Call& c) {
 
 fitrig_status check_shape(const fitrig_config& cfg, const Call& c) {
   const size_t bpp = c.dtype == FITRIG_F32 ? 4 : 2;
-  // the streaming kernel addresses a workgroup's rows through one buffer
-  // descriptor of 2^30 bytes starting at its first row
+  // the streaming kernels address a workgroup's rows (at most 32) through one
+  // buffer descriptor of 2^30 bytes starting at its first row
   if ((uint64_t)c.W * bpp * (uint64_t)(kBand + 2 * kMaxHalo + 1) >= (1ull << 30)) return FITRIG_E_INVAL;
   const Plan P = make_plan(cfg, c);
   // per-pixel spectra: the twiddle table (and, for harmonic sums, the

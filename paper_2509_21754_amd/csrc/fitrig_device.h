@@ -827,16 +827,33 @@ __global__ __launch_bounds__(kLanes) void k_tile_stream(TileStreamArgs A) {
   const int x = chunk * kLanes + lane;
   const bool cv = x < A.W;
   const int y0 = band * ROWS;
-  float P[ROWS], X0[ROWS];  // frames k-1, k-2
   int mxi = INT32_MIN;
   const void *fb = A.cd->base, *fc0 = A.cd->carry0, *fc1 = A.cd->carry1;
-#pragma unroll
-  for (int i = 0; i < ROWS; ++i) {
-    P[i] = 0.0f;
-    X0[i] = 0.0f;
-  }
-  for (int k = 0; k < A.n; ++k) {
+  // reads are unconditional: one buffer descriptor per frame from the band's
+  // first row (32 rows fit its 2^30 bytes for every accepted width), columns
+  // past the image masked to zero by the descriptor, rows past the last one
+  // read that row again (a running scalar offset that stops there); the terms
+  // of cells outside the image are zeroed where they are used, and a repeated
+  // pixel leaves the maximum alone
+  const int voff = cv ? lane * (int)sizeof(T) : kOffMasked;
+  const int last = A.H - 1 - y0;  // last in-image row of the band (relative)
+  auto load = [&](int k, float* dst) {
     const T* fr = frame_ptr<T>(fb, fc0, fc1, A.ncarry, A.plane, k);
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(fr + (int64_t)y0 * A.W + (int64_t)chunk * kLanes), (short)0, kRecords, kRsrcWord3);
+    int pitch = A.W * (int)sizeof(T);
+    asm volatile("" : "+s"(pitch));
+    int so = 0;
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      dst[i] = buf_ld<T>(r, voff, so);
+      so += i < last ? pitch : 0;
+    }
+  };
+  // frames k-2, k-1, k in X0, P, C; the next frame is read into N while this
+  // one is reduced (the four arrays rotate between calls)
+  auto step = [&](int k, const float* X0, const float* P, const float* C, float* N) {
+    load(k + 1 < A.n ? k + 1 : k, N);
     float sd[TPB], md[TPB], sr[TPB];
 #pragma unroll
     for (int t = 0; t < TPB; ++t) {
@@ -844,31 +861,20 @@ __global__ __launch_bounds__(kLanes) void k_tile_stream(TileStreamArgs A) {
       md[t] = 0.0f;
       sr[t] = 0.0f;
     }
-    // all rows of the frame are requested before any is used
-    float C[ROWS];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) mxi = max(mxi, __float_as_int(C[i]));
+    if (k < 2) return;
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
-      const int y = y0 + i;
-      C[i] = (cv && y < A.H) ? to_f<T>(fr[(int64_t)y * A.W + x]) : 0.0f;
+      const bool in = cv && y0 + i < A.H;
+      float dl, rl;
+      pix3<RS>(X0[i], P[i], C[i], A.Cf, dl, rl);
+      dl = in ? fabsf(dl) : 0.0f;
+      rl = in ? rl : 0.0f;
+      sd[i / TILE] += dl;
+      md[i / TILE] = fmaxf(md[i / TILE], dl);
+      sr[i / TILE] += rl;
     }
-#pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-      const int y = y0 + i;
-      const bool in = cv && y < A.H;
-      const float c = C[i];
-      mxi = max(mxi, __float_as_int(c));
-      if (k >= 2 && in) {
-        float dl, rl;
-        pix3<RS>(X0[i], P[i], c, A.Cf, dl, rl);
-        dl = fabsf(dl);
-        sd[i / TILE] += dl;
-        md[i / TILE] = fmaxf(md[i / TILE], dl);
-        sr[i / TILE] += rl;
-      }
-      X0[i] = P[i];
-      P[i] = c;
-    }
-    if (k < 2) continue;
     const int s = k - 2;
     if constexpr (TILE >= 16) {
       // few tiles per chunk: the TILE lanes of a tile combine their columns
@@ -928,6 +934,19 @@ __global__ __launch_bounds__(kLanes) void k_tile_stream(TileStreamArgs A) {
         A.cube_f[o] = (float)v;
       }
     }
+  };
+  float F0[ROWS], F1[ROWS], F2[ROWS], F3[ROWS];
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    F2[i] = 0.0f;
+    F3[i] = 0.0f;
+  }
+  load(0, F0);
+  for (int k = 0; k < A.n; k += 4) {
+    step(k, F2, F3, F0, F1);
+    if (k + 1 < A.n) step(k + 1, F3, F0, F1, F2);
+    if (k + 2 < A.n) step(k + 2, F0, F1, F2, F3);
+    if (k + 3 < A.n) step(k + 3, F1, F2, F3, F0);
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) mxi = max(mxi, __shfl_xor(mxi, off));
