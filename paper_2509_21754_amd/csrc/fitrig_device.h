@@ -45,6 +45,23 @@ __device__ __forceinline__ float to_f<bf16_t>(bf16_t v) {
   return __uint_as_float(((uint32_t)v.v) << 16);
 }
 
+// p[o] widened to FP32, read through a global-address pointer (vector
+// memory only, no LDS counter)
+template <typename T>
+__device__ __forceinline__ float ldg_f(const T* p, int64_t o);
+template <>
+__device__ __forceinline__ float ldg_f<float>(const float* p, int64_t o) {
+  return ((__attribute__((address_space(1))) const float*)p)[o];
+}
+template <>
+__device__ __forceinline__ float ldg_f<__half>(const __half* p, int64_t o) {
+  return __half2float(__ushort_as_half(((__attribute__((address_space(1))) const unsigned short*)p)[o]));
+}
+template <>
+__device__ __forceinline__ float ldg_f<bf16_t>(const bf16_t* p, int64_t o) {
+  return __uint_as_float(((uint32_t)((__attribute__((address_space(1))) const uint16_t*)p)[o]) << 16);
+}
+
 template <typename T>
 __device__ __forceinline__ const T* frame_ptr(const void* base, const void* c0, const void* c1,
                                               int ncarry, int64_t plane, int k) {
@@ -1021,22 +1038,30 @@ __global__ __launch_bounds__(64) void k_recompute(RecomputeArgs R) {
     // block (the association k_stream uses for that row). With the row a
     // compile-time index, the other outputs and the rows outside y's window
     // are never computed or read.
+    // Reads are unconditional (indices clamped into the image) and out-of-image
+    // pixels are zeroed after all of a column's reads are issued, so the reads
+    // of the window's rows are in flight together.
     auto column = [&](auto CY) {
       constexpr int C = decltype(CY)::value;
       for (int cc = lane; cc < ncols; cc += 64) {
         const int col = cmin + cc;
+        const bool colok = col >= 0 && col < Wh;
+        const int colc = min(max(col, 0), Wh - 1);
+        float ra[NV], rb[NV], rc[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          const int yc = min(max(by - H + j, 0), Hh - 1);
+          const int64_t o = (int64_t)yc * Wh + colc;
+          ra[j] = ldg_f<T>(f0, o);
+          rb[j] = ldg_f<T>(f1, o);
+          rc[j] = ldg_f<T>(f2, o);
+        }
         float dl[NV], rl[NV];
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
           const int yy = by - H + j;
-          float a = 0.0f, b = 0.0f, c = 0.0f;
-          if (col >= 0 && col < Wh && yy >= 0 && yy < Hh) {
-            const int64_t o = (int64_t)yy * Wh + col;
-            a = to_f<T>(f0[o]);
-            b = to_f<T>(f1[o]);
-            c = to_f<T>(f2[o]);
-          }
-          pix3<RS>(a, b, c, Cf, dl[j], rl[j]);
+          const bool ok = colok && yy >= 0 && yy < Hh;
+          pix3<RS>(ok ? ra[j] : 0.0f, ok ? rb[j] : 0.0f, ok ? rc[j] : 0.0f, Cf, dl[j], rl[j]);
           dl[j] = fabsf(dl[j]);
         }
         float o8[8];
