@@ -93,6 +93,7 @@ struct AsyncOut {
   uint32_t ran;
   ResultLayout R;
   bool captured;  // recorded into a graph: replays reuse it, freed with the context
+  bool direct;    // the records went straight into cand (page-locked)
 };
 
 // A launch sequence captured for one call shape (serving slots).
@@ -1267,12 +1268,13 @@ fitrig_status enqueue(fitrig_ctx* ctx, const Call& c, bool with_call) {
 }
 
 // Packs the results into host-visible memory (dst: a device-visible pointer).
-fitrig_status enqueue_results(fitrig_ctx* ctx, const Call& c, char* dst, const ResultLayout& R, int64_t cap) {
+fitrig_status enqueue_results(fitrig_ctx* ctx, const Call& c, char* dst, const ResultLayout& R, int64_t cap,
+                              fitrig_candidate* cand_dst = nullptr) {
   const int np = c.n - 2;
   KL(k_pack_results, dim3(grid_for(std::max<int64_t>(cap, 1) * 9 + 64, 256, 256)), dim3(256), 0, c.st,
      (const int64_t*)ctx->counters.p, (const double*)ctx->M.p, (const double*)ctx->eta_st.p,
      (const double*)ctx->mu.p, (const double*)ctx->sigma.p, (const uint32_t*)ctx->flags.p, np,
-     (const fitrig_candidate*)ctx->c_out.p, cap, R, dst);
+     (const fitrig_candidate*)ctx->c_out.p, cap, R, dst, cand_dst);
   LAUNCH_CHECK(ctx);
   if (ctx->cfg.profile && ctx->ev_recorded && !ctx->sizing) HIP_TRY(ctx, hipEventRecord(ctx->ev[5], c.st));
   return FITRIG_OK;
@@ -1318,19 +1320,21 @@ fitrig_status unpack_pieces(const int64_t* cnt, const double* sc, const double* 
 }
 
 // Host outputs from the packed results in host-visible memory h.
+// direct: the candidate records were written into cand by the device
 fitrig_status unpack_results(const char* h, const ResultLayout& R, int np, uint32_t ran, fitrig_candidate* cand,
                              int64_t cand_cap, int64_t* n_cand, fitrig_stats* stats, double* mu_o, double* sg_o,
-                             uint32_t* fl_o) {
+                             uint32_t* fl_o, bool direct = false) {
   return unpack_pieces((const int64_t*)(h + R.off_cnt), (const double*)(h + R.off_scalars),
                        (const double*)(h + R.off_mu), (const double*)(h + R.off_sigma),
-                       (const uint32_t*)(h + R.off_flags), (const fitrig_candidate*)(h + R.off_cand), np, ran, cand,
-                       cand_cap, n_cand, stats, mu_o, sg_o, fl_o);
+                       (const uint32_t*)(h + R.off_flags),
+                       direct ? cand : (const fitrig_candidate*)(h + R.off_cand), np, ran, cand, cand_cap, n_cand,
+                       stats, mu_o, sg_o, fl_o);
 }
 
 void async_done(void* p) {
   AsyncOut* o = (AsyncOut*)p;
   (void)unpack_results(o->ctx->h_stage, o->R, o->np, o->ran, o->cand, o->cand_cap, o->n_cand, o->stats, o->mu,
-                       o->sigma, o->flags);
+                       o->sigma, o->flags, o->direct);
   if (!o->captured) delete o;
 }
 
@@ -1379,6 +1383,19 @@ fitrig_status sizing_pass(fitrig_ctx* ctx, const Call& c, size_t result_bytes) {
 }
 
 // The whole call: sizing pass, scratch growth, launch pass, results.
+// Device address of the caller's candidate array when it is page-locked host
+// memory mapped for the device (then the records are written there
+// directly), else null.
+fitrig_candidate* mapped_cand(fitrig_candidate* cand) {
+  if (!cand) return nullptr;
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, cand) != hipSuccess) {
+    (void)hipGetLastError();  // pageable memory reports an error
+    return nullptr;
+  }
+  return at.type == hipMemoryTypeHost ? (fitrig_candidate*)at.devicePointer : nullptr;
+}
+
 fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand, int64_t* n_cand,
                           fitrig_stats* stats, bool async) {
   fitrig_status rc = check_shape(ctx->cfg, c);
@@ -1390,14 +1407,18 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   rc = sizing_pass(ctx, c, (size_t)R.bytes);
   if (rc != FITRIG_OK) return rc;
   if ((rc = provision(ctx, c.st)) != FITRIG_OK) return rc;
-  // launch pass
+  // launch pass (the caller's array is not queried while the stream is
+  // being captured: a graph keeps the staging copy)
+  hipStreamCaptureStatus cap_st = hipStreamCaptureStatusNone;
+  const bool capturing = hipStreamIsCapturing(c.st, &cap_st) == hipSuccess && cap_st != hipStreamCaptureStatusNone;
+  fitrig_candidate* cand_dev = capturing ? nullptr : mapped_cand(cand);
   if ((rc = enqueue(ctx, c, true)) != FITRIG_OK) return rc;
-  if ((rc = enqueue_results(ctx, c, ctx->h_stage_dev, R, cap)) != FITRIG_OK) return rc;
+  if ((rc = enqueue_results(ctx, c, ctx->h_stage_dev, R, cap, cand_dev)) != FITRIG_OK) return rc;
   const uint32_t ran = branches_ran(ctx->cfg, c);
   if (!async) {
     HIP_TRY(ctx, hipStreamSynchronize(c.st));
     return unpack_results(ctx->h_stage, R, np, ran, cand, cap, n_cand, stats, stats ? stats->mu : nullptr,
-                          stats ? stats->sigma : nullptr, stats ? stats->flags : nullptr);
+                          stats ? stats->sigma : nullptr, stats ? stats->flags : nullptr, cand_dev != nullptr);
   }
   AsyncOut* o = new (std::nothrow) AsyncOut();
   if (!o) return FITRIG_E_NOMEM;
@@ -1412,6 +1433,7 @@ fitrig_status detect_impl(fitrig_ctx* ctx, const Call& c, fitrig_candidate* cand
   o->np = np;
   o->ran = ran;
   o->R = R;
+  o->direct = cand_dev != nullptr;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   hipError_t e = hipStreamIsCapturing(c.st, &cs);
   o->captured = e == hipSuccess && cs != hipStreamCaptureStatusNone;

@@ -1901,9 +1901,11 @@ __global__ void k_hist_out(const CallDev* cd, const double* fs, int64_t n) {
 // Results of a call into host-visible memory: counters, M, the frequency
 // statistics, per-triple mu / sigma / flags and min(total, cap) candidates
 // (layout in ResultLayout). Only the records that exist cross the bus.
+// cand_dst (nullable): the caller's page-locked candidate array (its device
+// address), written directly instead of the staging copy
 __global__ void k_pack_results(const int64_t* cnt, const double* M, const double* eta_st, const double* mu,
                                const double* sigma, const uint32_t* flags, int np, const fitrig_candidate* cand,
-                               int64_t cap, ResultLayout R, char* dst) {
+                               int64_t cap, ResultLayout R, char* dst, fitrig_candidate* cand_dst) {
   int64_t ncand = cnt[CNT_OUTBASE];
   if (ncand > cap) ncand = cap;
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
@@ -1923,7 +1925,7 @@ __global__ void k_pack_results(const int64_t* cnt, const double* M, const double
     hfl[i] = flags[i];
   }
   const uint64_t* src = (const uint64_t*)cand;
-  uint64_t* out = (uint64_t*)(dst + R.off_cand);
+  uint64_t* out = cand_dst ? (uint64_t*)cand_dst : (uint64_t*)(dst + R.off_cand);
   const int64_t words = ncand * (int64_t)(sizeof(fitrig_candidate) / 8);
   for (int64_t i = tid; i < words; i += nth) out[i] = src[i];
 }

@@ -430,7 +430,8 @@ class Context:
         as an asynchronous call and this method synchronises that stream
         before reading the results. Returns (candidates, stats (dict),
         status). Candidates are a list of dicts, or with ``as_dicts=False`` a
-        numpy structured array (a copy of the records the library wrote)."""
+        numpy structured array over page-locked memory of its own, which the
+        device writes the records into directly (no host copy)."""
         import numpy as np
         import torch
 
@@ -447,19 +448,27 @@ class Context:
         # a null stream handle (the legacy default stream) makes the call
         # synchronous on the context's stream; any other stream makes it
         # asynchronous on that stream
-        rc = self.enqueue(stack, sigma, b, cand_cap, index_map, eta_map, eta_px_map, stream)
+        # the records go to page-locked memory (torch's cached host blocks):
+        # the library writes mapped page-locked arrays from the device
+        ct = torch.empty(max(cand_cap, 1) * ctypes.sizeof(fitrig_candidate), dtype=torch.uint8, pin_memory=True)
+        cand = ctypes.cast(ctypes.c_void_p(ct.data_ptr()), ctypes.POINTER(fitrig_candidate))
+        rc = self.enqueue(stack, sigma, b, cand_cap, index_map, eta_map, eta_px_map, stream, cand=cand)
         if rc not in (OK, E_TRUNC):
             raise FitrigError(rc, "fitrig_detect", fitrig_last_hip_error(self.handle))
         stream.synchronize()
         rc = b["st"].status
         if rc == E_TRUNC and raise_on_trunc:
             raise FitrigError(rc, "fitrig_detect")
-        return self._results(b, cand_cap, np_, rc, as_dicts)
+        return self._results(b, cand_cap, np_, rc, as_dicts, cand_t=ct)
 
-    def _results(self, b, cand_cap, np_, rc, as_dicts):
+    def _results(self, b, cand_cap, np_, rc, as_dicts, cand_t=None):
         ncand = b["n"].value
         k = min(ncand, cand_cap)
-        arr = _cand_array(ctypes.addressof(b["cand"]), k)
+        if cand_t is not None:
+            # a view of the page-locked records (it keeps the block alive)
+            arr = cand_t.numpy()[: k * ctypes.sizeof(fitrig_candidate)].view(cand_dtype())
+        else:
+            arr = _cand_array(ctypes.addressof(b["cand"]), k)
         cands = [_rec_dict(r) for r in arr] if as_dicts else arr
         st = b["st"]
         stats = dict(M=st.M, n_triples=st.n_triples, mu=list(b["mu"][:np_]), sigma=list(b["sg"][:np_]),
@@ -494,14 +503,16 @@ class Context:
             raise FitrigError(rc, "fitrig_detect_host", fitrig_last_hip_error(self.handle))
         return self._results(b, cand_cap, np_, rc, as_dicts)
 
-    def enqueue(self, stack, sigma, b, cand_cap, index_map, eta_map, eta_px_map, stream) -> int:
+    def enqueue(self, stack, sigma, b, cand_cap, index_map, eta_map, eta_px_map, stream, cand=None) -> int:
         """The asynchronous C call on ``stream`` with the host buffers ``b``
-        (from ``_buffers``), which must stay alive until the stream has run it."""
+        (from ``_buffers``) and the candidate array ``cand`` (default
+        ``b["cand"]``), which must stay alive until the stream has run it."""
         n, H, W = stack.shape
         ptr = lambda m: ctypes.c_void_p(m.data_ptr()) if m is not None else None  # noqa: E731
         return fitrig_detect(self.handle, ctypes.c_void_p(stack.data_ptr()), _dtype_code(stack), n, H, W,
-                             float(sigma), b["cand"], cand_cap, ctypes.byref(b["n"]), ptr(index_map), ptr(eta_map),
-                             ptr(eta_px_map), ctypes.byref(b["st"]), ctypes.c_void_p(stream.cuda_stream))
+                             float(sigma), b["cand"] if cand is None else cand, cand_cap, ctypes.byref(b["n"]),
+                             ptr(index_map), ptr(eta_map), ptr(eta_px_map), ctypes.byref(b["st"]),
+                             ctypes.c_void_p(stream.cuda_stream))
 
 
 class Server:
