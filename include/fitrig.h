@@ -141,7 +141,11 @@ fitrig_status fitrig_create(const fitrig_config* cfg, fitrig_ctx** out);
  *   n_snap     >= 3 (the frequency branches run only when n_snap - 2 >= 4)
  *   H, W       >= 1, H * W < 2^32, W * (bytes per pixel) * (17 + window) < 2^30
  *   sigma      the threshold tau of Eqs. (9), (12); finite and > 0
- *   cand       host, cand_cap records (nullable when cand_cap == 0)
+ *   cand       host, cand_cap records (nullable when cand_cap == 0); when it
+ *              is page-locked memory mapped for the device (hipHostMalloc)
+ *              and the stream is not being captured, the device writes the
+ *              records there directly, otherwise they are copied from the
+ *              library's staging memory
  *   n_cand     host, out: total number of candidates (always written)
  *   index_map  device, nullable: [n_snap-2][H][W] floats (sliding) or
  *              [n_snap-2][ceil(H/tile)][ceil(W/tile)] (tiles); written
