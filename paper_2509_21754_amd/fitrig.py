@@ -449,8 +449,16 @@ class Context:
         # synchronous on the context's stream; any other stream makes it
         # asynchronous on that stream
         # the records go to page-locked memory (torch's cached host blocks):
-        # the library writes mapped page-locked arrays from the device
-        ct = torch.empty(max(cand_cap, 1) * ctypes.sizeof(fitrig_candidate), dtype=torch.uint8, pin_memory=True)
+        # the library writes mapped page-locked arrays from the device. The
+        # first call of a size leaves four such blocks in torch's cache, so
+        # later calls take cached blocks (a fresh page-locked allocation costs
+        # milliseconds) while the caller keeps a few earlier results alive.
+        nbytes = max(cand_cap, 1) * ctypes.sizeof(fitrig_candidate)
+        if getattr(self, "_pinned_warm", 0) < nbytes:
+            warm = [torch.empty(nbytes, dtype=torch.uint8, pin_memory=True) for _ in range(4)]
+            del warm
+            self._pinned_warm = nbytes
+        ct = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
         cand = ctypes.cast(ctypes.c_void_p(ct.data_ptr()), ctypes.POINTER(fitrig_candidate))
         rc = self.enqueue(stack, sigma, b, cand_cap, index_map, eta_map, eta_px_map, stream, cand=cand)
         if rc not in (OK, E_TRUNC):
