@@ -470,17 +470,25 @@ fitrig_status rs_select_middle(fitrig_ctx* ctx, hipStream_t st, const float* val
     KL(k_rs_init_gathered, g1, dim3(64), 0, st, rs, nsets, rank_lo, base, kb, gate, want);
   else
     KL(k_rs_init_rank, g1, dim3(64), 0, st, rs, nsets, rank_lo, gate, want);
+  // upper middle value (even counts): from the last digit's histogram when
+  // it holds it, else by a counting pass over the values (need[s] = 1)
+  const bool two = rank_hi != rank_lo;
+  uint32_t* need = min_gt + nsets;
+  if (two) {
+    KL(k_fill_i64, dim3(1), dim3(64), 0, st, (int64_t*)cnt_le, (int64_t)nsets, (int64_t)0);
+    KL(k_fill_u32, dim3(1), dim3(64), 0, st, min_gt, (int64_t)nsets, 0xFFFFFFFFu);
+    KL(k_fill_u32, dim3(1), dim3(64), 0, st, need, (int64_t)nsets, 1u);
+  }
   for (int p = 0; p < 3; ++p) {
     KL(k_rs_hist, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, kmode, med, (const RsState*)rs, shifts[p],
        nbits[p], hist, nvalid, gate, want);
-    KL(k_rs_pick, dim3(nsets), dim3(256), 0, st, rs, hist, shifts[p], nbits[p], gate, want);
+    const RsNext nx = (two && p == 2) ? RsNext{cnt_le, min_gt, need} : RsNext{nullptr, nullptr, nullptr};
+    KL(k_rs_pick, dim3(nsets), dim3(256), 0, st, rs, hist, shifts[p], nbits[p], gate, want, nx);
   }
   KL(k_rs_store, g1, dim3(64), 0, st, (const RsState*)rs, nsets, vmode, 0, out, gate, want);
-  if (rank_hi != rank_lo) {
-    KL(k_fill_i64, dim3(1), dim3(64), 0, st, (int64_t*)cnt_le, (int64_t)nsets, (int64_t)0);
-    KL(k_fill_u32, dim3(1), dim3(64), 0, st, min_gt, (int64_t)nsets, 0xFFFFFFFFu);
+  if (two) {
     KL(k_rs_next, dim3(gx, nsets), dim3(256), 0, st, vals, per_set, kmode, med, (const RsState*)rs, cnt_le, min_gt,
-       nvalid, gate, want);
+       nvalid, gate, want, (const uint32_t*)need);
     KL(k_rs_next_store, g1, dim3(64), 0, st, (const RsState*)rs, nsets, rank_hi, vmode,
        (const unsigned long long*)cnt_le, (const uint32_t*)min_gt, base, out, gate, want);
   } else {
@@ -504,7 +512,8 @@ void sample_bracket(fitrig_ctx* ctx, hipStream_t st, const uint32_t* samp, int n
       KL(k_rs_hist, dim3(grid_for(S, 1 << 13, 1024), nsets), dim3(256), 0, st, (const float*)samp, S, 2,
          (const double*)nullptr, (const RsState*)rs, shifts[p], nbits[p], (uint32_t*)ctx->hist.p,
          (const unsigned long long*)nullptr, gate, want);
-      KL(k_rs_pick, dim3(nsets), dim3(256), 0, st, rs, (uint32_t*)ctx->hist.p, shifts[p], nbits[p], gate, want);
+      KL(k_rs_pick, dim3(nsets), dim3(256), 0, st, rs, (uint32_t*)ctx->hist.p, shifts[p], nbits[p], gate, want,
+         RsNext{nullptr, nullptr, nullptr});
     }
     KL(k_rs_key_out, g1, dim3(64), 0, st, (const RsState*)rs, nsets, w, bkt, gate, want);
   }
@@ -529,7 +538,7 @@ fitrig_status robust_spread(fitrig_ctx* ctx, hipStream_t st, const float* vals, 
   if ((rc = ensure(ctx, ctx->rs_state, (size_t)nsets * sizeof(RsState))) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->rs_med, (size_t)nsets * 2 * 8)) != FITRIG_OK) return rc;
   if ((rc = ensure(ctx, ctx->rs_dev, (size_t)nsets * 2 * 8)) != FITRIG_OK) return rc;
-  if ((rc = ensure(ctx, ctx->rs_next, (size_t)nsets * 12)) != FITRIG_OK) return rc;
+  if ((rc = ensure(ctx, ctx->rs_next, (size_t)nsets * 16)) != FITRIG_OK) return rc;
   KL(k_fill_u32, dim3(grid_for((int64_t)nsets * kHistBins)), dim3(256), 0, st, (uint32_t*)ctx->hist.p,
      (int64_t)nsets * kHistBins, 0u);
   const int64_t r_lo = (per_set - 1) / 2, r_hi = per_set / 2;

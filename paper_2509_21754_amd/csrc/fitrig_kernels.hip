@@ -197,9 +197,24 @@ __global__ __launch_bounds__(256) void k_rs_hist(const float* vals, int64_t per_
 // Digit of the rank-th key: the first bin whose running count exceeds the
 // rank (the last bin when none does); the histogram is cleared for the next
 // digit. One workgroup of 256 per set, nbits 10 or 11.
+// Upper middle value from the last digit's histogram (nullable in k_rs_pick):
+// the key after the selected one is the same key while the selected bin has
+// more keys, else the next non-empty bin's key; only when neither is in the
+// histogram does need[s] stay 1 (then k_rs_next counts over the values).
+// Written for k_rs_next_store: cnt_le huge (same key) or 0 with min_gt.
+struct RsNext {
+  unsigned long long* cnt_le;
+  uint32_t* min_gt;
+  uint32_t* need;
+};
+
 __global__ __launch_bounds__(256) void k_rs_pick(RsState* st, uint32_t* hist, int shift, int nbits, const uint32_t* gate,
-                                                 uint32_t want) {
+                                                 uint32_t want, RsNext nx) {
   __shared__ int64_t part[256];
+  __shared__ int nxt_sh[256];
+  __shared__ int sdig;
+  __shared__ int64_t srem;
+  __shared__ uint32_t scnt;
   const int s = blockIdx.x, t = threadIdx.x;
   if (gated_off(gate, s, want)) return;
   const RsState S = st[s];
@@ -224,19 +239,55 @@ __global__ __launch_bounds__(256) void k_rs_pick(RsState* st, uint32_t* hist, in
   const int64_t incl = part[t], excl = incl - own;
   int dig = -1;
   int64_t acc = excl;
+  uint32_t cdig = 0;
   if (excl <= S.rank && S.rank < incl) {
 #pragma unroll
     for (int j = 0; j < kHistBins / 256; ++j) {
       if (dig < 0 && j < per) {
-        if (acc + (int64_t)c[j] > S.rank)
+        if (acc + (int64_t)c[j] > S.rank) {
           dig = t * per + j;
-        else
+          cdig = c[j];
+        } else {
           acc += c[j];
+        }
       }
     }
   } else if (t == 255 && S.rank >= incl) {
     dig = nb - 1;  // rank beyond the count
     acc = incl;
+  }
+  if (nx.need) {
+    if (t == 0) sdig = -1;
+    __syncthreads();
+    if (dig >= 0) {
+      sdig = dig;
+      srem = S.rank - acc;
+      scnt = cdig;
+    }
+    __syncthreads();
+    const int d = sdig;
+    int nxt = INT32_MAX;
+#pragma unroll
+    for (int j = 0; j < kHistBins / 256; ++j) {
+      const int b = t * per + j;
+      if (j < per && b > d && c[j] != 0u && b < nxt) nxt = b;
+    }
+    nxt_sh[t] = nxt;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if (t < w) nxt_sh[t] = min(nxt_sh[t], nxt_sh[t + w]);
+      __syncthreads();
+    }
+    if (t == 0 && d >= 0) {
+      if (srem + 1 < (int64_t)scnt) {
+        nx.cnt_le[s] = 1ull << 62;  // the upper middle is the selected key
+        nx.need[s] = 0u;
+      } else if (nxt_sh[0] != INT32_MAX) {
+        nx.cnt_le[s] = 0ull;
+        nx.min_gt[s] = (S.prefix & ~(((uint32_t)(nb - 1)) << shift)) | ((uint32_t)nxt_sh[0] << shift);
+        nx.need[s] = 0u;
+      }
+    }
   }
   if (dig >= 0) {
     RsState o = S;
@@ -684,11 +735,11 @@ __global__ void k_rs_sample_dev(uint32_t* samp, int64_t S, const double* med, co
 __global__ __launch_bounds__(256) void k_rs_next(const float* vals, int64_t per_set, int mode, const double* med,
                                                  const RsState* st, unsigned long long* cnt_le, uint32_t* min_gt,
                                                  const unsigned long long* nvalid, const uint32_t* gate,
-                                                 uint32_t want) {
+                                                 uint32_t want, const uint32_t* need) {
   __shared__ uint32_t sh_c[256];
   __shared__ uint32_t sh_m[256];
   const int s = blockIdx.y;
-  if (gated_off(gate, s, want)) return;
+  if (gated_off(gate, s, want) || (need && !need[s])) return;
   const uint32_t sel = st[s].prefix;
   const float* v = vals + (int64_t)s * per_set;
   const double m = mode == 1 ? med[s] : 0.0;
