@@ -250,6 +250,25 @@ def test_freq_branch_long_series(n, harm):
     assert any(c["branch"] == ref.FREQ for c in cands)
 
 
+@pytest.mark.parametrize("n,harm", [(6, 0), (34, 0), (34, 2), (35, 0), (66, 3), (67, 0)])
+def test_freq_branch_register_series(n, harm):
+    """Tile branch on series of n' <= 64 (each tile's series held in
+    registers, in two sizes: up to 32 and up to 64 values, both ends of each
+    and a harmonic sum): eta per tile against the oracle, candidates by
+    component; H, W not multiples of the tile."""
+    rng = np.random.default_rng(900 + n + harm)
+    X = structured_stack(500 + n, n, 50, 90)
+    period = int(rng.integers(3, 7))
+    for k in range(0, n, period):
+        X[k, 20:25, 30:36] += 8.0
+    tau = 3.0
+    cands, stats, q, eta, used, rc = run_gpu(X, tau, branches=2, harm=harm, tile=8)
+    assert rc == 0
+    out = ref.detect(used, tau=tau, branches=ref.FREQ, harm=harm, tile=8)
+    check_eta(eta, out["eta"])
+    check_candidates(cands, out, tau)
+
+
 def test_r_signed_reading():
     X = structured_stack(61, 6, 40, 280)
     X -= 1.0
