@@ -83,3 +83,16 @@ def test_median_mad_grid_sample_defeated():
     stack = torch.randn((3, H, W), generator=g, device="cuda", dtype=torch.float32) + 3.0
     stack[1, ::16, ::16] += 50.0
     run_mad(stack, 1, 1e9, [0])
+
+
+@pytest.mark.parametrize("window", [1, 3])
+def test_median_mad_gathered_ties(window):
+    """A 4096^2 set (gathered selection from a hashed sample) whose q takes
+    few distinct values: the bracket bounds can be one key, so every digit
+    starts known, and the upper middle value lies in the same key or past
+    the histogram; the result must still be the exact order statistics."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5 + window)
+    H = W = 4096
+    stack = torch.randint(1, 4, (3, H, W), generator=g, device="cuda").to(torch.float32)
+    run_mad(stack, window, 1e9, [0])
