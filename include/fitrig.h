@@ -139,7 +139,9 @@ fitrig_status fitrig_create(const fitrig_config* cfg, fitrig_ctx** out);
  * Runs the whole path on one stack.
  *   stack      device, [n_snap][H][W] row-major, dtype as given, read only
  *   n_snap     >= 3 (the frequency branches run only when n_snap - 2 >= 4)
- *   H, W       >= 1, H * W < 2^32, W * (bytes per pixel) * (17 + window) < 2^30
+ *   H, W       >= 1, H * W < 2^32, W * (bytes per pixel) * 33 < 2^30 for every
+ *              window (a workgroup's rows are addressed within 2^30 bytes of its
+ *              first row: W <= 8134407 in FP32, 16268815 in FP16/BF16)
  *   sigma      the threshold tau of Eqs. (9), (12); finite and > 0
  *   cand       host, cand_cap records (nullable when cand_cap == 0); when it
  *              is page-locked memory mapped for the device (hipHostMalloc)
