@@ -4,8 +4,9 @@ descriptor of 2^30 bytes that starts at its first row, so the library accepts
 W * (bytes per pixel) * 33 < 2^30 and rejects one column more with E_INVAL
 before anything is launched. At the widest accepted FP32 width a band with
 all 32 rows inside the image reads bytes up to 31 W * 4 + W * 4 - 1, just
-under 2^30; q there must match the FP64 oracle (sliding window, Eq. (2)) at
-the image's left and right edges."""
+under 2^30 (FP16/BF16: 31 W * 2 + W * 2 - 1 at their widest); q there must
+match the FP64 oracle (sliding window, Eq. (2)) at the image's left and right
+edges."""
 import numpy as np
 import pytest
 
@@ -38,14 +39,16 @@ def test_one_column_past_the_bound_is_rejected(dtype, bpp):
     assert e.value.code == -1
 
 
-def test_widest_fp32_image_matches_oracle_at_both_edges():
+@pytest.mark.parametrize("dtype,bpp", [(torch.float32, 4), (torch.float16, 2), (torch.bfloat16, 2)])
+def test_widest_image_matches_oracle_at_both_edges(dtype, bpp):
+    """The oracle takes the stored values (FP16/BF16 widened exactly)."""
     from paper_2509_21754_amd import Context
 
-    W, H = widest(4), 40
-    print(f"[limits] accept {H}x{W} fp32 window {WINDOW}", flush=True)
+    W, H = widest(bpp), 40
+    print(f"[limits] accept {H}x{W} {dtype} window {WINDOW}", flush=True)
     g = torch.Generator(device="cuda")
-    g.manual_seed(8134407)
-    stack = torch.randn((3, H, W), generator=g, device="cuda", dtype=torch.float32) + 3.0
+    g.manual_seed(W)
+    stack = (torch.randn((3, H, W), generator=g, device="cuda", dtype=torch.float32) + 3.0).to(dtype)
     qmap = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
     with Context(window=WINDOW, max_pixels=H * W, max_snap=3, branches=1) as ctx:
         _, _, rc = ctx.detect(stack, 1e9, index_map=qmap, as_dicts=False)
@@ -53,7 +56,7 @@ def test_widest_fp32_image_matches_oracle_at_both_edges():
     assert rc == 0
     for x0, x1 in ((0, 48), (W - 48, W)):
         xa, xb = max(0, x0 - HALO), min(W, x1 + HALO)
-        X = stack[:, :, xa:xb].cpu().numpy()
+        X = stack[:, :, xa:xb].float().cpu().numpy()
         yy, xx = np.meshgrid(np.arange(H), np.arange(x0, x1), indexing="ij")
         cells = np.stack([np.zeros(yy.size, np.int64), yy.ravel(), (xx - xa).ravel()], 1)
         q_ref = ref.index_cells(X, cells, window=WINDOW).reshape(1, H, x1 - x0)
