@@ -61,3 +61,28 @@ def test_widest_image_matches_oracle_at_both_edges(dtype, bpp):
         cells = np.stack([np.zeros(yy.size, np.int64), yy.ravel(), (xx - xa).ravel()], 1)
         q_ref = ref.index_cells(X, cells, window=WINDOW).reshape(1, H, x1 - x0)
         check_maps(qmap[:, :, x0:x1].cpu().numpy(), q_ref, what=f"q[:, :, {x0}:{x1}]")
+
+
+@pytest.mark.parametrize("dtype,bpp", [(torch.float32, 4), (torch.float16, 2)])
+def test_widest_image_tile_mode_matches_oracle_at_both_edges(dtype, bpp):
+    """Tile mode (Eq. (6), tile 32): each band of 32 rows is read through one
+    descriptor; the tiles are independent, so the oracle runs on crops that
+    start on a tile boundary. The last tile column is ragged."""
+    from paper_2509_21754_amd import Context
+
+    T, H = 32, 64
+    W = widest(bpp)
+    nt = -(-W // T)
+    print(f"[limits] tile mode {H}x{W} {dtype}, {nt} tile columns (last {W - T * (nt - 1)} wide)", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(W + 1)
+    stack = (torch.randn((3, H, W), generator=g, device="cuda", dtype=torch.float32) + 3.0).to(dtype)
+    qmap = torch.empty((1, H // T, nt), dtype=torch.float32, device="cuda")
+    with Context(mode=1, tile=T, max_pixels=H * W, max_snap=3, branches=1) as ctx:
+        _, _, rc = ctx.detect(stack, 1e9, index_map=qmap, as_dicts=False)
+    torch.cuda.synchronize()
+    assert rc == 0
+    for t0, t1 in ((0, 3), (nt - 3, nt)):
+        X = stack[:, :, T * t0:min(W, T * t1)].float().cpu().numpy()
+        q_ref = ref.index_maps(X, mode=ref.TILES, tile=T)
+        check_maps(qmap[:, :, t0:t1].cpu().numpy(), q_ref, what=f"tiles {t0}:{t1}")
